@@ -1,0 +1,135 @@
+/*
+ * mxfft.h -- C ABI of the MI355X (gfx950) MX-scaled mixed-precision 2D FFT.
+ *
+ * Method: Deveshwar, Rajagopal, Larson, "A mixed precision FFT with applications
+ * in MRI".  A slice is one N x N complex k-space array of one coil.  Per slice the
+ * library applies the single global power-of-two prescale of Alg. 1 (Sec. 2.1),
+ * then an iterative radix-2 Cooley-Tukey FFT over every row and then every column,
+ * whose butterflies multiply by pre-quantised FP8 twiddles in the MX-scaled form
+ * of Alg. 2 (Sec. 2.2: MX-encoded operands, FP32 products and sums, stage-wise MX
+ * re-encoding with one shared power-of-two scale per block of B real scalars).
+ * The forward and round-trip transforms are those of Eq. 1 (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *  - Data pointers are DEVICE pointers owned by the caller (the library never
+ *    frees or keeps them).  Complex data is interleaved FP32 (re, im), i.e.
+ *    complex64; a batch is [batch][n][n], row-major, 8-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it; nothing here synchronises except where stated.
+ *  - Errors are returned as mxfft_status.  Argument checks happen on the host
+ *    before anything is enqueued, so on an argument error no buffer is touched.
+ *    Data-dependent errors (non-finite input, prescale overflow) are found on
+ *    the device: the slice's k becomes INT32_MIN, its output is undefined, and
+ *    mxfft_plan_last_status() reports the error.
+ *  - A plan is used by one stream at a time; calls that overlap on one plan race.
+ */
+#ifndef MXFFT_H
+#define MXFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element / arithmetic format (Sec. 2.2; Fig. 1C).  E4M3 and E5M2 are the OCP
+ * 8-bit elements of MXFP8.  FP32 is the plain single-precision form of the same
+ * radix-2 FFT (the comparison baseline, no quantisation). */
+typedef enum {
+    MXFFT_E4M3 = 0,
+    MXFFT_E5M2 = 1,
+    MXFFT_FP16 = 2,   /* reserved: the 16-bit positive control of Sec. 2.2 */
+    MXFFT_BF16 = 3,   /* reserved */
+    MXFFT_FP32 = 4
+} mxfft_format;
+
+typedef enum {
+    MXFFT_OK = 0,
+    MXFFT_EINVAL = -1,        /* bad argument (size, block, parameter, pointer) */
+    MXFFT_ENOMEM = -2,        /* device allocation failed while planning */
+    MXFFT_EHIP = -3,          /* a HIP runtime call failed */
+    MXFFT_ENONFINITE = -4,    /* a slice holds Inf or NaN (found on the device) */
+    MXFFT_ERANGE = -5,        /* the prescale would overflow FP32 (found on the device) */
+    MXFFT_EBUDGET = -6,       /* reserved */
+    MXFFT_EBUSY = -7,         /* reserved */
+    MXFFT_EUNSUPPORTED = -8   /* valid for the method but not built in this library */
+} mxfft_status;
+
+/* Flags of mxfft_params.flags. */
+#define MXFFT_NO_PRESCALE 0x1u  /* skip Alg. 1: k = 0 for every slice */
+#define MXFFT_KEEP_SCALE  0x2u  /* forward: return 2^k * F{x} (do not de-scale) */
+#define MXFFT_NORMALIZE   0x4u  /* inverse: multiply by 1/N^2 (Eq. 1 round trip) */
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(mxfft_params); checked for ABI versioning */
+    int32_t format;        /* mxfft_format */
+    int32_t block;         /* B: real scalars per MX block, a power of two with
+                              2 <= B <= n and B <= 128 (B/2 complex values per
+                              block; Sec. 2.2 and Sec. 4.2).  Ignored for FP32. */
+    int32_t k_min, k_max;  /* clip bounds of the prescale exponent (Alg. 1);
+                              INT32_MIN / INT32_MAX mean no bound */
+    uint32_t flags;        /* MXFFT_* flags above */
+    double target;         /* Alg. 1 peak target T > 0 (e.g. 2^7) */
+    double tau_pct;        /* Alg. 1 tail percentile tau, in percent, 0..100 */
+    double tau_min;        /* Alg. 1 tail floor tau_min > 0; this library needs a
+                              power of two (else MXFFT_EUNSUPPORTED) */
+} mxfft_params;
+
+typedef struct mxfft_plan_s* mxfft_plan_t;
+
+/* Fill p with the defaults: E4M3, B = 32, T = 2^7, tau = 5, tau_min = 2^-6,
+ * no clipping, no flags. */
+void mxfft_params_default(mxfft_params* p);
+
+/* Create a plan for n x n slices (n a power of two, 2 <= n <= 4096) and batches
+ * of up to max_batch slices.  The plan owns the pre-quantised twiddle tables
+ * (FP64-generated, MX-encoded once per stage and block: Sec. 2.2, Alg. 2) and
+ * its device workspace; it allocates device memory here and never again.
+ * `stream` orders the plan's initial uploads.  *out receives the handle. */
+mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch,
+                        const mxfft_params* p, void* stream);
+
+/* Release a plan (synchronises the device first).  NULL is accepted. */
+mxfft_status mxfft_plan_destroy(mxfft_plan_t plan);
+
+/* Forward transform (Eq. 1, forward): per slice k = Alg. 1 prescale of `in`,
+ * y = F{2^k x} with rows then columns, out = 2^-k y (2^k y with KEEP_SCALE).
+ * in, out: complex64 [batch][n][n] device buffers; in == out is allowed.
+ * k_out: device int32[batch] receiving k per slice, or NULL.
+ * 1 <= batch <= max_batch. */
+mxfft_status mxfft_forward(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
+                           int32_t* k_out, void* stream);
+
+/* Inverse transform F^-1 (conjugate twiddles, same pipeline; Eq. 1).
+ * k_in == NULL: the input is prescaled by its own Alg. 1 exponent k and the
+ * output is 2^-k F^-1{2^k x}.  k_in != NULL (device int32[batch]): the input is
+ * taken as already scaled by 2^k_in (e.g. a KEEP_SCALE forward output) and the
+ * output is 2^-k_in F^-1{x}.  With NORMALIZE the output is also multiplied by
+ * 1/N^2 (an exact power of two). */
+mxfft_status mxfft_inverse(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
+                           const int32_t* k_in, void* stream);
+
+/* Round trip (Eq. 1): T = (1/N^2) F^-1{F{x}} with one prescale k per slice,
+ * kept through both transforms and removed once at the end.  in == out is
+ * allowed.  k_out: device int32[batch] or NULL. */
+mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
+                             int32_t* k_out, void* stream);
+
+/* Synchronise `stream` and return the device status of the plan's last call
+ * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */
+mxfft_status mxfft_plan_last_status(mxfft_plan_t plan, void* stream);
+
+/* Bytes of device memory the plan holds (tables and workspace). */
+uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
+
+/* Static text for a status code. */
+const char* mxfft_status_string(mxfft_status st);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t mxfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MXFFT_H */
