@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the MX-scaled mixed-precision 2D FFT on one MI355X.
+
+Default workload: 1024 slices (64 slices x 16 coils) of 512 x 512 complex64
+synthetic k-space, MXFP8-E4M3 with B = 32, forward transform with the Alg. 1
+prescale (T = 2^7, tau = 5 %, tau_min = 2^-6).  A step is one forward call over
+the whole resident batch.  Also timed: the plain FP32 form of the same FFT on
+the same batch, and the CPU oracle on a bounded sample (host cores).
+
+Prints one JSON line (rank 0).  Usage:
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload kspace512_64x16]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MX-FP8 2D FFT slices/s vs FP32 at stated NRMSE; % HBM roofline; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+ALG_BYTES_PER_ELEM = 16.0      # complex64 read once + complex64 written once per transform
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="kspace512_64x16")
+    ap.add_argument("--fmt", default="e4m3", choices=["e4m3", "e5m2"])
+    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="slices the CPU oracle transforms")
+    return ap.parse_args()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2512_04317_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        fn()
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    return wall, per
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1). Slices are independent, so a "
+              "batch would shard across GPUs with no communication; no multi-GPU path is built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_04317_amd import mxfft, synth
+
+    mxfft.lib()   # fails loudly when the HIP library is not built
+    w = synth.WORKLOADS[args.workload]
+    N, batch = w["N"], w["slices"] * w["coils"]
+    workers = min(16, os.cpu_count() or 1)
+    x = synth.kspace_batch(N, w["config"], w["slices"], w["coils"], workers=workers)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    kout = torch.empty(batch, dtype=torch.int32, device=xd.device)
+
+    plan = mxfft.Plan(N, batch, fmt=args.fmt, block=args.block)
+    fwd = lambda: plan.forward(xd, out=out, k_out=kout)   # noqa: E731
+    for _ in range(args.warmup):
+        fwd()
+    assert plan.last_status() == mxfft.OK
+    plan.profile(True)
+    wall, per_step = timed_steps(fwd, args.steps, 0, torch)
+    ktimes = plan.kernel_times()
+    plan.profile(False)
+    slices_per_s = batch * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+
+    # accuracy of this run against FP64 (numpy), on a sample of slices
+    pick = list(range(0, batch, max(1, batch // 16)))[:16]
+    y = out[pick].cpu().numpy().astype(np.complex128)
+    ref = np.fft.fft2(x[pick].astype(np.complex128))
+    errs = np.linalg.norm((y - ref).reshape(len(pick), -1), axis=1) / np.linalg.norm(ref.reshape(len(pick), -1), axis=1)
+    mse = np.mean(np.abs(y - ref) ** 2, axis=(1, 2))
+    psnr = 20 * np.log10(np.abs(ref).max(axis=(1, 2)) / np.sqrt(mse))
+
+    # dominant kernel and its roofline: algorithmic bytes per launch are the
+    # transform's 16 B per complex element split over the two passes (the row
+    # pass owns the input read, the column pass the output write: 8 B each);
+    # the prescale statistics pass carries no algorithmic bytes of its own.
+    elems = batch * N * N
+    alg_bytes = {"row_pass": 8.0 * elems, "column_pass": 8.0 * elems, "prescale_stats": 0.0}
+    kern = {k: {"launches": n, "avg_ms": t / n} for k, (n, t) in ktimes.items()}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    avg_s = kern[dom]["avg_ms"] * 1e-3
+    achieved = alg_bytes.get(dom, 0.0) / avg_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (args.workload, args.fmt))
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("source_sha") == kernel_source_sha() and dom in t.get("kernels", {}):
+            traffic = t["kernels"][dom]["hbm_bytes_per_launch"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "kernel_avg_ms": round(kern[dom]["avg_ms"], 4),
+                "alg_bytes_per_launch": alg_bytes.get(dom, 0.0)}
+    step_frac = slices_per_s * N * N * ALG_BYTES_PER_ELEM / (HBM_PEAK_GBS * 1e9)
+
+    result = {
+        "metric": METRIC, "value": round(slices_per_s, 1), "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mxfp8_%s_b%d/f32" % (args.fmt, args.block), "data": "synthetic",
+        "config": {"workload": "%s: %d slices (%d x %d coils) of %dx%d complex64 k-space, MXFP8-%s B=%d, "
+                               "forward with Alg. 1 prescale" % (args.workload, batch, w["slices"], w["coils"],
+                                                                  N, N, args.fmt.upper(), args.block),
+                   "n": N, "batch": batch, "format": args.fmt, "block": args.block, "direction": "forward",
+                   "prescale": {"target": 128.0, "tau_pct": 5.0, "tau_min": 2.0 ** -6}},
+        "roofline": roofline,
+        "hbm_frac_whole_step": round(step_frac, 4),
+        "latency_ms": {"p50": round(float(np.percentile(per_step, 50)), 4),
+                       "p99": round(float(np.percentile(per_step, 99)), 4)},
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4)} for k, v in kern.items()},
+        "nrmse_vs_fp64": {"mean": round(float(errs.mean()), 5), "max": round(float(errs.max()), 5)},
+        "psnr_db_vs_fp64": round(float(psnr.mean()), 2),
+    }
+
+    if not args.no_fp32:
+        plan32 = mxfft.Plan(N, batch, fmt="fp32")
+        f32 = lambda: plan32.forward(xd, out=out, k_out=kout)   # noqa: E731
+        wall32, per32 = timed_steps(f32, args.steps, args.warmup, torch)
+        y32 = out[pick].cpu().numpy().astype(np.complex128)
+        e32 = np.linalg.norm((y32 - ref).reshape(len(pick), -1), axis=1) / np.linalg.norm(ref.reshape(len(pick), -1), axis=1)
+        sps32 = batch * args.steps / wall32
+        result["fp32_plain"] = {"value": round(sps32, 1), "unit": "slices/s", "ms_per_step": round(1e3 * wall32 / args.steps, 4),
+                                "nrmse_vs_fp64_max": float("%.3g" % e32.max())}
+        result["speedup_vs_fp32"] = round(slices_per_s / sps32, 3)
+        plan32.close()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = min(args.cpu_sample, batch)
+        nth = min(16, os.cpu_count() or 1)
+        fmt = oracle.E4M3 if args.fmt == "e4m3" else oracle.E5M2
+        t0 = time.perf_counter()
+        st, _, _ = oracle.transform(x[:ns], fmt=fmt, B=args.block, nthreads=nth)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(ns / dt, 3), "unit": "slices/s", "cores": nth, "kind": "oracle",
+                                  "sample": "first %d of %d slices, same input and parameters, %d threads"
+                                            % (ns, batch, nth)}
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

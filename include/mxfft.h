@@ -119,6 +119,22 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32
  * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */
 mxfft_status mxfft_plan_last_status(mxfft_plan_t plan, void* stream);
 
+/* Per-kernel timing for benchmarks.  While enabled, every kernel the plan
+ * launches is bracketed by a pair of HIP events recorded on the same stream.
+ * Enabling resets the accumulated times; disabling keeps them. */
+mxfft_status mxfft_plan_profile(mxfft_plan_t plan, int32_t enable);
+
+typedef struct {
+    char name[32];       /* kernel role, e.g. "prescale_stats", "row_pass" */
+    uint64_t launches;   /* launches timed since profiling was enabled */
+    double total_ms;     /* summed event-to-event durations */
+} mxfft_kernel_time;
+
+/* Synchronise the device and report the accumulated per-role times: writes
+ * up to cap entries to out and the number of roles seen to *count. */
+mxfft_status mxfft_plan_kernel_times(mxfft_plan_t plan, mxfft_kernel_time* out, int32_t cap,
+                                     int32_t* count);
+
 /* Bytes of device memory the plan holds (tables and workspace). */
 uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
 

@@ -140,16 +140,16 @@ def mx_butterfly(f, u, v, x, Ew):
     return y0, y1, tuple(int(t) for t in tr)
 
 
-def prescale(x, target=2.0 ** 7, tau=5.0, tau_min=2.0 ** -6, kmin=INT32_MIN, kmax=INT32_MAX):
+def prescale(x, target=2.0 ** 7, tau=5.0, tau_min=2.0 ** -6, k_min=INT32_MIN, k_max=INT32_MAX):
     """Alg. 1 on one slice (complex64 array of any shape). Returns (status, k)."""
     x = np.ascontiguousarray(x, dtype=np.complex64)
     k = ctypes.c_int32()
-    st = lib().orc_prescale(_ptr(x), x.size, target, tau, tau_min, kmin, kmax, ctypes.byref(k))
+    st = lib().orc_prescale(_ptr(x), x.size, target, tau, tau_min, k_min, k_max, ctypes.byref(k))
     return st, k.value
 
 
 def transform(x, op=FORWARD, mode=MODE_MX, fmt=E4M3, B=32, kp=None, target=2.0 ** 7, tau=5.0,
-              tau_min=2.0 ** -6, kmin=INT32_MIN, kmax=INT32_MAX, flags=0, nthreads=1):
+              tau_min=2.0 ** -6, k_min=INT32_MIN, k_max=INT32_MAX, flags=0, nthreads=1):
     """2D transform of complex64 slices [batch, N, N] (or [N, N]).
 
     op: FORWARD, INVERSE or ROUNDTRIP.  kp: for INVERSE, per-slice exponents
@@ -167,7 +167,7 @@ def transform(x, op=FORWARD, mode=MODE_MX, fmt=E4M3, B=32, kp=None, target=2.0 *
         k = np.ascontiguousarray(np.broadcast_to(np.asarray(kp, np.int32), (batch,)))
         given = 1
     st = lib().orc_transform(op, mode, fmt, B, N, batch, _ptr(x), _ptr(out), _ptr(k), given,
-                             target, tau, tau_min, kmin, kmax, flags, nthreads)
+                             target, tau, tau_min, k_min, k_max, flags, nthreads)
     if squeeze:
         out = out[0]
     return st, out, k

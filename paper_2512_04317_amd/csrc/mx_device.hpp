@@ -1,0 +1,79 @@
+// mx_device.hpp -- gfx950 device helpers for the MX-scaled FFT: OCP FP8 element
+// rounding, MX block exponents and the renormalisation exponent of Alg. 2.
+//
+// All element arithmetic is "fake quantisation" in FP32 registers: a value is
+// kept as the FP32 number equal to its FP8 element (an FP8 value is exact in
+// FP32), so codes need never be materialised except where they are stored.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mxd {
+
+// OCP 8-bit elements of MXFP8 (Sec. 2.2; Fig. 1C).
+//   EMAX : exponent of the largest normal (the OCP MX "emax_elem")
+//   MBITS: explicit mantissa bits;  EMIN: exponent of the smallest normal
+//   MAXV : largest finite magnitude (1.75 * 2^EMAX for both formats)
+template <int F> struct Elem;
+template <> struct Elem<0> {  // E4M3 ("fn": no infinities)
+    static constexpr int EMAX = 8, MBITS = 3, EMIN = -6;
+    static constexpr float MAXV = 448.0f;
+};
+template <> struct Elem<1> {  // E5M2
+    static constexpr int EMAX = 15, MBITS = 2, EMIN = -14;
+    static constexpr float MAXV = 57344.0f;
+};
+
+// Round y to the element grid of format F, ties to even, saturating at MAXV,
+// keeping the sign (also of zero).  Requires |y| < 2^100 (block-scaled
+// operands are below 2^(EMAX+1)).
+// The grid step is 2^(max(e, EMIN) - MBITS) for |y| in [2^e, 2^(e+1)); adding
+// and subtracting c = 1.5 * 2^(max(e,EMIN) - MBITS + 23) rounds |y| to it in one
+// IEEE addition (round to nearest even), and the subtraction is exact.
+template <int F>
+__device__ __forceinline__ float quant(float y)
+{
+    using E = Elem<F>;
+    const uint32_t b = __float_as_uint(y);
+    const uint32_t e = max(b & 0x7f800000u, uint32_t(E::EMIN + 127) << 23);
+    const float c = __uint_as_float(e + (uint32_t(23 - E::MBITS) << 23) + 0x00400000u);
+    float r = (fabsf(y) + c) - c;
+    r = fminf(r, E::MAXV);
+    return __uint_as_float(__float_as_uint(r) | (b & 0x80000000u));
+}
+
+// |x| as an ordered integer key (non-negative floats order like their bits).
+__device__ __forceinline__ uint32_t abs_key(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+
+// Shared block exponent from the block's largest magnitude (bits of a
+// non-negative float): E = floor(log2 amax) - EMAX clamped to >= -127 (the
+// upper clamp at 127 cannot bind for FP32 data); an all-zero block gets E = 0.
+template <int F>
+__device__ __forceinline__ int block_exp(uint32_t amax_key)
+{
+    const int e = __builtin_amdgcn_frexp_expf(__uint_as_float(amax_key)) - 1;  // exact, subnormals too
+    const int E = max(e - Elem<F>::EMAX, -127);
+    return amax_key ? E : 0;
+}
+
+// Alg. 2 renormalisation: the smallest k >= 1 with amax <= MAXV * 2^k when
+// amax > MAXV, else 0.  MAXV = 1.75 * 2^EMAX, so amax = 1.f * 2^e needs
+// k = e - EMAX, plus one when f > 1.75; adding 0x1FFFFF to the bits carries
+// into the exponent field exactly when the fraction field exceeds 0x600000.
+template <int F>
+__device__ __forceinline__ int renorm_exp(uint32_t amax_key)
+{
+    const int k = int((amax_key + 0x001FFFFFu) >> 23) - 127 - Elem<F>::EMAX;
+    return max(k, 0);
+}
+
+// Maximum over groups of `width` consecutive lanes (width a power of two,
+// 1 <= width <= 64); every lane of a group must be active.
+__device__ __forceinline__ uint32_t group_max(uint32_t v, int width)
+{
+    for (int o = 1; o < width; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+}  // namespace mxd

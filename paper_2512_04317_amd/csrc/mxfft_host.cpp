@@ -1,0 +1,496 @@
+// mxfft_host.cpp -- plans, argument checks, twiddle pre-quantisation and the
+// launch sequences behind the C ABI of include/mxfft.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "mxfft.h"
+#include "mxfft_internal.hpp"
+
+namespace {
+
+constexpr uint32_t kKnownFlags = MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE;
+
+// Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2).
+struct HostElem {
+    int mbits, emin, emax;
+    double maxv;
+};
+const HostElem kE4M3 = {3, -6, 8, 448.0};
+const HostElem kE5M2 = {2, -14, 15, 57344.0};
+
+// Nearest element value (ties to the even multiple of the grid step),
+// saturating at the largest finite element.
+double round_to_elem(double x, const HostElem& f)
+{
+    if (x == 0.0) return x;
+    const double a = std::fabs(x);
+    int e2;
+    std::frexp(a, &e2);          // a in [2^(e2-1), 2^e2)
+    int e = e2 - 1;
+    if (e < f.emin) e = f.emin;  // subnormal grid
+    const double step = std::ldexp(1.0, e - f.mbits);
+    const double units = a / step;          // exact: power-of-two division
+    double whole = std::floor(units);
+    const double frac = units - whole;
+    if (frac > 0.5 || (frac == 0.5 && std::fmod(whole, 2.0) != 0.0)) whole += 1.0;
+    double r = whole * step;
+    if (r > f.maxv) r = f.maxv;
+    return std::copysign(r, x);
+}
+
+// exp(-2 pi i j / m) for 0 <= j < m / 2, evaluated in extended precision on
+// the reduced angle and rounded to FP64; the axes are exact.
+void twiddle(long j, long m, double* re, double* im)
+{
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    long double c, s;
+    if (j == 0) { c = 1.0L; s = 0.0L; }
+    else if (4 * j == m) { c = 0.0L; s = 1.0L; }
+    else if (4 * j < m) {
+        const long double t = two_pi * (long double)j / (long double)m;
+        c = cosl(t); s = sinl(t);
+    } else {
+        // pi - t: cos changes sign, sin does not
+        const long double t = two_pi * (long double)(m / 2 - j) / (long double)m;
+        c = -cosl(t); s = sinl(t);
+    }
+    *re = (double)c;
+    *im = -(double)s;
+}
+
+int ilog2(long n)
+{
+    int l = 0;
+    while ((1L << l) < n) l++;
+    return l;
+}
+
+bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+struct mxfft_plan_s {
+    int n = 0, logn = 0, max_batch = 0;
+    mxfft_params p{};
+    int mode = 0;           // mxk::Mode
+    int cb = 1, logcb = 0;  // complex values per MX block
+    int device = 0;
+    float2* d_tw = nullptr;
+    int32_t* d_tw_exp = nullptr;
+    int32_t tw_exp_off[mxk::kMaxLog2N + 2] = {};
+    mxk::SliceStats* d_ws = nullptr;
+    int32_t* d_kp = nullptr;
+    int32_t* d_status = nullptr;
+    uint64_t bytes = 0;
+    int last_batch = 0;
+    bool last_has_stats = false;
+    // event timing of launches (benchmark support)
+    struct Timed {
+        int role;
+        hipEvent_t start, stop;
+    };
+    bool profiling = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> spare;
+    uint64_t launches[8] = {};
+    double total_ms[8] = {};
+};
+
+namespace {
+
+enum Role { ROLE_STATS = 0, ROLE_ROW, ROLE_COL, ROLE_INV_ROW, ROLE_INV_COL, ROLE_COUNT };
+const char* const kRoleNames[ROLE_COUNT] = {"prescale_stats", "row_pass", "column_pass", "inverse_row_pass",
+                                            "inverse_column_pass"};
+
+hipEvent_t take_event(mxfft_plan_s* pl)
+{
+    hipEvent_t e = nullptr;
+    if (!pl->spare.empty()) {
+        e = pl->spare.back();
+        pl->spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct LaunchTimer {
+    mxfft_plan_s* pl;
+    int role;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTimer(mxfft_plan_s* p, int r, hipStream_t st) : pl(p), role(r), s(st)
+    {
+        if (!pl->profiling) return;
+        a = take_event(pl);
+        b = take_event(pl);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~LaunchTimer()
+    {
+        if (!pl->profiling || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        pl->pending.push_back({role, a, b});
+    }
+};
+
+void collect_times(mxfft_plan_s* pl)
+{
+    for (auto& t : pl->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.stop) == hipSuccess && hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            pl->launches[t.role]++;
+            pl->total_ms[t.role] += ms;
+        }
+        pl->spare.push_back(t.start);
+        pl->spare.push_back(t.stop);
+    }
+    pl->pending.clear();
+}
+
+mxfft_status check_params(const mxfft_params* p, int n)
+{
+    if (!p || p->struct_size != sizeof(mxfft_params)) return MXFFT_EINVAL;
+    if (p->flags & ~kKnownFlags) return MXFFT_EINVAL;
+    switch (p->format) {
+    case MXFFT_E4M3:
+    case MXFFT_E5M2:
+        if (!is_pow2(p->block) || p->block < 2 || p->block > n) return MXFFT_EINVAL;
+        if (p->block > 128) return MXFFT_EUNSUPPORTED;
+        break;
+    case MXFFT_FP32: break;
+    case MXFFT_FP16:
+    case MXFFT_BF16: return MXFFT_EUNSUPPORTED;
+    default: return MXFFT_EINVAL;
+    }
+    if (!(p->flags & MXFFT_NO_PRESCALE)) {
+        if (!std::isfinite(p->target) || !(p->target > 0.0)) return MXFFT_EINVAL;
+        if (!(p->tau_pct >= 0.0 && p->tau_pct <= 100.0)) return MXFFT_EINVAL;
+        if (!std::isfinite(p->tau_min) || !(p->tau_min > 0.0)) return MXFFT_EINVAL;
+        int e;
+        if (std::frexp(p->tau_min, &e) != 0.5) return MXFFT_EUNSUPPORTED;
+        if (p->k_min > p->k_max) return MXFFT_EINVAL;
+    }
+    return MXFFT_OK;
+}
+
+template <class T>
+mxfft_status dev_alloc(T** ptr, size_t count, uint64_t* total)
+{
+    if (hipMalloc((void**)ptr, count * sizeof(T)) != hipSuccess) {
+        *ptr = nullptr;
+        return MXFFT_ENOMEM;
+    }
+    *total += count * sizeof(T);
+    return MXFFT_OK;
+}
+
+void release(mxfft_plan_s* pl)
+{
+    if (!pl) return;
+    collect_times(pl);
+    for (hipEvent_t e : pl->spare) (void)hipEventDestroy(e);
+    (void)hipFree(pl->d_tw);
+    (void)hipFree(pl->d_tw_exp);
+    (void)hipFree(pl->d_ws);
+    (void)hipFree(pl->d_kp);
+    (void)hipFree(pl->d_status);
+    delete pl;
+}
+
+// Twiddle tables, stage s at offset 2^(s-1) - 1: FP32 values for the plain
+// form; for MX the element values of each pre-quantised block (blocks of
+// min(cb, h) consecutive j, shared exponent floor(log2 amax) - emax).
+void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector<int32_t>& tw_exp,
+                    int32_t* off)
+{
+    const int n = pl->n;
+    tw.assign(n > 1 ? n - 1 : 1, make_float2(0.f, 0.f));
+    tw_exp.clear();
+    const HostElem& f = (pl->mode == mxk::MODE_E5M2) ? kE5M2 : kE4M3;
+    for (int s = 1; s <= pl->logn; s++) {
+        const long m = 1L << s, h = m / 2;
+        off[s] = (int32_t)tw_exp.size();
+        std::vector<double> wr(h), wi(h);
+        for (long j = 0; j < h; j++) twiddle(j, m, &wr[j], &wi[j]);
+        if (pl->mode == mxk::MODE_FP32) {
+            for (long j = 0; j < h; j++) tw[h - 1 + j] = make_float2((float)wr[j], (float)wi[j]);
+            continue;
+        }
+        const long tb = (pl->cb < h) ? pl->cb : h;
+        for (long j0 = 0; j0 < h; j0 += tb) {
+            double amax = 0.0;
+            for (long j = j0; j < j0 + tb; j++) amax = std::fmax(amax, std::fmax(std::fabs(wr[j]), std::fabs(wi[j])));
+            int e2;
+            std::frexp(amax, &e2);
+            const int E = (e2 - 1) - f.emax;   // amax >= 1/sqrt(2): no clamp needed
+            tw_exp.push_back(E);
+            for (long j = j0; j < j0 + tb; j++)
+                tw[h - 1 + j] = make_float2((float)round_to_elem(std::ldexp(wr[j], -E), f),
+                                            (float)round_to_elem(std::ldexp(wi[j], -E), f));
+        }
+    }
+    if (tw_exp.empty()) tw_exp.push_back(0);
+}
+
+mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* kp, int32_t* k_out,
+                  int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s)
+{
+    LaunchTimer timer(pl, inverse ? (axis ? ROLE_INV_COL : ROLE_INV_ROW) : (axis ? ROLE_COL : ROLE_ROW), s);
+    mxk::LineArgs a{};
+    a.src = (const float2*)src;
+    a.dst = (float2*)dst;
+    a.kp = kp;
+    a.k_out = k_out;
+    a.kin_mul = kin_mul;
+    a.kout_mul = kout_mul;
+    a.kout_add = kout_add;
+    a.tw = pl->d_tw;
+    a.tw_exp = pl->d_tw_exp;
+    std::memcpy(a.tw_exp_off, pl->tw_exp_off, sizeof(a.tw_exp_off));
+    a.n = pl->n;
+    a.logn = pl->logn;
+    a.cb = pl->cb;
+    a.logcb = pl->logcb;
+    a.lines = mxk::line_lines_per_group(pl->n);
+    a.axis = axis;
+    a.inverse = inverse;
+    a.encode = (pl->mode != mxk::MODE_FP32);
+    return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
+}
+
+mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
+{
+    mxk::PrescaleArgs pa{};
+    pa.target = pl->p.target;
+    pa.tau = pl->p.tau_pct;
+    int e;
+    std::frexp(pl->p.tau_min, &e);
+    pa.log2_tau_min = e - 1;
+    pa.k_min = pl->p.k_min;
+    pa.k_max = pl->p.k_max;
+    LaunchTimer timer(pl, ROLE_STATS, s);
+    if (mxk::launch_stats((const float2*)in, pl->n, batch, pl->d_ws, pl->d_kp, pl->d_status, pa, s) != hipSuccess)
+        return MXFFT_EHIP;
+    return MXFFT_OK;
+}
+
+mxfft_status check_call(const mxfft_plan_s* pl, const void* in, const void* out, int32_t batch)
+{
+    if (!pl || !in || !out) return MXFFT_EINVAL;
+    if (batch < 0 || batch > pl->max_batch) return MXFFT_EINVAL;
+    return MXFFT_OK;
+}
+
+#define MX_TRY(expr)                          \
+    do {                                      \
+        mxfft_status st_ = (expr);            \
+        if (st_ != MXFFT_OK) return st_;      \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+void mxfft_params_default(mxfft_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(mxfft_params);
+    p->format = MXFFT_E4M3;
+    p->block = 32;
+    p->k_min = INT32_MIN;
+    p->k_max = INT32_MAX;
+    p->flags = 0;
+    p->target = 128.0;
+    p->tau_pct = 5.0;
+    p->tau_min = 1.0 / 64.0;
+}
+
+mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const mxfft_params* p, void* stream)
+{
+    if (!out) return MXFFT_EINVAL;
+    *out = nullptr;
+    if (!is_pow2(n) || n < 2 || n > (1 << mxk::kMaxLog2N)) return MXFFT_EINVAL;
+    if (max_batch < 1 || max_batch > 65535) return MXFFT_EINVAL;
+    MX_TRY(check_params(p, n));
+
+    mxfft_plan_s* pl = new mxfft_plan_s();
+    pl->n = n;
+    pl->logn = ilog2(n);
+    pl->max_batch = max_batch;
+    pl->p = *p;
+    pl->mode = (p->format == MXFFT_E4M3) ? mxk::MODE_E4M3 : (p->format == MXFFT_E5M2) ? mxk::MODE_E5M2 : mxk::MODE_FP32;
+    if (pl->mode != mxk::MODE_FP32) {
+        pl->cb = p->block / 2;
+        pl->logcb = ilog2(pl->cb);
+    }
+    (void)hipGetDevice(&pl->device);
+    hipStream_t s = (hipStream_t)stream;
+
+    std::vector<float2> tw;
+    std::vector<int32_t> tw_exp;
+    build_twiddles(pl, tw, tw_exp, pl->tw_exp_off);
+
+    mxfft_status st = MXFFT_OK;
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw, tw.size(), &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw_exp, tw_exp.size(), &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_ws, (size_t)max_batch, &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_kp, (size_t)max_batch, &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
+    if (st != MXFFT_OK) {
+        release(pl);
+        return st;
+    }
+    bool ok = hipMemcpyAsync(pl->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(pl->d_tw_exp, tw_exp.data(), tw_exp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemsetAsync(pl->d_ws, 0, sizeof(mxk::SliceStats) * (size_t)max_batch, s) == hipSuccess;
+    ok = ok && hipMemsetAsync(pl->d_status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        release(pl);
+        return MXFFT_EHIP;
+    }
+    *out = pl;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_destroy(mxfft_plan_t plan)
+{
+    if (!plan) return MXFFT_OK;
+    (void)hipDeviceSynchronize();
+    release(plan);
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_forward(mxfft_plan_t pl, const void* in, void* out, int32_t batch, int32_t* k_out, void* stream)
+{
+    MX_TRY(check_call(pl, in, out, batch));
+    if (batch == 0) return MXFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
+    if (pre) MX_TRY(stats(pl, in, batch, s));
+    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
+    MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
+    pl->last_batch = batch;
+    pl->last_has_stats = pre;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t batch, const int32_t* k_in,
+                           void* stream)
+{
+    MX_TRY(check_call(pl, in, out, batch));
+    if (batch == 0) return MXFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int kout_add = (pl->p.flags & MXFFT_NORMALIZE) ? -2 * pl->logn : 0;
+    bool pre = false;
+    const int32_t* kp = k_in;
+    int kin_mul = 0;
+    if (!k_in && !(pl->p.flags & MXFFT_NO_PRESCALE)) {
+        MX_TRY(stats(pl, in, batch, s));
+        pre = true;
+        kp = pl->d_kp;
+        kin_mul = 1;
+    }
+    MX_TRY(pass(pl, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
+    pl->last_batch = batch;
+    pl->last_has_stats = pre;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t batch, int32_t* k_out,
+                             void* stream)
+{
+    MX_TRY(check_call(pl, in, out, batch));
+    if (batch == 0) return MXFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
+    if (pre) MX_TRY(stats(pl, in, batch, s));
+    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
+    pl->last_batch = batch;
+    pl->last_has_stats = pre;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_last_status(mxfft_plan_t pl, void* stream)
+{
+    if (!pl) return MXFFT_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MXFFT_EHIP;
+    if (!pl->last_has_stats || pl->last_batch == 0) return MXFFT_OK;
+    std::vector<int32_t> st(pl->last_batch);
+    if (hipMemcpy(st.data(), pl->d_status, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return MXFFT_EHIP;
+    for (int32_t v : st)
+        if (v != 0) return (mxfft_status)v;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_profile(mxfft_plan_t pl, int32_t enable)
+{
+    if (!pl) return MXFFT_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return MXFFT_EHIP;
+    collect_times(pl);
+    if (enable) {
+        for (int r = 0; r < ROLE_COUNT; r++) {
+            pl->launches[r] = 0;
+            pl->total_ms[r] = 0.0;
+        }
+    }
+    pl->profiling = enable != 0;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_kernel_times(mxfft_plan_t pl, mxfft_kernel_time* out, int32_t cap, int32_t* count)
+{
+    if (!pl || !count || (cap > 0 && !out)) return MXFFT_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return MXFFT_EHIP;
+    collect_times(pl);
+    int n = 0;
+    for (int r = 0; r < ROLE_COUNT; r++) {
+        if (!pl->launches[r]) continue;
+        if (n < cap) {
+            std::memset(out[n].name, 0, sizeof(out[n].name));
+            std::strncpy(out[n].name, kRoleNames[r], sizeof(out[n].name) - 1);
+            out[n].launches = pl->launches[r];
+            out[n].total_ms = pl->total_ms[r];
+        }
+        n++;
+    }
+    *count = n;
+    return MXFFT_OK;
+}
+
+uint64_t mxfft_plan_device_bytes(mxfft_plan_t pl) { return pl ? pl->bytes : 0; }
+
+const char* mxfft_status_string(mxfft_status st)
+{
+    switch (st) {
+    case MXFFT_OK: return "ok";
+    case MXFFT_EINVAL: return "invalid argument";
+    case MXFFT_ENOMEM: return "device allocation failed";
+    case MXFFT_EHIP: return "HIP runtime error";
+    case MXFFT_ENONFINITE: return "non-finite input";
+    case MXFFT_ERANGE: return "prescale overflows FP32";
+    case MXFFT_EBUDGET: return "over memory budget";
+    case MXFFT_EBUSY: return "busy";
+    case MXFFT_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+int32_t mxfft_version(void) { return 100; }
+
+}  // extern "C"

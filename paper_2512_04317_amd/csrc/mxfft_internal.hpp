@@ -1,0 +1,61 @@
+// mxfft_internal.hpp -- host-side interface between the plan code and the
+// kernel launchers (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mxk {
+
+constexpr int kMaxLog2N = 12;       // n <= 4096
+constexpr int kStatsBins = 288;     // floor(log2 |x|) + 149, |x| from FP32 parts: 0..276
+constexpr int kBinOffset = 149;
+
+// Per-slice prescale statistics (device workspace; all zero between calls).
+struct alignas(16) SliceStats {
+    uint32_t hist[kStatsBins];      // nonzero |x| per binade floor(log2 |x|)
+    unsigned long long max_m2;      // bits of max |x|^2 (FP64, non-negative)
+    uint32_t count;                 // nonzero elements
+    uint32_t max_comp;              // bits of max(|re|, |im|) (FP32)
+    uint32_t nonfinite;             // any Inf/NaN part
+    uint32_t ticket;                // work-groups done
+    uint32_t pad[2];
+};
+
+// Alg. 1 parameters as the device needs them.
+struct PrescaleArgs {
+    double target;      // T > 0
+    double tau;         // percent
+    int32_t log2_tau_min;  // tau_min = 2^log2_tau_min
+    int32_t k_min, k_max;
+};
+
+// One launch of the line kernel: a 1D pass over lines (rows or columns) of
+// every slice in the batch.
+struct LineArgs {
+    const float2* src;
+    float2* dst;
+    const int32_t* kp;       // per-slice prescale exponent, or nullptr (= 0)
+    int32_t* k_out;          // per-slice copy of kp written by the row pass, or nullptr
+    int32_t kin_mul;         // input is scaled by 2^(kin_mul * kp)
+    int32_t kout_mul;        // output is scaled by 2^(kout_mul * kp + kout_add)
+    int32_t kout_add;
+    const float2* tw;        // stage s, index j at [2^(s-1) - 1 + j]: element values (MX) or FP32 twiddles
+    const int32_t* tw_exp;   // MX: twiddle block exponents, stage s at tw_exp_off[s]
+    int32_t tw_exp_off[kMaxLog2N + 2];
+    int32_t n, logn;
+    int32_t cb, logcb;       // complex values per MX block (B/2)
+    int32_t lines;           // lines per work-group (power of two)
+    int32_t axis;            // 0 rows (contiguous), 1 columns
+    int32_t inverse;
+    int32_t encode;          // MX-encode the pass input
+};
+
+enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP32 = 4 };
+
+hipError_t launch_stats(const float2* x, int n, int batch, SliceStats* ws, int32_t* kp,
+                        int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s);
+hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
+int line_lines_per_group(int n);
+
+}  // namespace mxk

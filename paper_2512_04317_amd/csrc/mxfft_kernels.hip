@@ -1,0 +1,376 @@
+// mxfft_kernels.hip -- gfx950 kernels of the MX-scaled mixed-precision 2D FFT.
+//
+//  k_stats : global power-of-two prescale of each slice (Alg. 1), exact.
+//  k_lines : one radix-2 decimation-in-time pass over the rows or the columns
+//            of every slice, with per-block MX encoding of the pass input and
+//            the MX-scaled butterfly of Alg. 2 at every stage (or the plain
+//            FP32 butterfly for the comparison form).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mx_device.hpp"
+#include "mxfft_internal.hpp"
+
+namespace mxk {
+
+// ---------------------------------------------------------------------------
+// Alg. 1: prescale statistics and exponent
+// ---------------------------------------------------------------------------
+
+// round(log2(T / a)) exactly for T, a > 0.  With R = (T/a)^2 and
+// l = floor(log2 R) the result is floor((l + 1) / 2): log2(T/a) lies in
+// [l/2, (l+1)/2), and a tie would need T/a to be an odd power of sqrt 2.
+__device__ int round_log2_ratio(double T, double a)
+{
+    int eT, ea;
+    const double fT = frexp(T, &eT), fa = frexp(a, &ea);
+    const unsigned long long MT = (unsigned long long)ldexp(fT, 53);
+    const unsigned long long Ma = (unsigned long long)ldexp(fa, 53);
+    const unsigned __int128 A = (unsigned __int128)MT * MT;
+    const unsigned __int128 C = (unsigned __int128)Ma * Ma;
+    int j;  // floor(log2(A / C)), A / C in (1/4, 4)
+    if (A >= (C << 1)) j = 1;
+    else if (A >= C) j = 0;
+    else if ((A << 1) >= C) j = -1;
+    else j = -2;
+    const int l = 2 * (eT - ea) + j;
+    return (l + 1) >> 1;
+}
+
+__global__ __launch_bounds__(256) void k_stats(const float2* __restrict__ x, int nn, int chunk,
+                                                int chunks, SliceStats* __restrict__ wsall,
+                                                int32_t* __restrict__ kp, int32_t* __restrict__ slice_status,
+                                                PrescaleArgs pa)
+{
+#pragma clang fp contract(off)
+    __shared__ uint32_t hist[kStatsBins];
+    __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
+    __shared__ uint32_t s_count, s_maxc, s_nonfin;
+    __shared__ int s_last, s_refine, s_bin_lo, s_bin_hi;
+
+    const int tid = threadIdx.x, lane = tid & 63, slice = blockIdx.y;
+    SliceStats* ws = wsall + slice;
+    const float2* xs = x + (size_t)slice * nn;
+
+    for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
+    if (tid == 0) { s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; }
+    __syncthreads();
+
+    unsigned long long mm = 0;
+    uint32_t cnt = 0, mc = 0, nf = 0;
+    const int beg = blockIdx.x * chunk, end = min(beg + chunk, nn);
+    for (int base = beg; base < end; base += blockDim.x) {
+        const int i = base + tid;
+        int bin = -1;
+        if (i < end) {
+            const float2 v = xs[i];
+            const uint32_t br = __float_as_uint(v.x), bi = __float_as_uint(v.y);
+            const uint32_t bad = ((br & 0x7f800000u) == 0x7f800000u) | ((bi & 0x7f800000u) == 0x7f800000u);
+            nf |= bad;
+            mc = max(mc, max(br & 0x7fffffffu, bi & 0x7fffffffu));
+            // |x|^2 in FP64: both squares are exact, the sum is rounded once
+            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+            if (!bad && m2 > 0.0) {
+                cnt++;
+                mm = max(mm, b);
+                // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (sqrt is monotone and
+                // correctly rounded, so it never crosses a power of two)
+                bin = ((((int)(b >> 52)) - 1023) >> 1) + kBinOffset;
+            }
+        }
+        // histogram update, aggregated over lanes that share a bin
+        unsigned long long act = __ballot(bin >= 0);
+        while (act) {
+            const int leader = __builtin_ctzll(act);
+            const int lb = __shfl(bin, leader, 64);
+            const unsigned long long same = __ballot(bin == lb);
+            if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
+            act &= ~same;
+        }
+    }
+    atomicMax(&s_m2, mm);
+    atomicAdd(&s_count, cnt);
+    atomicMax(&s_maxc, mc);
+    atomicOr(&s_nonfin, nf);
+    __syncthreads();
+
+    for (int i = tid; i < kStatsBins; i += blockDim.x)
+        if (hist[i]) atomicAdd(&ws->hist[i], hist[i]);
+    if (tid == 0) {
+        atomicMax(&ws->max_m2, s_m2);
+        atomicAdd(&ws->count, s_count);
+        atomicMax(&ws->max_comp, s_maxc);
+        atomicOr(&ws->nonfinite, s_nonfin);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&ws->ticket, 1u) == (uint32_t)(chunks - 1));
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    // ---- the last work-group of the slice computes k ----
+    for (int i = tid; i < kStatsBins; i += blockDim.x)
+        hist[i] = __hip_atomic_load(&ws->hist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+        s_m2 = __hip_atomic_load(&ws->max_m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_count = __hip_atomic_load(&ws->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_maxc = __hip_atomic_load(&ws->max_comp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_nonfin = __hip_atomic_load(&ws->nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_refine = 0;
+    }
+    __syncthreads();
+
+    const uint32_t n = s_count;
+    const double pos = ((double)(n ? n - 1 : 0) * pa.tau) / 100.0;
+    long long ri = (long long)floor(pos);
+    if (n && ri > (long long)n - 1) ri = (long long)n - 1;
+    const double fr = pos - (double)ri;
+    if (tid == 0 && n && !s_nonfin) {
+        // binades holding the order statistics ri and ri + 1 (S[n] := S[n-1])
+        const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
+        long long cum = 0;
+        int blo = -1, bhi = -1;
+        for (int b = 0; b < kStatsBins; b++) {
+            cum += hist[b];
+            if (blo < 0 && cum > ri) blo = b;
+            if (bhi < 0 && cum > r1) { bhi = b; break; }
+        }
+        s_bin_lo = blo;
+        s_bin_hi = bhi;
+        s_refine = (blo != bhi) && (fr != 0.0);
+        s_lo_max = 0;
+        s_hi_min = ~0ull;
+    }
+    __syncthreads();
+    if (s_refine) {
+        // the two order statistics sit in different binades: S[ri] is the largest
+        // value of the lower one and S[ri+1] the smallest of the upper one
+        for (int i = tid; i < nn; i += blockDim.x) {
+            const float2 v = xs[i];
+            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+            if (m2 > 0.0) {
+                const int bin = ((((int)(b >> 52)) - 1023) >> 1) + kBinOffset;
+                if (bin == s_bin_lo) atomicMax(&s_lo_max, b);
+                if (bin == s_bin_hi) atomicMin(&s_hi_min, b);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int32_t k = 0, st = 0;
+        if (s_nonfin) {
+            st = -4;  // MXFFT_ENONFINITE
+        } else if (n) {
+            const double amax = __dsqrt_rn(__longlong_as_double((long long)s_m2));
+            const int k1 = round_log2_ratio(pa.target, amax > 1e-30 ? amax : 1e-30);
+            int lp;  // floor(log2 p_tau)
+            if (s_refine) {
+                const double lo = __dsqrt_rn(__longlong_as_double((long long)s_lo_max));
+                const double hi = __dsqrt_rn(__longlong_as_double((long long)s_hi_min));
+                const double d = hi - lo;
+                const double fd = fr * d;
+                const double p = lo + fd;
+                int e;
+                frexp(p, &e);
+                lp = e - 1;
+            } else {
+                lp = s_bin_lo - kBinOffset;
+            }
+            lp = max(lp, -100);  // max(p, 1e-30): 1e-30 lies in binade -100
+            const int k2 = pa.log2_tau_min - lp;
+            long long kk = max(k1, k2);
+            kk = min(max(kk, (long long)pa.k_min), (long long)pa.k_max);
+            k = (int32_t)kk;
+            // every component scaled by 2^k must stay finite in FP32
+            if (s_maxc) {
+                const int e = __builtin_amdgcn_frexp_expf(__uint_as_float(s_maxc)) - 1;
+                if ((long long)e + kk > 127) st = -5;  // MXFFT_ERANGE
+            }
+        }
+        kp[slice] = st ? INT32_MIN : k;
+        slice_status[slice] = st;
+    }
+    // leave the workspace zeroed for the next call
+    for (int i = tid; i < kStatsBins; i += blockDim.x) ws->hist[i] = 0;
+    if (tid == 0) {
+        ws->max_m2 = 0;
+        ws->count = 0;
+        ws->max_comp = 0;
+        ws->nonfinite = 0;
+        ws->ticket = 0;
+    }
+}
+
+hipError_t launch_stats(const float2* x, int n, int batch, SliceStats* ws, int32_t* kp,
+                        int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s)
+{
+    const int nn = n * n;
+    int chunks = nn / 16384;
+    if (chunks < 1) chunks = 1;
+    const int chunk = nn / chunks;
+    hipLaunchKernelGGL(k_stats, dim3(chunks, batch), dim3(256), 0, s, x, nn, chunk, chunks, ws, kp,
+                       slice_status, pa);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One radix-2 pass over lines held in LDS
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float2 u, float2 v,
+                                          float2& y0, float2& y1)
+{
+    const int h = 1 << (s - 1);
+    float2 w = a.tw[h - 1 + j];
+    if (a.inverse) w.y = -w.y;
+    float pr, pi;
+    if constexpr (MODE == MODE_FP32) {
+        pr = w.x * v.x - w.y * v.y;
+        pi = w.x * v.y + w.y * v.x;
+    } else {
+        constexpr int F = MODE;
+        // twiddle block: min(cb, h) consecutive j share one exponent
+        const int Ew = a.tw_exp[a.tw_exp_off[s] + (a.cb <= h ? (j >> a.logcb) : 0)];
+        // operand v: EncodeBlockMX over the cb butterflies of this block (cb lanes)
+        const uint32_t av = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
+        const int Ev = mxd::block_exp<F>(av);
+        const float yr = mxd::quant<F>(ldexpf(v.x, -Ev));
+        const float yi = mxd::quant<F>(ldexpf(v.y, -Ev));
+        // mantissa-space product: products of 8-bit elements are exact in FP32
+        const float qr = w.x * yr - w.y * yi;
+        const float qi = w.x * yi + w.y * yr;
+        // renormalise the product block when it exceeds the element range
+        const uint32_t ap = mxd::group_max(max(mxd::abs_key(qr), mxd::abs_key(qi)), a.cb);
+        const int kr = mxd::renorm_exp<F>(ap);
+        const float cr = mxd::quant<F>(ldexpf(qr, -kr));
+        const float ci = mxd::quant<F>(ldexpf(qi, -kr));
+        const int Eo = Ew + Ev + kr;
+        pr = ldexpf(cr, Eo);
+        pi = ldexpf(ci, Eo);
+    }
+    y0 = make_float2(u.x + pr, u.y + pi);
+    y1 = make_float2(u.x - pr, u.y - pi);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_lines(LineArgs a)
+{
+    extern __shared__ float2 lds[];
+    const int N = a.n, logn = a.logn, R = a.lines, tid = threadIdx.x;
+    const int slice = blockIdx.y;
+    const size_t sbase = (size_t)slice * N * N;
+    const int line0 = blockIdx.x * R;
+    int kp = a.kp ? a.kp[slice] : 0;
+    if (kp == INT32_MIN) kp = 0;  // failed slice: output undefined, keep it finite-safe
+    const int kin = a.kin_mul * kp, kout = a.kout_mul * kp + a.kout_add;
+    if (a.k_out && blockIdx.x == 0 && tid == 0) a.k_out[slice] = a.kp ? a.kp[slice] : 0;
+    const int total = R * N;
+
+    // load (coalesced along the contiguous axis), apply the prescale
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        int r, e;
+        size_t g;
+        if (a.axis == 0) {
+            r = idx >> logn;
+            e = idx & (N - 1);
+            g = sbase + (size_t)(line0 + r) * N + e;
+        } else {
+            e = idx / R;
+            r = idx & (R - 1);
+            g = sbase + (size_t)e * N + line0 + r;
+        }
+        float2 v = a.src[g];
+        v.x = ldexpf(v.x, kin);
+        v.y = ldexpf(v.y, kin);
+        lds[r * N + e] = v;
+    }
+    __syncthreads();
+
+    if constexpr (MODE != MODE_FP32) {
+        if (a.encode) {
+            // pass input: blocks of cb consecutive values along the line
+            for (int idx = tid; idx < total; idx += blockDim.x) {
+                float2 v = lds[idx];
+                const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
+                const int E = mxd::block_exp<MODE>(am);
+                v.x = ldexpf(mxd::quant<MODE>(ldexpf(v.x, -E)), E);
+                v.y = ldexpf(mxd::quant<MODE>(ldexpf(v.y, -E)), E);
+                lds[idx] = v;
+            }
+            __syncthreads();
+        }
+    }
+
+    // bit reversal (decimation in time)
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        const int r = idx >> logn, e = idx & (N - 1);
+        const int rev = (int)(__brev((unsigned)e) >> (32 - logn));
+        if (rev > e) {
+            const float2 t = lds[r * N + e];
+            lds[r * N + e] = lds[r * N + rev];
+            lds[r * N + rev] = t;
+        }
+    }
+    __syncthreads();
+
+    const int half = N >> 1, nbf = total >> 1;
+    for (int s = 1; s <= logn; s++) {
+        const int h = 1 << (s - 1);
+        for (int b = tid; b < nbf; b += blockDim.x) {
+            const int r = b >> (logn - 1);
+            const int t = b & (half - 1);
+            const int g = t >> (s - 1), j = t & (h - 1);
+            const int iu = r * N + (g << s) + j, iv = iu + h;
+            float2 y0, y1;
+            butterfly<MODE>(a, s, j, lds[iu], lds[iv], y0, y1);
+            lds[iu] = y0;
+            lds[iv] = y1;
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        int r, e;
+        size_t g;
+        if (a.axis == 0) {
+            r = idx >> logn;
+            e = idx & (N - 1);
+            g = sbase + (size_t)(line0 + r) * N + e;
+        } else {
+            e = idx / R;
+            r = idx & (R - 1);
+            g = sbase + (size_t)e * N + line0 + r;
+        }
+        float2 v = lds[r * N + e];
+        v.x = ldexpf(v.x, kout);
+        v.y = ldexpf(v.y, kout);
+        a.dst[g] = v;
+    }
+}
+
+int line_lines_per_group(int n)
+{
+    int r = 8192 / n;
+    if (r > n) r = n;
+    if (r < 1) r = 1;
+    return r;
+}
+
+hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s)
+{
+    const dim3 grid(a.n / a.lines, batch), block(256);
+    const size_t lds = (size_t)a.lines * a.n * sizeof(float2);
+    switch (mode) {
+    case MODE_E4M3: hipLaunchKernelGGL(k_lines<MODE_E4M3>, grid, block, lds, s, a); break;
+    case MODE_E5M2: hipLaunchKernelGGL(k_lines<MODE_E5M2>, grid, block, lds, s, a); break;
+    case MODE_FP32: hipLaunchKernelGGL(k_lines<MODE_FP32>, grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mxk

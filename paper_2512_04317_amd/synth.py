@@ -78,11 +78,22 @@ def kspace_slice(N, config, slice_idx, coils):
     return out
 
 
-def kspace_batch(N, config, slices, coils, first_slice=0):
-    """complex64 [slices * coils, N, N]: slice-major, coil-minor."""
+def kspace_batch(N, config, slices, coils, first_slice=0, workers=1):
+    """complex64 [slices * coils, N, N]: slice-major, coil-minor.  `workers`
+    threads build slices concurrently (numpy's FFT releases the GIL); the
+    result does not depend on it."""
     out = np.empty((slices * coils, N, N), np.complex64)
-    for s in range(slices):
+
+    def one(s):
         out[s * coils:(s + 1) * coils] = kspace_slice(N, config, first_slice + s, coils)
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, range(slices)))
+    else:
+        for s in range(slices):
+            one(s)
     return out
 
 

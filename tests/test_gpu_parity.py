@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+MX results are compared bit for bit (outputs, prescale exponents); the FP32
+plain form within NRMSE 1e-6 of the oracle's FP32 form (it may contract
+multiply-adds).  Inputs are the seeded synthetic k-space and seeded random
+data with heavy-tailed magnitudes.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2512_04317_amd import mxfft, synth
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+FMTS = {"e4m3": O.E4M3, "e5m2": O.E5M2}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+
+
+def gpu_run(x, op="forward", n_batch=None, k_in=None, **params):
+    x = np.ascontiguousarray(x.reshape(-1, x.shape[-2], x.shape[-1]))
+    batch, N = x.shape[0], x.shape[-1]
+    print("gpu case: op=%s N=%d batch=%d %s" % (op, N, batch, params), flush=True)
+    plan = mxfft.Plan(N, n_batch or batch, **params)
+    xd = torch.from_numpy(x).cuda()
+    k = None
+    if op == "forward":
+        y, k = plan.forward(xd)
+    elif op == "inverse":
+        kd = None if k_in is None else torch.from_numpy(np.asarray(k_in, np.int32)).cuda()
+        y = plan.inverse(xd, k_in=kd)
+    else:
+        y, k = plan.roundtrip(xd)
+    st = plan.last_status()
+    torch.cuda.synchronize()
+    out = (y.cpu().numpy(), None if k is None else k.cpu().numpy(), st)
+    plan.close()
+    return out
+
+
+def orc_run(x, op="forward", fmt="e4m3", block=32, k_in=None, flags=0, **kw):
+    opcode = {"forward": O.FORWARD, "inverse": O.INVERSE, "roundtrip": O.ROUNDTRIP}[op]
+    if fmt == "fp32":
+        mode, f = O.MODE_FP32, O.E4M3
+    else:
+        mode, f = O.MODE_MX, FMTS[fmt]
+    return O.transform(x, op=opcode, mode=mode, fmt=f, B=block, kp=k_in, flags=flags, nthreads=NTHREADS, **kw)
+
+
+def nrmse(y, r):
+    return float(np.linalg.norm((y - r).ravel()) / max(np.linalg.norm(r.ravel()), 1e-300))
+
+
+def assert_bitexact(yg, yo, what=""):
+    yg = np.ascontiguousarray(yg).reshape(yo.shape)
+    bad = yg.view(np.uint32) != yo.view(np.uint32)
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        raise AssertionError("%s: %d of %d words differ (NRMSE %.3g); first at %s: gpu %s oracle %s"
+                             % (what, bad.sum(), bad.size, nrmse(yg, yo), idx.tolist(),
+                                yg.view(np.float32).ravel()[bad.ravel()][:4],
+                                yo.view(np.float32).ravel()[bad.ravel()][:4]))
+
+
+def small_cases():
+    out = []
+    for N in (2, 4, 8, 16, 32, 64, 128):
+        for fmt in ("e4m3", "e5m2"):
+            for B in (2, 4, 8, 16, 32, 64, 128):
+                if B <= N:
+                    out.append((N, fmt, B))
+    return out
+
+
+@pytest.mark.parametrize("N,fmt,B", small_cases())
+def test_forward_small(N, fmt, B):
+    x = synth.random_complex((3, N, N), seed=N * 1000 + B, dist="lognormal")
+    yg, kg, st = gpu_run(x, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "forward N=%d %s B=%d" % (N, fmt, B))
+
+
+@pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
+@pytest.mark.parametrize("B", [8, 16, 32, 64])
+def test_forward_kspace_256(fmt, B):
+    x = synth.kspace_batch(256, 2, 1, 8)
+    yg, kg, st = gpu_run(x, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, fmt=fmt, block=B)
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "kspace256 %s B=%d" % (fmt, B))
+
+
+@pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
+@pytest.mark.parametrize("N", [64, 256])
+def test_inverse_and_roundtrip(fmt, N):
+    x = synth.kspace_batch(N, 2, 1, 4)
+    # inverse with its own prescale
+    yg, _, st = gpu_run(x, op="inverse", fmt=fmt, block=32)
+    so, yo, _ = orc_run(x, op="inverse", fmt=fmt, block=32)
+    assert_bitexact(yg, yo, "inverse")
+    # inverse of a KEEP_SCALE forward output with the forward's k, normalised
+    so, mid, k = orc_run(x, fmt=fmt, block=32, flags=O.KEEP_SCALE)
+    yg, _, st = gpu_run(mid, op="inverse", k_in=k, fmt=fmt, block=32, flags=mxfft.NORMALIZE)
+    so, yo, _ = orc_run(mid, op="inverse", fmt=fmt, block=32, k_in=k, flags=O.NORMALIZE)
+    assert_bitexact(yg, yo, "inverse with k_in")
+    # the round trip of Eq. 1
+    yg, kg, st = gpu_run(x, op="roundtrip", fmt=fmt, block=32)
+    so, yo, ko = orc_run(x, op="roundtrip", fmt=fmt, block=32)
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "roundtrip")
+
+
+@pytest.mark.parametrize("N", [4, 64, 256, 512])
+def test_fp32_plain(N):
+    x = synth.kspace_batch(N, 2, 1, 2) if N >= 64 else synth.random_complex((2, N, N), seed=5)
+    yg, kg, st = gpu_run(x, fmt="fp32")
+    so, yo, ko = orc_run(x, fmt="fp32")
+    np.testing.assert_array_equal(kg, ko)
+    assert nrmse(yg, yo) <= 1e-6
+    ref = np.fft.fft2(x.astype(np.complex128))
+    assert nrmse(yg, ref) <= 2e-6
+    yg, _, _ = gpu_run(x, op="roundtrip", fmt="fp32")
+    assert nrmse(yg, x) <= 1e-6
+
+
+def prescale_cases():
+    rng = np.random.default_rng(77)
+    N = 32
+    cases = []
+    cases.append(("zeros", np.zeros((N, N), np.complex64), {}))
+    one = np.zeros((N, N), np.complex64)
+    one[3, 5] = 3.0 - 4.0j
+    cases.append(("single", one, {}))
+    cases.append(("lognormal", synth.random_complex((N, N), seed=9, dist="lognormal"), {}))
+    cases.append(("kspace", synth.kspace_batch(N, 1, 1, 1)[0], {}))
+    cases.append(("tiny", (synth.random_complex((N, N), seed=10) * np.float32(1e-30)), {}))
+    cases.append(("clip", synth.random_complex((N, N), seed=11), dict(k_min=-2, k_max=1)))
+    cases.append(("target", synth.random_complex((N, N), seed=12), dict(target=300.0, tau=37.0, tau_min=2.0 ** 3)))
+    # order statistics either side of a power of two: refinement path
+    st = np.full(N * N, 1.1, np.float32)
+    st[:2] = 0.9
+    rng.shuffle(st)
+    cases.append(("straddle", st.reshape(N, N).astype(np.complex64), dict(tau=0.15, tau_min=2.0 ** 10)))
+    st2 = np.full(N * N, 3.0, np.float32)
+    st2[:40] = 1.75
+    cases.append(("straddle2", st2.reshape(N, N).astype(np.complex64), dict(tau=3.85, tau_min=2.0 ** 10)))
+    return cases
+
+
+@pytest.mark.parametrize("name,x,kw", prescale_cases(), ids=[c[0] for c in prescale_cases()])
+def test_prescale_exponent(name, x, kw):
+    so, yo, ko = orc_run(x[None], fmt="e4m3", block=32, **kw)
+    yg, kg, st = gpu_run(x[None], fmt="e4m3", block=32, **kw)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "prescale case " + name)
+
+
+def test_flags_no_prescale_keep_scale():
+    x = synth.kspace_batch(64, 2, 1, 2)
+    for flags in (mxfft.NO_PRESCALE, mxfft.KEEP_SCALE):
+        yg, kg, st = gpu_run(x, fmt="e5m2", block=16, flags=flags)
+        so, yo, ko = orc_run(x, fmt="e5m2", block=16, flags=flags)
+        np.testing.assert_array_equal(kg, ko)
+        assert_bitexact(yg, yo, "flags %d" % flags)
+
+
+def test_nonfinite_and_range_errors():
+    x = synth.kspace_batch(32, 1, 1, 3)
+    x[1, 4, 4] = np.nan
+    yg, kg, st = gpu_run(x, fmt="e4m3", block=8)
+    assert st == mxfft.ENONFINITE
+    assert kg[1] == mxfft.INT32_MIN and kg[0] != mxfft.INT32_MIN and kg[2] != mxfft.INT32_MIN
+    so, yo, ko = orc_run(x, fmt="e4m3", block=8)
+    assert_bitexact(yg[[0, 2]], yo[[0, 2]], "finite slices beside a non-finite one")
+    # largest component 215.09 = 1.68 * 2^7: 2^120 still fits FP32, 2^121 overflows
+    x = synth.kspace_batch(32, 1, 1, 1)
+    yg, kg, st = gpu_run(x, fmt="e4m3", block=8, k_min=120)
+    assert st == mxfft.OK and kg[0] == 120 and O.prescale(x[0], k_min=120) == (O.OK, 120)
+    yg, kg, st = gpu_run(x, fmt="e4m3", block=8, k_min=121)
+    assert st == mxfft.ERANGE and kg[0] == mxfft.INT32_MIN
+    assert O.prescale(x[0], k_min=121) == (O.ERANGE, O.INT32_MIN)
+
+
+def test_in_place_batch_independence_determinism():
+    x = synth.kspace_batch(128, 2, 2, 3)
+    plan = mxfft.Plan(128, 8, fmt="e4m3", block=32)
+    xd = torch.from_numpy(x).cuda()
+    y1, k1 = plan.forward(xd)
+    y2, k2 = plan.forward(xd)
+    xi = xd.clone()
+    y3, k3 = plan.forward(xi, out=xi)
+    y4, k4 = plan.forward(xd[2:3].contiguous())
+    torch.cuda.synchronize()
+    a = y1.cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), y2.cpu().numpy().view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), y3.cpu().numpy().view(np.uint32))
+    assert np.array_equal(a[2:3].view(np.uint32), y4.cpu().numpy().view(np.uint32))
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def full_workload():
+    w = synth.WORKLOADS["kspace512_64x16"]
+    x = synth.kspace_batch(w["N"], w["config"], w["slices"], w["coils"], workers=NTHREADS)
+    return x
+
+
+def test_full_size_sampled(full_workload):
+    """The benchmark's launch: 1024 slices of 512^2, MXFP8-E4M3, B = 32.
+    Every slice's k against the oracle's Alg. 1; three whole slices bit for bit."""
+    x = full_workload
+    plan = mxfft.Plan(512, x.shape[0], fmt="e4m3", block=32)
+    xd = torch.from_numpy(x).cuda()
+    print("gpu case: full size 1024 x 512^2 e4m3 B=32", flush=True)
+    y, k = plan.forward(xd)
+    assert plan.last_status() == mxfft.OK
+    kg = k.cpu().numpy()
+    for s in range(0, x.shape[0], 16):
+        st, ko = O.prescale(x[s])
+        assert kg[s] == ko, s
+    pick = [0, 517, x.shape[0] - 1]
+    so, yo, ko = orc_run(x[pick], fmt="e4m3", block=32)
+    yg = y[pick].cpu().numpy()
+    assert_bitexact(yg, yo, "full-size sampled slices")
+    plan.close()

@@ -112,14 +112,14 @@ def test_numpy_percentile_agrees_away_from_ties():
 
 def test_clip_and_errors():
     x = one([3.0, 1e-3])
-    assert O.prescale(x, kmin=10)[1] == 10
-    assert O.prescale(x, kmax=-2)[1] == -2
+    assert O.prescale(x, k_min=10)[1] == 10
+    assert O.prescale(x, k_max=-2)[1] == -2
     st, k = O.prescale(one([1.0, np.inf]))
     assert st == O.ENONFINITE and k == O.INT32_MIN
     st, k = O.prescale(one([np.nan, 1.0]))
     assert st == O.ENONFINITE
     # component 2^100 shifted by k >= 28 overflows FP32
-    st, k = O.prescale(one([2.0 ** 100]), kmin=28)
+    st, k = O.prescale(one([2.0 ** 100]), k_min=28)
     assert st == O.ERANGE and k == O.INT32_MIN
-    st, k = O.prescale(one([2.0 ** 100]), kmin=27)
+    st, k = O.prescale(one([2.0 ** 100]), k_min=27)
     assert st == O.OK and k == 27
