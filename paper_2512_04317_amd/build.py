@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmxfft.so")
 
-SOURCES = ["mxfft_kernels.hip", "mxfft_host.cpp"]
+SOURCES = ["mxfft_kernels.hip", "mxfft_fast.hip", "mxfft_host.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -85,6 +85,11 @@ struct mxfft_plan_s {
     mxk::SliceStats* d_ws = nullptr;
     int32_t* d_kp = nullptr;
     int32_t* d_status = nullptr;
+    // register-resident path (n = 512): twiddles at [h + j], MX intermediate
+    bool fast = false;
+    float2* d_twf = nullptr;
+    uint32_t* d_codes = nullptr;
+    uint8_t* d_exps = nullptr;
     uint64_t bytes = 0;
     int last_batch = 0;
     bool last_has_stats = false;
@@ -200,6 +205,9 @@ void release(mxfft_plan_s* pl)
     (void)hipFree(pl->d_ws);
     (void)hipFree(pl->d_kp);
     (void)hipFree(pl->d_status);
+    (void)hipFree(pl->d_twf);
+    (void)hipFree(pl->d_codes);
+    (void)hipFree(pl->d_exps);
     delete pl;
 }
 
@@ -242,6 +250,24 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
                   int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s)
 {
     LaunchTimer timer(pl, inverse ? (axis ? ROLE_INV_COL : ROLE_INV_ROW) : (axis ? ROLE_COL : ROLE_ROW), s);
+    if (pl->fast) {
+        // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
+        mxk::FastPassArgs f{};
+        f.src = (const float2*)src;
+        f.dst = (float2*)dst;
+        f.codes = pl->d_codes;
+        f.exps = pl->d_exps;
+        f.kp = kp;
+        f.k_out = k_out;
+        f.kin_mul = kin_mul;
+        f.kout_mul = kout_mul;
+        f.kout_add = kout_add;
+        f.tw = pl->d_twf;
+        f.tw_exp = pl->d_tw_exp;
+        for (int i = 0; i < 16; i++) f.tw_off[i] = i < mxk::kMaxLog2N + 2 ? pl->tw_exp_off[i] : 0;
+        return mxk::launch_fast(pl->mode, pl->cb, axis == 0, inverse != 0, f, batch, s) == hipSuccess ? MXFFT_OK
+                                                                                                     : MXFFT_EHIP;
+    }
     mxk::LineArgs a{};
     a.src = (const float2*)src;
     a.dst = (float2*)dst;
@@ -343,12 +369,26 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_ws, (size_t)max_batch, &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_kp, (size_t)max_batch, &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
+    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
+    std::vector<float2> twf;
+    if (st == MXFFT_OK && pl->fast) {
+        twf.assign((size_t)n, make_float2(0.f, 0.f));
+        for (long h = 1; h < n; h <<= 1)
+            for (long j = 0; j < h; j++) twf[h + j] = tw[h - 1 + j];
+        st = dev_alloc(&pl->d_twf, twf.size(), &pl->bytes);
+        if (st == MXFFT_OK && pl->mode != mxk::MODE_FP32) {
+            st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n / 2, &pl->bytes);
+            if (st == MXFFT_OK) st = dev_alloc(&pl->d_exps, (size_t)max_batch * n * (n / pl->cb), &pl->bytes);
+        }
+    }
     if (st != MXFFT_OK) {
         release(pl);
         return st;
     }
     bool ok = hipMemcpyAsync(pl->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(pl->d_tw_exp, tw_exp.data(), tw_exp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (pl->fast)
+        ok = ok && hipMemcpyAsync(pl->d_twf, twf.data(), twf.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemsetAsync(pl->d_ws, 0, sizeof(mxk::SliceStats) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipMemsetAsync(pl->d_status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;

@@ -53,6 +53,23 @@ struct LineArgs {
 
 enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP32 = 4 };
 
+// Register-resident passes for n = 512 (see mxfft_fast.hip).
+struct FastPassArgs {
+    const float2* src;
+    float2* dst;
+    uint32_t* codes;         // MX intermediate codes, 2 bytes per complex value
+    uint8_t* exps;           // MX intermediate block exponents (E8M0)
+    const int32_t* kp;
+    int32_t* k_out;
+    int32_t kin_mul, kout_mul, kout_add;
+    const float2* tw;        // stage s (h = 2^(s-1)) index j at [h + j]
+    const int32_t* tw_exp;
+    int32_t tw_off[16];
+};
+
+bool fast_supported(int mode, int n, int cb);
+hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassArgs& p, int batch, hipStream_t s);
+
 hipError_t launch_stats(const float2* x, int n, int batch, SliceStats* ws, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);

@@ -237,3 +237,18 @@ def test_full_size_sampled(full_workload):
     yg = y[pick].cpu().numpy()
     assert_bitexact(yg, yo, "full-size sampled slices")
     plan.close()
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
+@pytest.mark.parametrize("B", [2, 4, 8, 16, 32, 64])
+def test_n512_all_blocks(op, fmt, B):
+    """512^2 slices take the register-resident kernels for 4 <= B <= 32 and
+    the generic kernels otherwise; every combination is bit-exact."""
+    x = synth.kspace_batch(512, 3, 1, 2)
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "512^2 %s %s B=%d" % (op, fmt, B))
