@@ -1,0 +1,27 @@
+// fast_e5m2.hip -- instantiations of the register-resident 512^2 passes for MXFP8-E5M2.
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s)
+{
+    const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
+#define MXF_CASE(CC, INV)                                                                 \
+    if (row) hipLaunchKernelGGL((mxf::k_row<1, CC, INV>), grid, block, 0, s, g);         \
+    else hipLaunchKernelGGL((mxf::k_col<1, CC, INV>), grid, block, 0, s, g);
+    switch (cb * 2 + (inverse ? 1 : 0)) {
+    case 4: MXF_CASE(1, false) break;
+    case 5: MXF_CASE(1, true) break;
+    case 8: MXF_CASE(2, false) break;
+    case 9: MXF_CASE(2, true) break;
+    case 16: MXF_CASE(3, false) break;
+    case 17: MXF_CASE(3, true) break;
+    case 32: MXF_CASE(4, false) break;
+    case 33: MXF_CASE(4, true) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MXF_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mxk

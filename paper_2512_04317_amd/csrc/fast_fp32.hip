@@ -1,0 +1,19 @@
+// fast_fp32.hip -- instantiations of the register-resident 512^2 passes for the plain FP32 form.
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+hipError_t launch_fast_fp32(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s)
+{
+    const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
+#define MXF_CASE(CC, INV)                                                                 \
+    if (row) hipLaunchKernelGGL((mxf::k_row<mxf::FP32, CC, INV>), grid, block, 0, s, g);         \
+    else hipLaunchKernelGGL((mxf::k_col<mxf::FP32, CC, INV>), grid, block, 0, s, g);
+    (void)cb;
+    if (inverse) { MXF_CASE(1, true) }
+    else { MXF_CASE(1, false) }
+#undef MXF_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mxk

@@ -1,595 +1,17 @@
-// mxfft_fast.hip -- register-resident row and column passes for 512 x 512 slices.
-//
-// Each lane holds 32 complex values of one 512-point line; 16 lanes (one DPP
-// row) hold a line, a wave holds 4 lines and a work-group of 4 waves 16 lines.
-// A "layout" names which 5 of the 9 position bits (bit-reversed order) sit in a
-// lane.  Layout 0 holds bits 0..4 and runs stages 1..5 in registers; every later
-// layout holds bits 0..C-1 (the low bits of an MX block of 2^C butterflies)
-// plus the next 5-C unprocessed bits, so every MX block of every stage lies in
-// one lane and its shared exponent is an in-register reduction.  Layouts change
-// through a per-wave LDS exchange (re and im planes in turn, XOR-swizzled).
-//
-// MX arithmetic uses the gfx950 FP8/BF8 conversions with an E8M0-style scale:
-// encode x / 2^E with round-to-nearest-even (saturation by a prior v_med3
-// clamp, since the scaled conversion does not saturate) and decode codes
-// times 2^E exactly.  These were checked bit for bit against integer rounding
-// over all FP32 inputs of the relevant ranges.
-//
-// Row pass (MX):   load -> MX-encode blocks of 2^C consecutive values ->
-//                  bit reversal -> 9 stages -> MX-encode each column over the
-//                  work-group's 16 rows -> FP8 codes + E8M0 exponents.
-// Column pass (MX): codes -> decode (this is the column input encode) -> bit
-//                  reversal -> 9 stages -> 2^kout -> complex64.
-// The FP32 plain form uses the same skeleton without quantisation and keeps
-// an FP32 intermediate.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <utility>
-
-#include "mx_device.hpp"
-#include "mxfft_internal.hpp"
-
-namespace mxf {
-
-typedef short short2v __attribute__((ext_vector_type(2)));
-typedef float float2v __attribute__((ext_vector_type(2)));
-
-constexpr int LOGN = 9;
-constexpr int N = 1 << LOGN;
-constexpr int P = 32;            // complex values per lane
-constexpr int LPL = N / P;       // lanes per line (16)
-constexpr int LPW = 64 / LPL;    // lines per wave (4)
-constexpr int WAVES = 4;
-constexpr int LINES = LPW * WAVES;  // lines per work-group (16)
-constexpr int FP32 = 4;          // format id of the plain form (mxk::MODE_FP32)
-
-// ---------------------------------------------------------------------------
-// compile-time helpers
-// ---------------------------------------------------------------------------
-
-template <int... Is, class Fn>
-__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, Fn&& fn)
-{
-    (fn(std::integral_constant<int, Is>{}), ...);
-}
-// fn(integral_constant<int, i>) for i = 0 .. Nn-1, fully unrolled
-template <int Nn, class Fn>
-__device__ __forceinline__ void sfor(Fn&& fn)
-{
-    sfor_impl(std::make_integer_sequence<int, Nn>{}, fn);
-}
-
-constexpr int deposit(int v, int mask)
-{
-    int r = 0, k = 0;
-    for (int b = 0; b < 31; b++)
-        if ((mask >> b) & 1) {
-            if ((v >> k) & 1) r |= 1 << b;
-            k++;
-        }
-    return r;
-}
-
-constexpr int rev(int v, int bits)
-{
-    int r = 0;
-    for (int b = 0; b < bits; b++) r |= ((v >> b) & 1) << (bits - 1 - b);
-    return r;
-}
-
-// Layouts for MX blocks of 2^C butterflies (1 <= C <= 4).
-template <int C>
-struct Lay {
-    static constexpr int NEW = 5 - C;
-    static constexpr int NL = 1 + (LOGN - 5 + NEW - 1) / NEW;
-    // position bit held by in-lane offset bit i in layout k
-    static constexpr int fbit(int k, int i)
-    {
-        if (k == 0 || i < C) return i;
-        const int b = 5 + (k - 1) * NEW + (i - C);
-        return b < LOGN ? b : C + (b - LOGN);
-    }
-    static constexpr int index_of(int k, int bit)
-    {
-        for (int i = 0; i < 5; i++)
-            if (fbit(k, i) == bit) return i;
-        return -1;
-    }
-    // q-th position bit fixed per lane (ascending), taken from lane bit q
-    static constexpr int xbit(int k, int q)
-    {
-        int cnt = 0;
-        for (int b = 0; b < LOGN; b++)
-            if (index_of(k, b) < 0) {
-                if (cnt == q) return b;
-                cnt++;
-            }
-        return -1;
-    }
-    static constexpr int posF(int k, int o)
-    {
-        int p = 0;
-        for (int i = 0; i < 5; i++)
-            if ((o >> i) & 1) p |= 1 << fbit(k, i);
-        return p;
-    }
-    static constexpr int bfirst(int k) { return k == 0 ? 0 : 5 + (k - 1) * NEW; }
-    static constexpr int blast(int k)
-    {
-        const int e = (k == 0) ? 5 : 5 + k * NEW;
-        return e < LOGN ? e : LOGN;
-    }
-};
-
-template <int C, int K>
-__device__ __forceinline__ int posM(int m)
-{
-    int p = 0;
-    sfor<LOGN - 5>([&](auto Q) { p |= ((m >> Q) & 1) << Lay<C>::xbit(K, Q); });
-    return p;
-}
-
-// LDS plane index of position p of a line: bits 1..4 XOR a function of bits
-// 5..8 chosen so that, with blocks of 16 butterflies, the 16 lanes of a line
-// hit 16 distinct bank pairs in every layout (other block sizes may see 2-way
-// conflicts); bit 0 is kept so pairs stay adjacent.
-__device__ __forceinline__ int swz(int p)
-{
-    const int b5 = (p >> 5) & 1, b6 = (p >> 6) & 1, b7 = (p >> 7) & 1, b8 = (p >> 8) & 1;
-    const int s = (b5 ^ b8) | ((b6 ^ b8) << 1) | ((b7 ^ b8) << 2) | (b8 << 3);
-    return p ^ (s << 1);
-}
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// ---------------------------------------------------------------------------
-// MX element conversions (gfx950)
-// ---------------------------------------------------------------------------
-
-// 2^E as the E8M0-style scale operand, -127 <= E <= 127.
-__device__ __forceinline__ float e8(int E) { return __uint_as_float((uint32_t)(E + 127) << 23); }
-
-// MAXV * 2^E (MAXV = 1.75 * 2^EMAX), the saturation bound at block scale 2^E.
-template <int F>
-__device__ __forceinline__ float lim_of(int E)
-{
-    return __uint_as_float(((uint32_t)(E + mxd::Elem<F>::EMAX + 127) << 23) | 0x00600000u);
-}
-
-// codes of (a, b) / 2^E in the low (W = 0) or high (W = 1) half of `old`
-template <int F, bool W>
-__device__ __forceinline__ uint32_t enc2(uint32_t old, float a, float b, float scale)
-{
-    short2v o;
-    __builtin_memcpy(&o, &old, 4);
-    short2v r;
-    if constexpr (F == 0) r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(o, a, b, scale, W);
-    else r = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(o, a, b, scale, W);
-    uint32_t u;
-    __builtin_memcpy(&u, &r, 4);
-    return u;
-}
-
-// element values of the two codes in half W, times 2^E
-template <int F, bool W>
-__device__ __forceinline__ float2 dec2(uint32_t codes, float scale)
-{
-    float2v d;
-    if constexpr (F == 0) d = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, scale, W);
-    else d = __builtin_amdgcn_cvt_scalef32_pk_f32_bf8(codes, scale, W);
-    return make_float2(d.x, d.y);
-}
-
-__device__ __forceinline__ float amax2(float a, float2 v) { return fmaxf(a, fmaxf(fabsf(v.x), fabsf(v.y))); }
-
-// MX-encode a group of values sharing one block exponent, in place:
-// v <- Q(v / 2^E) * 2^E with E from the group maximum.  Returns E.
-template <int F, int CNT>
-__device__ __forceinline__ int mx_requant(float2* v)
-{
-    float am = 0.f;
-    sfor<CNT>([&](auto T) { am = amax2(am, v[T]); });
-    const int E = mxd::block_exp<F>(__float_as_uint(am));
-    const float s = e8(E), lim = lim_of<F>(E);
-    sfor<CNT>([&](auto T) {
-        const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(v[T].x, -lim, lim),
-                                          __builtin_amdgcn_fmed3f(v[T].y, -lim, lim), s);
-        v[T] = dec2<F, false>(c, s);
-    });
-    return E;
-}
-
-struct Tw {
-    const float2* tw;      // stage s = b+1, index j at [2^b + j]
-    const int32_t* ex;     // twiddle block exponents
-    const int32_t* off;    // per stage s: offset into ex
-};
-
-// ---------------------------------------------------------------------------
-// one radix-2 stage (butterfly position bit B) in layout K
-// ---------------------------------------------------------------------------
-template <int F, int C, int K, int B, bool INV>
-__device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
-{
-    using Ly = Lay<C>;
-    constexpr int ob = Ly::index_of(K, B);
-    static_assert(ob >= 0, "butterfly bit must be in-lane");
-    constexpr int h = 1 << B;
-    constexpr int CB = 1 << C;
-    constexpr int fbb = (B > C) ? B : C;
-    constexpr int obb = Ly::index_of(K, fbb);
-    static_assert(obb >= 0, "block must be in-lane");
-    constexpr int FREE = (CB - 1) | (1 << obb);        // in-lane bits of one block
-    constexpr int BFLY = FREE & ~(1 << ob);            // bits enumerating its butterflies
-    constexpr int OTHER = (P - 1) & ~FREE;             // bits enumerating blocks
-    constexpr int NBLK = P / (2 * CB);
-    const int jm = posM<C, K>(m) & (h - 1);           // lane part of j
-
-    sfor<NBLK>([&](auto BLK) {
-        constexpr int base = deposit(BLK, OTHER);
-        float2 U[CB], V[CB];
-        sfor<CB>([&](auto T) {
-            constexpr int ou = base | deposit(T, BFLY);
-            U[T] = a[ou];
-            V[T] = a[ou | (1 << ob)];
-        });
-        if constexpr (F == FP32) {
-            sfor<CB>([&](auto T) {
-                constexpr int ou = base | deposit(T, BFLY);
-                constexpr int jc = Ly::posF(K, ou) & (h - 1);
-                const float2 w = t.tw[h + (jm | jc)];
-                const float wi = INV ? -w.y : w.y;
-                const float pr = w.x * V[T].x - wi * V[T].y;
-                const float pi = w.x * V[T].y + wi * V[T].x;
-                a[ou] = make_float2(U[T].x + pr, U[T].y + pi);
-                a[ou | (1 << ob)] = make_float2(U[T].x - pr, U[T].y - pi);
-            });
-        } else if constexpr (B <= 1) {
-            // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
-            // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
-            float am = 0.f;
-            sfor<CB>([&](auto T) { am = amax2(am, V[T]); });
-            const int Ev = mxd::block_exp<F>(__float_as_uint(am));
-            const float s = e8(Ev), lim = lim_of<F>(Ev);
-            sfor<CB>([&](auto T) {
-                constexpr int ou = base | deposit(T, BFLY);
-                constexpr int jc = Ly::posF(K, ou) & (h - 1);
-                const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(V[T].x, -lim, lim),
-                                                  __builtin_amdgcn_fmed3f(V[T].y, -lim, lim), s);
-                float2 w = dec2<F, false>(c, s);
-                if constexpr (jc == 1) w = INV ? make_float2(-w.y, w.x) : make_float2(w.y, -w.x);
-                a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
-                a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
-            });
-        } else {
-            constexpr int jc0 = Ly::posF(K, base) & (h - 1);
-            const int Ew = t.ex[t.off[B + 1] + ((CB <= h) ? ((jm | jc0) >> C) : 0)];
-            // operand v: EncodeBlockMX, element values as FP32 mantissas
-            float am = 0.f;
-            sfor<CB>([&](auto T) { am = amax2(am, V[T]); });
-            const int Ev = mxd::block_exp<F>(__float_as_uint(am));
-            const float s = e8(Ev), lim = lim_of<F>(Ev);
-            float2 Pp[CB];
-            sfor<CB>([&](auto T) {
-                constexpr int ou = base | deposit(T, BFLY);
-                constexpr int jc = Ly::posF(K, ou) & (h - 1);
-                const float2 x = t.tw[h + (jm | jc)];
-                const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(V[T].x, -lim, lim),
-                                                  __builtin_amdgcn_fmed3f(V[T].y, -lim, lim), s);
-                const float2 y = dec2<F, false>(c, 1.0f);
-                const float xi = INV ? -x.y : x.y;
-                // products of 8-bit elements are exact: one rounding per component
-                Pp[T].x = x.x * y.x - xi * y.y;
-                Pp[T].y = x.x * y.y + xi * y.x;
-            });
-            float ap = 0.f;
-            sfor<CB>([&](auto T) { ap = amax2(ap, Pp[T]); });
-            const int kr = mxd::renorm_exp<F>(__float_as_uint(ap));
-            const float sp = e8(kr);
-            const int Eo = Ew + Ev + kr;
-            if (__builtin_expect(Eo >= -127, 1)) {
-                const float so = e8(Eo);
-                sfor<CB>([&](auto T) {
-                    constexpr int ou = base | deposit(T, BFLY);
-                    const uint32_t c = enc2<F, false>(0u, Pp[T].x, Pp[T].y, sp);
-                    const float2 w = dec2<F, false>(c, so);
-                    a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
-                    a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
-                });
-            } else {
-                // product scale below the E8M0 range: decode the elements and
-                // apply 2^Eo with ldexp (correctly rounded, subnormals kept)
-                sfor<CB>([&](auto T) {
-                    constexpr int ou = base | deposit(T, BFLY);
-                    const uint32_t c = enc2<F, false>(0u, Pp[T].x, Pp[T].y, sp);
-                    const float2 q = dec2<F, false>(c, 1.0f);
-                    const float2 w = make_float2(ldexpf(q.x, Eo), ldexpf(q.y, Eo));
-                    a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
-                    a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
-                });
-            }
-        }
-    });
-}
-
-// all stages of layout K
-template <int F, int C, int K, bool INV>
-__device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t)
-{
-    constexpr int b0 = Lay<C>::bfirst(K), b1 = Lay<C>::blast(K);
-    sfor<b1 - b0>([&](auto I) { stage<F, C, K, b0 + I, INV>(a, m, t); });
-}
-
-// Layout K -> K+1 through this wave's LDS planes (re, then im).
-template <int C, int K>
-__device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
-{
-    using Ly = Lay<C>;
-    const int pm0 = posM<C, K>(m), pm1 = posM<C, K + 1>(m);
-    sfor<2>([&](auto R) {
-        wave_sync();
-        sfor<P / 2>([&](auto I) {
-            constexpr int o = 2 * I;
-            const int p = Ly::posF(K, o) | pm0;
-            const float2 v = R ? make_float2(a[o].y, a[o + 1].y) : make_float2(a[o].x, a[o + 1].x);
-            *(float2*)&plane[swz(p)] = v;
-        });
-        wave_sync();
-        sfor<P / 2>([&](auto I) {
-            constexpr int o = 2 * I;
-            const int p = Ly::posF(K + 1, o) | pm1;
-            const float2 v = *(const float2*)&plane[swz(p)];
-            if (R) { a[o].y = v.x; a[o + 1].y = v.y; }
-            else { a[o].x = v.x; a[o + 1].x = v.y; }
-        });
-    });
-}
-
-template <int F, int C, bool INV>
-__device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane)
-{
-    using Ly = Lay<C>;
-    sfor<Ly::NL>([&](auto K) {
-        if constexpr (K > 0) exchange<C, K - 1>(a, m, plane);
-        stages<F, C, K, INV>(a, m, t);
-    });
-}
-
-// ---------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------
-
-struct FastArgs {
-    const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
-    float2* dst;             // complex64 output (row pass FP32 form / column pass)
-    uint32_t* codes;         // MX intermediate: [slice][cg][row][cb] code pairs (2 bytes each)
-    uint8_t* exps;           // MX intermediate: [slice][cg][c][row block] E8M0 bytes
-    const int32_t* kp;       // per-slice prescale exponent or nullptr
-    int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
-    int32_t kin_mul, kout_mul, kout_add;
-    const float2* tw;
-    const int32_t* tw_exp;
-    int32_t tw_off[16];
-};
-
-__device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
-{
-    int k = g.kp ? g.kp[slice] : 0;
-    return k == INT32_MIN ? 0 : k;
-}
-
-// Row pass. F: 0 E4M3, 1 E5M2, 4 FP32.  C: log2 of complex values per MX block.
-template <int F, int C, bool INV>
-__global__ __launch_bounds__(256) void k_row(FastArgs g)
-{
-    __shared__ float s_plane[WAVES][LPW * N];     // per-wave exchange planes (32 KiB)
-    __shared__ uint32_t s_colmax[(C >= 1 ? LINES >> C : 1) * N];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int line = lane >> 4, m = lane & 15;
-    const int slice = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
-    const int row = rb * LINES + wave * LPW + line;
-    const int kp = slice_k(g, slice);
-    const int kin = g.kin_mul * kp;
-    if (g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
-    const float2* x = g.src + ((size_t)slice * N + row) * N;
-    float* plane = s_plane[wave] + line * N;
-    const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
-    Tw t{g.tw, g.tw_exp, g.tw_off};
-    float2 a[P];
-
-    if constexpr (F == FP32) {
-        // layout 0 directly: natural 16k + rev4(m) -> offset rev5(k)
-        sfor<P>([&](auto Kk) {
-            float2 v = x[16 * Kk + rm];
-            a[rev(Kk, 5)] = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
-        });
-    } else {
-        // 32 consecutive naturals per lane: MX-encode the pass input in-lane
-        float2 v[P];
-        const float4* x4 = (const float4*)(x + P * m);
-        sfor<P / 2>([&](auto I) {
-            const float4 q = x4[I];
-            v[2 * I] = make_float2(ldexpf(q.x, kin), ldexpf(q.y, kin));
-            v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
-        });
-        constexpr int CB = 1 << C;
-        sfor<P / CB>([&](auto G) { mx_requant<F, CB>(v + G * CB); });
-        // bit reversal into layout 0 through the LDS planes
-        sfor<2>([&](auto R) {
-            wave_sync();
-            // natural 32m + i sits at position rev5(i) * 16 + rev4(m)
-            sfor<P>([&](auto I) { plane[swz((rev(I, 5) << 4) | rm)] = R ? v[I].y : v[I].x; });
-            wave_sync();
-            sfor<P / 2>([&](auto I) {
-                const float2 q = *(const float2*)&plane[swz(P * m + 2 * I)];
-                if (R) { a[2 * I].y = q.x; a[2 * I + 1].y = q.y; }
-                else { a[2 * I].x = q.x; a[2 * I + 1].x = q.y; }
-            });
-        });
-    }
-
-    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane);
-
-    constexpr int CL = (F == FP32) ? 1 : C;
-    constexpr int KL = Lay<CL>::NL - 1;
-    const int pmL = posM<CL, KL>(m);
-    if constexpr (F == FP32) {
-        float2* y = g.dst + ((size_t)slice * N + row) * N;
-        sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
-    } else {
-        // column MX encode: blocks of CB consecutive rows (NSB of them in this work-group)
-        constexpr int CB = 1 << C;
-        constexpr int NSB = LINES / CB;
-        const int sb = (wave * LPW + line) / CB;          // this row's block within the work-group
-        for (int i = tid; i < NSB * N; i += 256) s_colmax[i] = 0;
-        __syncthreads();
-        sfor<P>([&](auto O) {
-            atomicMax(&s_colmax[sb * N + (Lay<C>::posF(KL, O) | pmL)],
-                      __float_as_uint(fmaxf(fabsf(a[O].x), fabsf(a[O].y))));
-        });
-        __syncthreads();
-        // one exponent per (row block, column): scale and clamp into the (now free) planes
-        float* s_scale = &s_plane[0][0];
-        float* s_lim = s_scale + NSB * N;
-        uint8_t* ex = g.exps + (size_t)slice * N * (N / CB);
-        for (int i = tid; i < NSB * N; i += 256) {
-            const int c = i % N, b = i / N;
-            const int E = mxd::block_exp<F>(s_colmax[i]);
-            s_scale[i] = e8(E);
-            s_lim[i] = lim_of<F>(E);
-            ex[(size_t)c * (N / CB) + rb * NSB + b] = (uint8_t)(E + 127);
-        }
-        __syncthreads();
-        const float* my_scale = s_scale + sb * N;
-        const float* my_lim = s_lim + sb * N;
-        uint32_t* cd = g.codes + ((size_t)slice * N * N) / 2;
-        // in-lane column groups: offsets with bits 0..C-1 consecutive columns
-        sfor<P / CB>([&](auto G) {
-            constexpr int o0 = deposit(G, (P - 1) & ~(CB - 1));
-            const int col0 = Lay<C>::posF(KL, o0) | pmL;      // first column of the group
-            uint32_t w[CB / 2 > 0 ? CB / 2 : 1];
-            sfor<CB / 2>([&](auto H) {
-                constexpr int oa = o0 + 2 * H, obx = oa + 1;
-                const int ca = col0 + 2 * H, cbx = ca + 1;
-                const float la = my_lim[ca], lb = my_lim[cbx];
-                uint32_t r = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(a[oa].x, -la, la),
-                                            __builtin_amdgcn_fmed3f(a[oa].y, -la, la), my_scale[ca]);
-                r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x, -lb, lb),
-                                  __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), my_scale[cbx]);
-                w[H] = r;
-            });
-            // [cg][row][cb] with cg = col0 / CB
-            uint32_t* dstw = cd + (((size_t)(col0 / CB) * N + row) * CB) / 2;
-            if constexpr (CB == 16) {
-                ((uint4*)dstw)[0] = make_uint4(w[0], w[1], w[2], w[3]);
-                ((uint4*)dstw)[1] = make_uint4(w[4], w[5], w[6], w[7]);
-            } else if constexpr (CB == 8) {
-                ((uint4*)dstw)[0] = make_uint4(w[0], w[1], w[2], w[3]);
-            } else if constexpr (CB == 4) {
-                ((uint2*)dstw)[0] = make_uint2(w[0], w[1]);
-            } else {
-                dstw[0] = w[0];
-            }
-        });
-    }
-}
-
-// Column pass.
-template <int F, int C, bool INV>
-__global__ __launch_bounds__(256) void k_col(FastArgs g)
-{
-    constexpr int TSTR = 9;                         // LDS words per tile row (8 + pad)
-    __shared__ float s_plane[WAVES][LPW * N];       // 32 KiB: exchange planes, first the code tile
-    __shared__ uint8_t s_ex[LINES * N / 2];         // exponents of the 16 columns (up to N/2 blocks)
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int line = lane >> 4, m = lane & 15;
-    const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
-    const int col = cb16 * LINES + wave * LPW + line;   // this lane's column
-    const int kp = slice_k(g, slice);
-    const int kout = g.kout_mul * kp + g.kout_add;
-    float* plane = s_plane[wave] + line * N;
-    const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
-    Tw t{g.tw, g.tw_exp, g.tw_off};
-    float2 a[P];
-
-    if constexpr (F == FP32) {
-        const float2* x = g.src + (size_t)slice * N * N + col;
-        sfor<P>([&](auto Kk) { a[rev(Kk, 5)] = x[(size_t)(16 * Kk + rm) * N]; });
-    } else {
-        constexpr int CB = 1 << C;
-        constexpr int NRB = N / CB;                 // row blocks per column
-        // code tile of the 16 columns: 16 / CB column groups of [row][CB] pairs
-        uint32_t* tile = (uint32_t*)&s_plane[0][0];
-        const uint32_t* cd = g.codes + ((size_t)slice * N * N + (size_t)cb16 * LINES * N) / 2;
-        for (int i = tid; i < LINES * N / 8; i += 256) {            // 16-byte pieces
-            const uint4 q = ((const uint4*)cd)[i];
-            const int word0 = i * 4;                                // in units of code pairs / 2
-            sfor<4>([&](auto W) {
-                const int pair = 2 * (word0 + W);                  // first code pair of this word
-                const int cgi = pair / (N * CB), rem = pair % (N * CB);
-                const int r = rem / CB, c = cgi * CB + rem % CB;   // row and column (0..15)
-                const uint32_t val = W == 0 ? q.x : W == 1 ? q.y : W == 2 ? q.z : q.w;
-                tile[r * TSTR + c / 2] = val;
-            });
-        }
-        const uint8_t* ex = g.exps + (size_t)slice * N * NRB + (size_t)cb16 * LINES * NRB;
-        for (int i = tid; i < LINES * NRB; i += 256) s_ex[i] = ex[i];
-        __syncthreads();
-        const int cl = col - cb16 * LINES;
-        sfor<P>([&](auto O) {
-            const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
-            const uint32_t wd = tile[n * TSTR + cl / 2];
-            const float s = __uint_as_float((uint32_t)s_ex[cl * NRB + n / CB] << 23);
-            a[O] = (cl & 1) ? dec2<F, true>(wd, s) : dec2<F, false>(wd, s);
-        });
-        __syncthreads();
-    }
-
-    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane);
-
-    constexpr int CL = (F == FP32) ? 1 : C;
-    constexpr int KL = Lay<CL>::NL - 1;
-    const int pmL = posM<CL, KL>(m);
-    float2* y = g.dst + (size_t)slice * N * N + col;
-    sfor<P>([&](auto O) {
-        const int r = Lay<CL>::posF(KL, O) | pmL;
-        y[(size_t)r * N] = make_float2(ldexpf(a[O].x, kout), ldexpf(a[O].y, kout));
-    });
-}
-
-}  // namespace mxf
+// mxfft_fast.hip -- dispatch of the register-resident 512^2 passes.
+#include "mxfft_fast.hpp"
 
 namespace mxk {
+
+hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_fp32(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
 
 bool fast_supported(int mode, int n, int cb)
 {
     if (n != mxf::N) return false;
     if (mode == MODE_FP32) return true;
     return cb >= 2 && cb <= 16;
-}
-
-template <int F, bool INV>
-static hipError_t launch_c(int cb, bool row, const mxf::FastArgs& g, int batch, hipStream_t s)
-{
-    const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
-#define MXF_CASE(CC)                                                                      \
-    if (row) hipLaunchKernelGGL((mxf::k_row<F, CC, INV>), grid, block, 0, s, g);          \
-    else hipLaunchKernelGGL((mxf::k_col<F, CC, INV>), grid, block, 0, s, g);
-    switch (cb) {
-    case 2: MXF_CASE(1) break;
-    case 4: MXF_CASE(2) break;
-    case 8: MXF_CASE(3) break;
-    case 16: MXF_CASE(4) break;
-    default: return hipErrorInvalidValue;
-    }
-#undef MXF_CASE
-    return hipGetLastError();
 }
 
 hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassArgs& p, int batch, hipStream_t s)
@@ -607,21 +29,12 @@ hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassA
     g.tw = p.tw;
     g.tw_exp = p.tw_exp;
     for (int i = 0; i < 16; i++) g.tw_off[i] = p.tw_off[i];
-    const int c = (mode == MODE_FP32) ? 16 : cb;
-    if (mode == MODE_E4M3) return inverse ? launch_c<0, true>(c, row, g, batch, s) : launch_c<0, false>(c, row, g, batch, s);
-    if (mode == MODE_E5M2) return inverse ? launch_c<1, true>(c, row, g, batch, s) : launch_c<1, false>(c, row, g, batch, s);
-    if (mode == MODE_FP32) {
-        const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
-        if (row) {
-            if (inverse) hipLaunchKernelGGL((mxf::k_row<mxf::FP32, 1, true>), grid, block, 0, s, g);
-            else hipLaunchKernelGGL((mxf::k_row<mxf::FP32, 1, false>), grid, block, 0, s, g);
-        } else {
-            if (inverse) hipLaunchKernelGGL((mxf::k_col<mxf::FP32, 1, true>), grid, block, 0, s, g);
-            else hipLaunchKernelGGL((mxf::k_col<mxf::FP32, 1, false>), grid, block, 0, s, g);
-        }
-        return hipGetLastError();
+    switch (mode) {
+    case MODE_E4M3: return launch_fast_e4m3(cb, row, inverse, g, batch, s);
+    case MODE_E5M2: return launch_fast_e5m2(cb, row, inverse, g, batch, s);
+    case MODE_FP32: return launch_fast_fp32(cb, row, inverse, g, batch, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 }  // namespace mxk

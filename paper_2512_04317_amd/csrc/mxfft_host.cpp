@@ -82,7 +82,7 @@ struct mxfft_plan_s {
     float2* d_tw = nullptr;
     int32_t* d_tw_exp = nullptr;
     int32_t tw_exp_off[mxk::kMaxLog2N + 2] = {};
-    mxk::SliceStats* d_ws = nullptr;
+    mxk::StatPart* d_parts = nullptr;
     int32_t* d_kp = nullptr;
     int32_t* d_status = nullptr;
     // register-resident path (n = 512): twiddles at [h + j], MX intermediate
@@ -202,7 +202,7 @@ void release(mxfft_plan_s* pl)
     for (hipEvent_t e : pl->spare) (void)hipEventDestroy(e);
     (void)hipFree(pl->d_tw);
     (void)hipFree(pl->d_tw_exp);
-    (void)hipFree(pl->d_ws);
+    (void)hipFree(pl->d_parts);
     (void)hipFree(pl->d_kp);
     (void)hipFree(pl->d_status);
     (void)hipFree(pl->d_twf);
@@ -301,7 +301,7 @@ mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
     pa.k_min = pl->p.k_min;
     pa.k_max = pl->p.k_max;
     LaunchTimer timer(pl, ROLE_STATS, s);
-    if (mxk::launch_stats((const float2*)in, pl->n, batch, pl->d_ws, pl->d_kp, pl->d_status, pa, s) != hipSuccess)
+    if (mxk::launch_stats((const float2*)in, pl->n, batch, pl->d_parts, pl->d_kp, pl->d_status, pa, s) != hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
 }
@@ -366,7 +366,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw, tw.size(), &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw_exp, tw_exp.size(), &pl->bytes);
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_ws, (size_t)max_batch, &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(&pl->d_parts, mxk::stats_parts(n, max_batch), &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_kp, (size_t)max_batch, &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
@@ -389,7 +389,6 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     ok = ok && hipMemcpyAsync(pl->d_tw_exp, tw_exp.data(), tw_exp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) == hipSuccess;
     if (pl->fast)
         ok = ok && hipMemcpyAsync(pl->d_twf, twf.data(), twf.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemsetAsync(pl->d_ws, 0, sizeof(mxk::SliceStats) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipMemsetAsync(pl->d_status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {

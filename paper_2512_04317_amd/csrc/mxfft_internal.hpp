@@ -11,16 +11,22 @@ constexpr int kMaxLog2N = 12;       // n <= 4096
 constexpr int kStatsBins = 288;     // floor(log2 |x|) + 149, |x| from FP32 parts: 0..276
 constexpr int kBinOffset = 149;
 
-// Per-slice prescale statistics (device workspace; all zero between calls).
-struct alignas(16) SliceStats {
+// Prescale statistics of one chunk of one slice (device workspace, written
+// in full by every call; summed per slice by the finalize kernel).
+struct alignas(16) StatPart {
     uint32_t hist[kStatsBins];      // nonzero |x| per binade floor(log2 |x|)
     unsigned long long max_m2;      // bits of max |x|^2 (FP64, non-negative)
     uint32_t count;                 // nonzero elements
     uint32_t max_comp;              // bits of max(|re|, |im|) (FP32)
     uint32_t nonfinite;             // any Inf/NaN part
-    uint32_t ticket;                // work-groups done
-    uint32_t pad[2];
+    uint32_t pad[3];
 };
+
+// Chunks per slice for a batch: enough work-groups to fill the chip, at
+// least 8192 elements each.
+int stats_chunks(int n, int batch);
+// StatPart entries a plan must hold for batches up to max_batch.
+size_t stats_parts(int n, int max_batch);
 
 // Alg. 1 parameters as the device needs them.
 struct PrescaleArgs {
@@ -70,7 +76,7 @@ struct FastPassArgs {
 bool fast_supported(int mode, int n, int cb);
 hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassArgs& p, int batch, hipStream_t s);
 
-hipError_t launch_stats(const float2* x, int n, int batch, SliceStats* ws, int32_t* kp,
+hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);

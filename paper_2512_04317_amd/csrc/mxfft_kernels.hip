@@ -1,6 +1,7 @@
 // mxfft_kernels.hip -- gfx950 kernels of the MX-scaled mixed-precision 2D FFT.
 //
-//  k_stats : global power-of-two prescale of each slice (Alg. 1), exact.
+//  k_stats_part / k_stats_final : global power-of-two prescale of each slice
+//            (Alg. 1), exact: chunk statistics, then one work-group per slice.
 //  k_lines : one radix-2 decimation-in-time pass over the rows or the columns
 //            of every slice, with per-block MX encoding of the pass input and
 //            the MX-scaled butterfly of Alg. 2 at every stage (or the plain
@@ -37,19 +38,15 @@ __device__ int round_log2_ratio(double T, double a)
     return (l + 1) >> 1;
 }
 
-__global__ __launch_bounds__(256) void k_stats(const float2* __restrict__ x, int nn, int chunk,
-                                                int chunks, SliceStats* __restrict__ wsall,
-                                                int32_t* __restrict__ kp, int32_t* __restrict__ slice_status,
-                                                PrescaleArgs pa)
+// Statistics of one chunk of one slice: binade histogram of |x|, count of
+// nonzero values, max |x|^2, max part, non-finite flag.
+__global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x, int nn, int chunk,
+                                                     int chunks, StatPart* __restrict__ parts)
 {
-#pragma clang fp contract(off)
     __shared__ uint32_t hist[kStatsBins];
-    __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
+    __shared__ unsigned long long s_m2;
     __shared__ uint32_t s_count, s_maxc, s_nonfin;
-    __shared__ int s_last, s_refine, s_bin_lo, s_bin_hi;
-
-    const int tid = threadIdx.x, lane = tid & 63, slice = blockIdx.y;
-    SliceStats* ws = wsall + slice;
+    const int tid = threadIdx.x, slice = blockIdx.y;
     const float2* xs = x + (size_t)slice * nn;
 
     for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
@@ -59,35 +56,42 @@ __global__ __launch_bounds__(256) void k_stats(const float2* __restrict__ x, int
     unsigned long long mm = 0;
     uint32_t cnt = 0, mc = 0, nf = 0;
     const int beg = blockIdx.x * chunk, end = min(beg + chunk, nn);
-    for (int base = beg; base < end; base += blockDim.x) {
-        const int i = base + tid;
-        int bin = -1;
-        if (i < end) {
-            const float2 v = xs[i];
-            const uint32_t br = __float_as_uint(v.x), bi = __float_as_uint(v.y);
-            const uint32_t bad = ((br & 0x7f800000u) == 0x7f800000u) | ((bi & 0x7f800000u) == 0x7f800000u);
-            nf |= bad;
-            mc = max(mc, max(br & 0x7fffffffu, bi & 0x7fffffffu));
-            // |x|^2 in FP64: both squares are exact, the sum is rounded once
-            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
-            if (!bad && m2 > 0.0) {
-                cnt++;
-                mm = max(mm, b);
-                // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (sqrt is monotone and
-                // correctly rounded, so it never crosses a power of two)
-                bin = ((((int)(b >> 52)) - 1023) >> 1) + kBinOffset;
+    // one element: non-finite flag, largest part, |x|^2 in FP64 (both squares
+    // exact, the sum rounded once), count, max and binade histogram of |x|
+    auto elem = [&](float re, float im) {
+        const uint32_t br = __float_as_uint(re), bi = __float_as_uint(im);
+        const uint32_t bad = ((br & 0x7f800000u) == 0x7f800000u) | ((bi & 0x7f800000u) == 0x7f800000u);
+        nf |= bad;
+        mc = max(mc, max(br & 0x7fffffffu, bi & 0x7fffffffu));
+        const double m2 = (double)re * (double)re + (double)im * (double)im;
+        const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+        if (!bad && m2 > 0.0) {
+            cnt++;
+            mm = max(mm, b);
+            // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2): sqrt is monotone and
+            // correctly rounded, so it never crosses a power of two
+            atomicAdd(&hist[((((int)(b >> 52)) - 1023) >> 1) + kBinOffset], 1u);
+        }
+    };
+    if (((end - beg) & 1) == 0 && ((((uintptr_t)(xs + beg)) & 15) == 0)) {
+        // two complex values per 16-byte load, four loads in flight per thread
+        const float4* x4 = (const float4*)(xs + beg);
+        const int nv = (end - beg) >> 1;
+        for (int base = 0; base < nv; base += 4 * (int)blockDim.x) {
+            float4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = base + u * (int)blockDim.x + tid;
+                q[u] = i < nv ? x4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                elem(q[u].x, q[u].y);
+                elem(q[u].z, q[u].w);
             }
         }
-        // histogram update, aggregated over lanes that share a bin
-        unsigned long long act = __ballot(bin >= 0);
-        while (act) {
-            const int leader = __builtin_ctzll(act);
-            const int lb = __shfl(bin, leader, 64);
-            const unsigned long long same = __ballot(bin == lb);
-            if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
-            act &= ~same;
-        }
+    } else {
+        for (int i = beg + tid; i < end; i += blockDim.x) elem(xs[i].x, xs[i].y);
     }
     atomicMax(&s_m2, mm);
     atomicAdd(&s_count, cnt);
@@ -95,30 +99,43 @@ __global__ __launch_bounds__(256) void k_stats(const float2* __restrict__ x, int
     atomicOr(&s_nonfin, nf);
     __syncthreads();
 
-    for (int i = tid; i < kStatsBins; i += blockDim.x)
-        if (hist[i]) atomicAdd(&ws->hist[i], hist[i]);
+    StatPart* pt = parts + (size_t)slice * chunks + blockIdx.x;
+    for (int i = tid; i < kStatsBins; i += blockDim.x) pt->hist[i] = hist[i];
     if (tid == 0) {
-        atomicMax(&ws->max_m2, s_m2);
-        atomicAdd(&ws->count, s_count);
-        atomicMax(&ws->max_comp, s_maxc);
-        atomicOr(&ws->nonfinite, s_nonfin);
+        pt->max_m2 = s_m2;
+        pt->count = s_count;
+        pt->max_comp = s_maxc;
+        pt->nonfinite = s_nonfin;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&ws->ticket, 1u) == (uint32_t)(chunks - 1));
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
 
-    // ---- the last work-group of the slice computes k ----
-    for (int i = tid; i < kStatsBins; i += blockDim.x)
-        hist[i] = __hip_atomic_load(&ws->hist[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (tid == 0) {
-        s_m2 = __hip_atomic_load(&ws->max_m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_count = __hip_atomic_load(&ws->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_maxc = __hip_atomic_load(&ws->max_comp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_nonfin = __hip_atomic_load(&ws->nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_refine = 0;
+// Alg. 1 for one slice from its chunk statistics (one work-group per slice).
+__global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ x, int nn, int chunks,
+                                                      const StatPart* __restrict__ parts,
+                                                      int32_t* __restrict__ kp, int32_t* __restrict__ slice_status,
+                                                      PrescaleArgs pa)
+{
+#pragma clang fp contract(off)
+    __shared__ uint32_t hist[kStatsBins];
+    __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
+    __shared__ uint32_t s_count, s_maxc, s_nonfin;
+    __shared__ int s_refine, s_bin_lo, s_bin_hi;
+    const int tid = threadIdx.x, slice = blockIdx.x;
+    const float2* xs = x + (size_t)slice * nn;
+    const StatPart* pt = parts + (size_t)slice * chunks;
+
+    if (tid == 0) { s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0; }
+    __syncthreads();
+    for (int i = tid; i < kStatsBins; i += blockDim.x) {
+        uint32_t h = 0;
+        for (int c = 0; c < chunks; c++) h += pt[c].hist[i];
+        hist[i] = h;
+    }
+    for (int c = tid; c < chunks; c += blockDim.x) {
+        atomicMax(&s_m2, pt[c].max_m2);
+        atomicAdd(&s_count, pt[c].count);
+        atomicMax(&s_maxc, pt[c].max_comp);
+        atomicOr(&s_nonfin, pt[c].nonfinite);
     }
     __syncthreads();
 
@@ -193,26 +210,35 @@ __global__ __launch_bounds__(256) void k_stats(const float2* __restrict__ x, int
         kp[slice] = st ? INT32_MIN : k;
         slice_status[slice] = st;
     }
-    // leave the workspace zeroed for the next call
-    for (int i = tid; i < kStatsBins; i += blockDim.x) ws->hist[i] = 0;
-    if (tid == 0) {
-        ws->max_m2 = 0;
-        ws->count = 0;
-        ws->max_comp = 0;
-        ws->nonfinite = 0;
-        ws->ticket = 0;
-    }
 }
 
-hipError_t launch_stats(const float2* x, int n, int batch, SliceStats* ws, int32_t* kp,
+int stats_chunks(int n, int batch)
+{
+    const long nn = (long)n * n;
+    long want = (4096 + batch - 1) / batch;       // work-groups per slice to fill the chip
+    const long most = nn / 8192;                  // at least 8192 elements per chunk
+    if (want > most) want = most;
+    if (want < 1) want = 1;
+    long c = 1;
+    while (c * 2 <= want) c *= 2;                 // a power of two divides n^2
+    return (int)c;
+}
+
+size_t stats_parts(int n, int max_batch)
+{
+    (void)n;
+    return (size_t)max_batch + 4096;              // batch * chunks <= batch + 4096
+}
+
+hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s)
 {
     const int nn = n * n;
-    int chunks = nn / 16384;
-    if (chunks < 1) chunks = 1;
-    const int chunk = nn / chunks;
-    hipLaunchKernelGGL(k_stats, dim3(chunks, batch), dim3(256), 0, s, x, nn, chunk, chunks, ws, kp,
-                       slice_status, pa);
+    const int chunks = stats_chunks(n, batch);
+    hipLaunchKernelGGL(k_stats_part, dim3(chunks, batch), dim3(256), 0, s, x, nn, nn / chunks, chunks, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, nn, chunks, parts, kp, slice_status, pa);
     return hipGetLastError();
 }
 
