@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32, help="slices the CPU oracle transforms")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of the input (known bytes) to scale HBM counters")
     return ap.parse_args()
 
 
@@ -86,6 +88,11 @@ def main():
     xd = torch.from_numpy(x).cuda()
     out = torch.empty_like(xd)
     kout = torch.empty(batch, dtype=torch.int32, device=xd.device)
+
+    if args.copy_calibration:
+        # a plain copy of the whole input: reads and writes exactly batch * N * N * 8 bytes
+        out.copy_(xd)
+        torch.cuda.synchronize()
 
     plan = mxfft.Plan(N, batch, fmt=args.fmt, block=args.block)
     fwd = lambda: plan.forward(xd, out=out, k_out=kout)   # noqa: E731

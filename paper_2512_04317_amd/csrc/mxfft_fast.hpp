@@ -188,21 +188,66 @@ __device__ __forceinline__ float2 dec2(uint32_t codes, float scale)
     return make_float2(d.x, d.y);
 }
 
-__device__ __forceinline__ float amax2(float a, float2 v) { return fmaxf(a, fmaxf(fabsf(v.x), fabsf(v.y))); }
+// max(a, |v.x|, |v.y|) for a >= 0 in one v_max3_f32 (abs source modifiers)
+__device__ __forceinline__ float amax2(float a, float2 v)
+{
+    float r;
+    asm("v_max3_f32 %0, %1, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(v.x), "v"(v.y));
+    return r;
+}
+
+// largest |component| of CNT complex values: chains of v_max3_f32, four per
+// asm statement (the compiler separates asm statements with wait states)
+template <int CNT>
+__device__ __forceinline__ float amax_of(const float2* v)
+{
+    float a = 0.f;
+    if constexpr (CNT % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < CNT / 4; g++) {
+            const float2 p = v[4 * g], q = v[4 * g + 1], r = v[4 * g + 2], t = v[4 * g + 3];
+            asm("v_max3_f32 %0, %0, |%1|, |%2|\n\t"
+                "v_max3_f32 %0, %0, |%3|, |%4|\n\t"
+                "v_max3_f32 %0, %0, |%5|, |%6|\n\t"
+                "v_max3_f32 %0, %0, |%7|, |%8|"
+                : "+v"(a)
+                : "v"(p.x), "v"(p.y), "v"(q.x), "v"(q.y), "v"(r.x), "v"(r.y), "v"(t.x), "v"(t.y));
+        }
+    } else {
+        sfor<CNT>([&](auto T) { a = amax2(a, v[T]); });
+    }
+    return a;
+}
+
+// Codes of two complex values (each re, im) in the low and high halves of one
+// register.  The first conversion's destination starts as the bits of its own
+// first operand (dead afterwards), so no register needs clearing.
+template <int F>
+__device__ __forceinline__ uint32_t enc4(float2 v0, float2 v1, float scale)
+{
+    const uint32_t c = enc2<F, false>(__float_as_uint(v0.x), v0.x, v0.y, scale);
+    return enc2<F, true>(c, v1.x, v1.y, scale);
+}
+
+// v clamped to +-lim (the saturation of the element format at scale lim / MAXV)
+__device__ __forceinline__ float2 clamp2(float2 v, float lim)
+{
+    return make_float2(__builtin_amdgcn_fmed3f(v.x, -lim, lim), __builtin_amdgcn_fmed3f(v.y, -lim, lim));
+}
 
 // MX-encode a group of values sharing one block exponent, in place:
 // v <- Q(v / 2^E) * 2^E with E from the group maximum.  Returns E.
 template <int F, int CNT>
 __device__ __forceinline__ int mx_requant(float2* v)
 {
-    float am = 0.f;
-    sfor<CNT>([&](auto T) { am = amax2(am, v[T]); });
+    const float am = amax_of<CNT>(v);
     const int E = mxd::block_exp<F>(__float_as_uint(am));
     const float s = e8(E), lim = lim_of<F>(E);
-    sfor<CNT>([&](auto T) {
-        const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(v[T].x, -lim, lim),
-                                          __builtin_amdgcn_fmed3f(v[T].y, -lim, lim), s);
-        v[T] = dec2<F, false>(c, s);
+    uint32_t c[CNT / 2];
+    sfor<CNT / 2>([&](auto H) { c[H] = enc4<F>(clamp2(v[2 * H], lim), clamp2(v[2 * H + 1], lim), s); });
+    sfor<CNT / 2>([&](auto H) {
+        v[2 * H] = dec2<F, false>(c[H], s);
+        v[2 * H + 1] = dec2<F, true>(c[H], s);
     });
     return E;
 }
@@ -255,16 +300,15 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
         } else if constexpr (B <= 1) {
             // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
             // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
-            float am = 0.f;
-            sfor<CB>([&](auto T) { am = amax2(am, V[T]); });
+            const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
             const float s = e8(Ev), lim = lim_of<F>(Ev);
+            uint32_t c[CB / 2];
+            sfor<CB / 2>([&](auto H) { c[H] = enc4<F>(clamp2(V[2 * H], lim), clamp2(V[2 * H + 1], lim), s); });
             sfor<CB>([&](auto T) {
                 constexpr int ou = base | deposit(T, BFLY);
                 constexpr int jc = Ly::posF(K, ou) & (h - 1);
-                const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(V[T].x, -lim, lim),
-                                                  __builtin_amdgcn_fmed3f(V[T].y, -lim, lim), s);
-                float2 w = dec2<F, false>(c, s);
+                float2 w = dec2<F, (T & 1) == 1>(c[T / 2], s);
                 if constexpr (jc == 1) w = INV ? make_float2(-w.y, w.x) : make_float2(w.y, -w.x);
                 a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
                 a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
@@ -273,34 +317,33 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
             constexpr int jc0 = Ly::posF(K, base) & (h - 1);
             const int Ew = t.ex[t.off[B + 1] + ((CB <= h) ? ((jm | jc0) >> C) : 0)];
             // operand v: EncodeBlockMX, element values as FP32 mantissas
-            float am = 0.f;
-            sfor<CB>([&](auto T) { am = amax2(am, V[T]); });
+            const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
             const float s = e8(Ev), lim = lim_of<F>(Ev);
             float2 Pp[CB];
+            uint32_t cv[CB / 2];
+            sfor<CB / 2>([&](auto H) { cv[H] = enc4<F>(clamp2(V[2 * H], lim), clamp2(V[2 * H + 1], lim), s); });
             sfor<CB>([&](auto T) {
                 constexpr int ou = base | deposit(T, BFLY);
                 constexpr int jc = Ly::posF(K, ou) & (h - 1);
                 const float2 x = t.tw[h + (jm | jc)];
-                const uint32_t c = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(V[T].x, -lim, lim),
-                                                  __builtin_amdgcn_fmed3f(V[T].y, -lim, lim), s);
-                const float2 y = dec2<F, false>(c, 1.0f);
+                const float2 y = dec2<F, (T & 1) == 1>(cv[T / 2], 1.0f);
                 const float xi = INV ? -x.y : x.y;
                 // products of 8-bit elements are exact: one rounding per component
                 Pp[T].x = x.x * y.x - xi * y.y;
                 Pp[T].y = x.x * y.y + xi * y.x;
             });
-            float ap = 0.f;
-            sfor<CB>([&](auto T) { ap = amax2(ap, Pp[T]); });
+            const float ap = amax_of<CB>(Pp);
             const int kr = mxd::renorm_exp<F>(__float_as_uint(ap));
             const float sp = e8(kr);
             const int Eo = Ew + Ev + kr;
             if (__builtin_expect(Eo >= -127, 1)) {
                 const float so = e8(Eo);
+                uint32_t cp[CB / 2];
+                sfor<CB / 2>([&](auto H) { cp[H] = enc4<F>(Pp[2 * H], Pp[2 * H + 1], sp); });
                 sfor<CB>([&](auto T) {
                     constexpr int ou = base | deposit(T, BFLY);
-                    const uint32_t c = enc2<F, false>(0u, Pp[T].x, Pp[T].y, sp);
-                    const float2 w = dec2<F, false>(c, so);
+                    const float2 w = dec2<F, (T & 1) == 1>(cp[T / 2], so);
                     a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
                     a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
                 });
@@ -309,7 +352,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
                 // apply 2^Eo with ldexp (correctly rounded, subnormals kept)
                 sfor<CB>([&](auto T) {
                     constexpr int ou = base | deposit(T, BFLY);
-                    const uint32_t c = enc2<F, false>(0u, Pp[T].x, Pp[T].y, sp);
+                    const uint32_t c = enc2<F, false>(__float_as_uint(Pp[T].x), Pp[T].x, Pp[T].y, sp);
                     const float2 q = dec2<F, false>(c, 1.0f);
                     const float2 w = make_float2(ldexpf(q.x, Eo), ldexpf(q.y, Eo));
                     a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
@@ -480,7 +523,8 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
                 constexpr int oa = o0 + 2 * H, obx = oa + 1;
                 const int ca = col0 + 2 * H, cbx = ca + 1;
                 const float la = my_lim[ca], lb = my_lim[cbx];
-                uint32_t r = enc2<F, false>(0u, __builtin_amdgcn_fmed3f(a[oa].x, -la, la),
+                const float ra = __builtin_amdgcn_fmed3f(a[oa].x, -la, la);
+                uint32_t r = enc2<F, false>(__float_as_uint(ra), ra,
                                             __builtin_amdgcn_fmed3f(a[oa].y, -la, la), my_scale[ca]);
                 r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x, -lb, lb),
                                   __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), my_scale[cbx]);
