@@ -132,16 +132,62 @@ __device__ __forceinline__ int posM(int m)
     return p;
 }
 
-// LDS plane index of position p of a line: bits 1..4 XOR a function of bits
-// 5..8 chosen so that, with blocks of 16 butterflies, the 16 lanes of a line
-// hit 16 distinct bank pairs in every layout (other block sizes may see 2-way
-// conflicts); bit 0 is kept so pairs stay adjacent.
+// LDS plane index of position p of a line: bits 1..4 XOR a linear function of
+// bits 5..8, chosen so that in every layout of every block size the 16 lanes
+// of a line reach 16 distinct 8-byte banks with their 64-bit accesses (the LDS
+// serves 64- and 128-bit accesses from 32 banks of 8 bytes, 32-bit ones from
+// 32 banks of 4 bytes); bit 0 is kept so pairs stay adjacent.  Lines sit
+// XLINE words apart (32 words = 16 banks of padding), so the 4 lines of a wave
+// fill all 32 banks twice: conflict-free.
 __device__ __forceinline__ int swz(int p)
 {
     const int b5 = (p >> 5) & 1, b6 = (p >> 6) & 1, b7 = (p >> 7) & 1, b8 = (p >> 8) & 1;
-    const int s = (b5 ^ b8) | ((b6 ^ b8) << 1) | ((b7 ^ b8) << 2) | (b8 << 3);
+    const int s = (b5 ^ b8) | ((b6 ^ b7) << 1) | ((b7 ^ b8) << 2) | (b8 << 3);
     return p ^ (s << 1);
 }
+
+constexpr int XLINE = N + 32;            // words per line in the layout exchanges
+constexpr int RLINE = N + 16;            // words per line in the 32-bit bit-reversal stores
+constexpr int WPL = 3 * XLINE + N;       // words of one wave's planes (covers both)
+
+// pext: the bits of v at the set positions of MASK, packed from bit 0
+template <int MASK>
+__device__ __forceinline__ int pext(int v)
+{
+    int r = 0, q = 0;
+    sfor<LOGN>([&](auto B) {
+        if constexpr ((MASK >> B) & 1) { r |= ((v >> B) & 1) << q; q++; }
+    });
+    return r;
+}
+
+// position bits held by the lanes (not in-lane) in layout K
+template <int C, int K>
+constexpr int lane_mask()
+{
+    int mk = 0;
+    for (int q = 0; q < LOGN - 5; q++) mk |= 1 << Lay<C>::xbit(K, q);
+    return mk;
+}
+
+// Slot (in float2) of row r (0..255), column c (0..15) of a 256 x 16 complex
+// tile written by lanes whose rows differ in the bits LM (4 bits; x are those
+// bits of r): row bit 0 flips with x bit 0 (unless bit 0 is itself a lane
+// bit) and column bits 2..3 XOR x bits 1..2, so one 64-bit store by a wave
+// (4 columns x 16 rows) hits every 8-byte bank exactly twice, while a row of
+// the tile stays one contiguous 128-byte run with column pairs kept adjacent.
+template <int LM>
+__device__ __forceinline__ int tslot(int r, int c)
+{
+    const int x = pext<LM>(r);
+    const int R = (LM & 1) ? r : (r ^ (x & 1));
+    return R * 16 + (c ^ (((x >> 1) & 3) << 2));
+}
+
+// Column slot in the [row][512] maximum and [block][512] scale arrays of the
+// row pass: bits 2..5 XOR bits 4..7, so the 16 lanes of a line (16 different
+// 4-column groups in every final layout) cover all banks.
+__device__ __forceinline__ int csw(int c) { return c ^ (((c >> 4) & 15) << 2); }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -396,6 +442,7 @@ __device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
     });
 }
 
+// plane: this line's exchange plane (XLINE words apart per line)
 template <int F, int C, bool INV>
 __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane)
 {
@@ -414,7 +461,7 @@ struct FastArgs {
     const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
     float2* dst;             // complex64 output (row pass FP32 form / column pass)
     uint32_t* codes;         // MX intermediate: [slice][cg][row][cb] code pairs (2 bytes each)
-    uint8_t* exps;           // MX intermediate: [slice][cg][c][row block] E8M0 bytes
+    uint8_t* exps;           // MX intermediate: [slice][row block][column] E8M0 bytes
     const int32_t* kp;       // per-slice prescale exponent or nullptr
     int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
     int32_t kin_mul, kout_mul, kout_add;
@@ -433,17 +480,20 @@ __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
 template <int F, int C, bool INV>
 __global__ __launch_bounds__(256) void k_row(FastArgs g)
 {
-    __shared__ float s_plane[WAVES][LPW * N];     // per-wave exchange planes (32 KiB)
-    __shared__ uint32_t s_colmax[(C >= 1 ? LINES >> C : 1) * N];
+    constexpr int CB = 1 << C;
+    constexpr int NSB = (F == FP32) ? 1 : LINES / CB;     // column blocks (of CB rows) per work-group
+    __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; then column maxima
+    __shared__ __align__(16) float s_sc[NSB * N];         // column block scales 2^E (MX)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int line = lane >> 4, m = lane & 15;
     const int slice = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
-    const int row = rb * LINES + wave * LPW + line;
+    const int rl = wave * LPW + line;                     // row within the work-group
+    const int row = rb * LINES + rl;
     const int kp = slice_k(g, slice);
     const int kin = g.kin_mul * kp;
     if (g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
     const float2* x = g.src + ((size_t)slice * N + row) * N;
-    float* plane = s_plane[wave] + line * N;
+    float* plane = s_plane + wave * WPL + line * XLINE;
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
@@ -463,16 +513,17 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
             v[2 * I] = make_float2(ldexpf(q.x, kin), ldexpf(q.y, kin));
             v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
         });
-        constexpr int CB = 1 << C;
         sfor<P / CB>([&](auto G) { mx_requant<F, CB>(v + G * CB); });
-        // bit reversal into layout 0 through the LDS planes
+        // bit reversal into layout 0 through the LDS planes (32-bit stores:
+        // lines RLINE words apart)
+        float* rplane = s_plane + wave * WPL + line * RLINE;
         sfor<2>([&](auto R) {
             wave_sync();
             // natural 32m + i sits at position rev5(i) * 16 + rev4(m)
-            sfor<P>([&](auto I) { plane[swz((rev(I, 5) << 4) | rm)] = R ? v[I].y : v[I].x; });
+            sfor<P>([&](auto I) { rplane[swz((rev(I, 5) << 4) | rm)] = R ? v[I].y : v[I].x; });
             wave_sync();
             sfor<P / 2>([&](auto I) {
-                const float2 q = *(const float2*)&plane[swz(P * m + 2 * I)];
+                const float2 q = *(const float2*)&rplane[swz(P * m + 2 * I)];
                 if (R) { a[2 * I].y = q.x; a[2 * I + 1].y = q.y; }
                 else { a[2 * I].x = q.x; a[2 * I + 1].x = q.y; }
             });
@@ -488,46 +539,70 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
         float2* y = g.dst + ((size_t)slice * N + row) * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
     } else {
-        // column MX encode: blocks of CB consecutive rows (NSB of them in this work-group)
-        constexpr int CB = 1 << C;
-        constexpr int NSB = LINES / CB;
-        const int sb = (wave * LPW + line) / CB;          // this row's block within the work-group
-        for (int i = tid; i < NSB * N; i += 256) s_colmax[i] = 0;
-        __syncthreads();
-        sfor<P>([&](auto O) {
-            atomicMax(&s_colmax[sb * N + (Lay<C>::posF(KL, O) | pmL)],
-                      __float_as_uint(fmaxf(fabsf(a[O].x), fabsf(a[O].y))));
+        // Column MX encode of the next pass's input: blocks of CB consecutive
+        // rows of one column; this work-group holds NSB such blocks.
+        // 1. per-element max(|re|, |im|) into a [16][512] array (column-swizzled);
+        //    VW consecutive columns per lane are in-lane offset bits 0..log2(VW)-1
+        constexpr int VW = (C >= 2) ? 4 : 2;
+        float* s_m = s_plane;
+        __syncthreads();                                   // every wave is done with its planes
+        sfor<P / VW>([&](auto G) {
+            constexpr int o0 = deposit(G, (P - 1) & ~(VW - 1));
+            const int c0 = Lay<C>::posF(KL, o0) | pmL;
+            float mv[VW];
+            sfor<VW>([&](auto J) { mv[J] = fmaxf(fabsf(a[o0 + J].x), fabsf(a[o0 + J].y)); });
+            float* d = &s_m[rl * N + csw(c0)];
+            if constexpr (VW == 4) *(float4*)d = make_float4(mv[0], mv[1], mv[2], mv[3]);
+            else *(float2*)d = make_float2(mv[0], mv[1]);
         });
         __syncthreads();
-        // one exponent per (row block, column): scale and clamp into the (now free) planes
-        float* s_scale = &s_plane[0][0];
-        float* s_lim = s_scale + NSB * N;
-        uint8_t* ex = g.exps + (size_t)slice * N * (N / CB);
-        for (int i = tid; i < NSB * N; i += 256) {
-            const int c = i % N, b = i / N;
-            const int E = mxd::block_exp<F>(s_colmax[i]);
-            s_scale[i] = e8(E);
-            s_lim[i] = lim_of<F>(E);
-            ex[(size_t)c * (N / CB) + rb * NSB + b] = (uint8_t)(E + 127);
+        // 2. one thread per column pair: block exponents -> E8M0 bytes (global,
+        //    [slice][row block][column]) and scales 2^E (LDS)
+        {
+            const int c2 = 2 * tid;
+            uint8_t* ex = g.exps + (size_t)slice * (N / CB) * N + (size_t)rb * NSB * N;
+            sfor<NSB>([&](auto B) {
+                float m0 = 0.f, m1 = 0.f;
+                sfor<CB>([&](auto Rr) {
+                    const float2 v = *(const float2*)&s_m[(B * CB + Rr) * N + csw(c2)];
+                    m0 = fmaxf(m0, v.x);
+                    m1 = fmaxf(m1, v.y);
+                });
+                const int E0 = mxd::block_exp<F>(__float_as_uint(m0)), E1 = mxd::block_exp<F>(__float_as_uint(m1));
+                *(uint16_t*)&ex[B * N + c2] = (uint16_t)((E0 + 127) | ((E1 + 127) << 8));
+                *(float2*)&s_sc[B * N + csw(c2)] = make_float2(e8(E0), e8(E1));
+            });
         }
         __syncthreads();
-        const float* my_scale = s_scale + sb * N;
-        const float* my_lim = s_lim + sb * N;
+        // 3. encode: clamp to MAXV * 2^E (bits of 2^E plus those of MAXV), scaled conversion
+        constexpr uint32_t LIMADD = ((uint32_t)mxd::Elem<F>::EMAX << 23) | 0x00600000u;
+        const float* my_sc = s_sc + (rl / CB) * N;
         uint32_t* cd = g.codes + ((size_t)slice * N * N) / 2;
         // in-lane column groups: offsets with bits 0..C-1 consecutive columns
         sfor<P / CB>([&](auto G) {
             constexpr int o0 = deposit(G, (P - 1) & ~(CB - 1));
             const int col0 = Lay<C>::posF(KL, o0) | pmL;      // first column of the group
-            uint32_t w[CB / 2 > 0 ? CB / 2 : 1];
+            float sc[CB];
+            sfor<CB / VW>([&](auto J) {
+                const float* src = &my_sc[csw(col0 + VW * J)];
+                if constexpr (VW == 4) {
+                    const float4 q = *(const float4*)src;
+                    sc[4 * J] = q.x; sc[4 * J + 1] = q.y; sc[4 * J + 2] = q.z; sc[4 * J + 3] = q.w;
+                } else {
+                    const float2 q = *(const float2*)src;
+                    sc[2 * J] = q.x; sc[2 * J + 1] = q.y;
+                }
+            });
+            uint32_t w[CB / 2];
             sfor<CB / 2>([&](auto H) {
                 constexpr int oa = o0 + 2 * H, obx = oa + 1;
-                const int ca = col0 + 2 * H, cbx = ca + 1;
-                const float la = my_lim[ca], lb = my_lim[cbx];
+                const float sa = sc[2 * H], sb = sc[2 * H + 1];
+                const float la = __uint_as_float(__float_as_uint(sa) + LIMADD);
+                const float lb = __uint_as_float(__float_as_uint(sb) + LIMADD);
                 const float ra = __builtin_amdgcn_fmed3f(a[oa].x, -la, la);
-                uint32_t r = enc2<F, false>(__float_as_uint(ra), ra,
-                                            __builtin_amdgcn_fmed3f(a[oa].y, -la, la), my_scale[ca]);
+                uint32_t r = enc2<F, false>(__float_as_uint(ra), ra, __builtin_amdgcn_fmed3f(a[oa].y, -la, la), sa);
                 r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x, -lb, lb),
-                                  __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), my_scale[cbx]);
+                                  __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), sb);
                 w[H] = r;
             });
             // [cg][row][cb] with cg = col0 / CB
@@ -550,28 +625,46 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
 template <int F, int C, bool INV>
 __global__ __launch_bounds__(256) void k_col(FastArgs g)
 {
-    constexpr int TSTR = 9;                         // LDS words per tile row (8 + pad)
-    __shared__ float s_plane[WAVES][LPW * N];       // 32 KiB: exchange planes, first the code tile
-    __shared__ uint8_t s_ex[LINES * N / 2];         // exponents of the 16 columns (up to N/2 blocks)
+    constexpr int TSTR = 9;                            // LDS words per code-tile row (8 + pad)
+    constexpr int CB = 1 << C;
+    constexpr int NRB = N / CB;                        // row blocks per column
+    __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; input and output tiles
+    __shared__ __align__(16) uint8_t s_ex[(F == FP32) ? 16 : LINES * NRB];  // [row block][16 columns]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int line = lane >> 4, m = lane & 15;
     const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
-    const int col = cb16 * LINES + wave * LPW + line;   // this lane's column
+    const int cl = wave * LPW + line;                  // column within the work-group
     const int kp = slice_k(g, slice);
     const int kout = g.kout_mul * kp + g.kout_add;
-    float* plane = s_plane[wave] + line * N;
+    float* plane = s_plane + wave * WPL + line * XLINE;
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
+    float2* tile = (float2*)s_plane;                   // 256 x 16 complex (32 KiB)
 
     if constexpr (F == FP32) {
-        const float2* x = g.src + (size_t)slice * N * N + col;
-        sfor<P>([&](auto Kk) { a[rev(Kk, 5)] = x[(size_t)(16 * Kk + rm) * N]; });
+        // rows are read whole (128 bytes = the work-group's 16 columns) into an
+        // LDS tile, 256 rows at a time; lanes then take rows 16k + rev4(m)
+        // (layout 0: offset rev5(k)), whose low 4 bits are the lane bits
+        const float2* xs = g.src + (size_t)slice * N * N + cb16 * LINES;
+        sfor<2>([&](auto H) {
+            if constexpr (H == 1) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int q = i * 256 + tid, r = q >> 3, pr = q & 7;
+                const float4 v = *(const float4*)&xs[(size_t)(H * 256 + r) * N + 2 * pr];
+                *(float4*)&tile[tslot<0xF>(r, 2 * pr)] = v;
+            }
+            __syncthreads();
+            sfor<16>([&](auto Kl) {
+                constexpr int Kk = H * 16 + Kl;
+                a[rev(Kk, 5)] = tile[tslot<0xF>(16 * Kl + rm, cl)];
+            });
+        });
+        __syncthreads();
     } else {
-        constexpr int CB = 1 << C;
-        constexpr int NRB = N / CB;                 // row blocks per column
         // code tile of the 16 columns: 16 / CB column groups of [row][CB] pairs
-        uint32_t* tile = (uint32_t*)&s_plane[0][0];
+        uint32_t* ctile = (uint32_t*)s_plane;
         const uint32_t* cd = g.codes + ((size_t)slice * N * N + (size_t)cb16 * LINES * N) / 2;
         for (int i = tid; i < LINES * N / 8; i += 256) {            // 16-byte pieces
             const uint4 q = ((const uint4*)cd)[i];
@@ -581,17 +674,17 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
                 const int cgi = pair / (N * CB), rem = pair % (N * CB);
                 const int r = rem / CB, c = cgi * CB + rem % CB;   // row and column (0..15)
                 const uint32_t val = W == 0 ? q.x : W == 1 ? q.y : W == 2 ? q.z : q.w;
-                tile[r * TSTR + c / 2] = val;
+                ctile[r * TSTR + c / 2] = val;
             });
         }
-        const uint8_t* ex = g.exps + (size_t)slice * N * NRB + (size_t)cb16 * LINES * NRB;
-        for (int i = tid; i < LINES * NRB; i += 256) s_ex[i] = ex[i];
+        // exponents [slice][row block][column]: 16 bytes per row block
+        const uint8_t* ex = g.exps + (size_t)slice * NRB * N + cb16 * LINES;
+        for (int i = tid; i < NRB; i += 256) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
         __syncthreads();
-        const int cl = col - cb16 * LINES;
         sfor<P>([&](auto O) {
             const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
-            const uint32_t wd = tile[n * TSTR + cl / 2];
-            const float s = __uint_as_float((uint32_t)s_ex[cl * NRB + n / CB] << 23);
+            const uint32_t wd = ctile[n * TSTR + cl / 2];
+            const float s = __uint_as_float((uint32_t)s_ex[(n / CB) * 16 + cl] << 23);
             a[O] = (cl & 1) ? dec2<F, true>(wd, s) : dec2<F, false>(wd, s);
         });
         __syncthreads();
@@ -599,13 +692,34 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
 
     all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane);
 
+    // output: scaled by 2^kout, staged through an LDS tile 256 rows at a time
+    // (row bit 8 is an in-lane bit of the last layout) and written as whole
+    // 128-byte row pieces
     constexpr int CL = (F == FP32) ? 1 : C;
     constexpr int KL = Lay<CL>::NL - 1;
+    constexpr int HB = Lay<CL>::index_of(KL, LOGN - 1);
+    constexpr int LM = lane_mask<CL, KL>();
+    static_assert(HB >= 0 && (LM & 1) == 0 && (LM >> 8) == 0, "row bit 8 in-lane, bit 0 in-lane");
     const int pmL = posM<CL, KL>(m);
-    float2* y = g.dst + (size_t)slice * N * N + col;
-    sfor<P>([&](auto O) {
-        const int r = Lay<CL>::posF(KL, O) | pmL;
-        y[(size_t)r * N] = make_float2(ldexpf(a[O].x, kout), ldexpf(a[O].y, kout));
+    float2* ys = g.dst + (size_t)slice * N * N + cb16 * LINES;
+    sfor<2>([&](auto H) {
+        __syncthreads();
+        sfor<P>([&](auto O) {
+            if constexpr (((O >> HB) & 1) == H) {
+                const int r = (Lay<CL>::posF(KL, O) | pmL) & 255;
+                tile[tslot<LM>(r, cl)] = make_float2(ldexpf(a[O].x, kout), ldexpf(a[O].y, kout));
+            }
+        });
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int q = i * 256 + tid, R = q >> 3, pr = q & 7;
+            const float4 v = *(const float4*)&tile[R * 16 + 2 * pr];
+            const int xr = pext<LM>(R);
+            const int r = R ^ (xr & 1);
+            const int c = (2 * pr) ^ (((xr >> 1) & 3) << 2);
+            *(float4*)&ys[(size_t)(H * 256 + r) * N + c] = v;
+        }
     });
 }
 

@@ -40,16 +40,21 @@ __device__ int round_log2_ratio(double T, double a)
 
 // Statistics of one chunk of one slice: binade histogram of |x|, count of
 // nonzero values, max |x|^2, max part, non-finite flag.
+// The histogram has one copy per lane of a half-wave (bin * 32 + lane % 32):
+// data concentrated in a few binades would otherwise serialise the LDS
+// atomics of a wave on one address; this way the two lanes sharing a copy
+// are the only possible collision, which the 32-bank LDS pays anyway.
+constexpr int kHistCopies = 32;
 __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x, int nn, int chunk,
                                                      int chunks, StatPart* __restrict__ parts)
 {
-    __shared__ uint32_t hist[kStatsBins];
+    __shared__ __align__(16) uint32_t hist[kStatsBins * kHistCopies];
     __shared__ unsigned long long s_m2;
     __shared__ uint32_t s_count, s_maxc, s_nonfin;
-    const int tid = threadIdx.x, slice = blockIdx.y;
+    const int tid = threadIdx.x, slice = blockIdx.y, copy = tid & (kHistCopies - 1);
     const float2* xs = x + (size_t)slice * nn;
 
-    for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
+    for (int i = tid; i < kStatsBins * kHistCopies / 4; i += blockDim.x) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
     if (tid == 0) { s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; }
     __syncthreads();
 
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x
             mm = max(mm, b);
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2): sqrt is monotone and
             // correctly rounded, so it never crosses a power of two
-            atomicAdd(&hist[((((int)(b >> 52)) - 1023) >> 1) + kBinOffset], 1u);
+            atomicAdd(&hist[(((((int)(b >> 52)) - 1023) >> 1) + kBinOffset) * kHistCopies + copy], 1u);
         }
     };
     if (((end - beg) & 1) == 0 && ((((uintptr_t)(xs + beg)) & 15) == 0)) {
@@ -100,7 +105,13 @@ __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x
     __syncthreads();
 
     StatPart* pt = parts + (size_t)slice * chunks + blockIdx.x;
-    for (int i = tid; i < kStatsBins; i += blockDim.x) pt->hist[i] = hist[i];
+    // sum the copies of bin i; thread i starts at copy i % 32 so a wave's
+    // reads fall in 32 different banks
+    for (int i = tid; i < kStatsBins; i += blockDim.x) {
+        uint32_t h = 0;
+        for (int j = 0; j < kHistCopies; j++) h += hist[i * kHistCopies + ((i + j) & (kHistCopies - 1))];
+        pt->hist[i] = h;
+    }
     if (tid == 0) {
         pt->max_m2 = s_m2;
         pt->count = s_count;
