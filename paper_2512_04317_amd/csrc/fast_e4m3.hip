@@ -3,12 +3,15 @@
 
 namespace mxk {
 
-hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s)
+hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch,
+                          hipStream_t s)
 {
     const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
-#define MXF_CASE(CC, INV)                                                                 \
-    if (row) hipLaunchKernelGGL((mxf::k_row<0, CC, INV>), grid, block, 0, s, g);         \
-    else hipLaunchKernelGGL((mxf::k_col<0, CC, INV>), grid, block, 0, s, g);
+#define MXF_CASE(CC, INV)                                                                                \
+    if (!row) hipLaunchKernelGGL((mxf::k_col<0, CC, INV>), grid, block, 0, s, g);                       \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf::k_row<0, CC, INV, ROW_STATS>), grid, block, 0, s, g); \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf::k_row_fix<0, CC, INV>), grid, block, 0, s, g);       \
+    else hipLaunchKernelGGL((mxf::k_row<0, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
     switch (cb * 2 + (inverse ? 1 : 0)) {
     case 4: MXF_CASE(1, false) break;
     case 5: MXF_CASE(1, true) break;

@@ -3,9 +3,9 @@
 
 namespace mxk {
 
-hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
-hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
-hipError_t launch_fast_fp32(int cb, bool row, bool inverse, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_fp32(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 
 bool fast_supported(int mode, int n, int cb)
 {
@@ -14,7 +14,13 @@ bool fast_supported(int mode, int n, int cb)
     return cb >= 2 && cb <= 16;
 }
 
-hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassArgs& p, int batch, hipStream_t s)
+int fast_row_tiles(int n)
+{
+    return n / mxf::LINES;
+}
+
+hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const FastPassArgs& p, int batch,
+                       hipStream_t s)
 {
     mxf::FastArgs g{};
     g.src = p.src;
@@ -29,10 +35,14 @@ hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassA
     g.tw = p.tw;
     g.tw_exp = p.tw_exp;
     for (int i = 0; i < 16; i++) g.tw_off[i] = p.tw_off[i];
+    g.parts = p.parts;
+    g.kadd = p.kadd;
+    g.fix_list = p.fix_list;
+    g.fix_count = p.fix_count;
     switch (mode) {
-    case MODE_E4M3: return launch_fast_e4m3(cb, row, inverse, g, batch, s);
-    case MODE_E5M2: return launch_fast_e5m2(cb, row, inverse, g, batch, s);
-    case MODE_FP32: return launch_fast_fp32(cb, row, inverse, g, batch, s);
+    case MODE_E4M3: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
+    case MODE_E5M2: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);
+    case MODE_FP32: return launch_fast_fp32(cb, row, inverse, kind, g, batch, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -282,11 +282,11 @@ __device__ __forceinline__ float2 clamp2(float2 v, float lim)
 }
 
 // MX-encode a group of values sharing one block exponent, in place:
-// v <- Q(v / 2^E) * 2^E with E from the group maximum.  Returns E.
+// v <- Q(v / 2^E) * 2^E with E from the group maximum am.  Returns E.
 template <int F, int CNT>
-__device__ __forceinline__ int mx_requant(float2* v)
+__device__ __forceinline__ int mx_requant(float2* v, float& am)
 {
-    const float am = amax_of<CNT>(v);
+    am = amax_of<CNT>(v);
     const int E = mxd::block_exp<F>(__float_as_uint(am));
     const float s = e8(E), lim = lim_of<F>(E);
     uint32_t c[CNT / 2];
@@ -298,6 +298,13 @@ __device__ __forceinline__ int mx_requant(float2* v)
     return E;
 }
 
+// Running range of the MX block exponents a pass uses (only tracked by the
+// row pass that runs unscaled while it gathers the prescale statistics).
+struct ERange {
+    int lo = 0, hi = 0;
+    __device__ __forceinline__ void add(int e) { lo = min(lo, e); hi = max(hi, e); }
+};
+
 struct Tw {
     const float2* tw;      // stage s = b+1, index j at [2^b + j]
     const int32_t* ex;     // twiddle block exponents
@@ -307,8 +314,8 @@ struct Tw {
 // ---------------------------------------------------------------------------
 // one radix-2 stage (butterfly position bit B) in layout K
 // ---------------------------------------------------------------------------
-template <int F, int C, int K, int B, bool INV>
-__device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
+template <int F, int C, int K, int B, bool INV, bool TR>
+__device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     using Ly = Lay<C>;
     constexpr int ob = Ly::index_of(K, B);
@@ -348,6 +355,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
             // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
             const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
+            if constexpr (TR) er.add(Ev);
             const float s = e8(Ev), lim = lim_of<F>(Ev);
             uint32_t c[CB / 2];
             sfor<CB / 2>([&](auto H) { c[H] = enc4<F>(clamp2(V[2 * H], lim), clamp2(V[2 * H + 1], lim), s); });
@@ -365,6 +373,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
             // operand v: EncodeBlockMX, element values as FP32 mantissas
             const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
+            if constexpr (TR) er.add(Ev);
             const float s = e8(Ev), lim = lim_of<F>(Ev);
             float2 Pp[CB];
             uint32_t cv[CB / 2];
@@ -410,11 +419,11 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t)
 }
 
 // all stages of layout K
-template <int F, int C, int K, bool INV>
-__device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t)
+template <int F, int C, int K, bool INV, bool TR>
+__device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     constexpr int b0 = Lay<C>::bfirst(K), b1 = Lay<C>::blast(K);
-    sfor<b1 - b0>([&](auto I) { stage<F, C, K, b0 + I, INV>(a, m, t); });
+    sfor<b1 - b0>([&](auto I) { stage<F, C, K, b0 + I, INV, TR>(a, m, t, er); });
 }
 
 // Layout K -> K+1 through this wave's LDS planes (re, then im).
@@ -443,13 +452,13 @@ __device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
 }
 
 // plane: this line's exchange plane (XLINE words apart per line)
-template <int F, int C, bool INV>
-__device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane)
+template <int F, int C, bool INV, bool TR = false>
+__device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane, ERange& er)
 {
     using Ly = Lay<C>;
     sfor<Ly::NL>([&](auto K) {
         if constexpr (K > 0) exchange<C, K - 1>(a, m, plane);
-        stages<F, C, K, INV>(a, m, t);
+        stages<F, C, K, INV, TR>(a, m, t, er);
     });
 }
 
@@ -468,7 +477,17 @@ struct FastArgs {
     const float2* tw;
     const int32_t* tw_exp;
     int32_t tw_off[16];
+    mxk::StatPart* parts;    // row pass with statistics: [slice][tile]
+    const int32_t* kadd;     // column pass: per-slice offset of the stored exponents, or nullptr
+    const int32_t* fix_list; // list-driven row pass: slices to redo
+    int32_t* fix_count;      // list length (zeroed by the row pass with statistics)
 };
+
+using mxk::kStatsBins;
+using mxk::StatPart;
+using mxk::ROW_PLAIN;
+using mxk::ROW_STATS;
+using mxk::ROW_FIX;
 
 __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
 {
@@ -476,27 +495,63 @@ __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
     return k == INT32_MIN ? 0 : k;
 }
 
-// Row pass. F: 0 E4M3, 1 E5M2, 4 FP32.  C: log2 of complex values per MX block.
-template <int F, int C, bool INV>
-__global__ __launch_bounds__(256) void k_row(FastArgs g)
+// Shared memory of the row pass.
+template <int F, int C, int KIND>
+struct alignas(16) RowLds {
+    static constexpr int NSB = (F == FP32) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
+    float plane[WAVES * WPL];          // exchange planes; then column maxima
+    float sc[NSB * N];                 // column block scales 2^E (MX)
+    // prescale statistics (row pass with statistics only): binade histogram,
+    // 8 copies (bin * 8 + lane % 8); bin kStatsBins - 1 collects zeros and non-finite values
+    uint32_t hist[KIND == ROW_STATS ? kStatsBins * 8 : 4];
+    double m2[WAVES];
+    float mc[WAVES];
+    int nf[WAVES], elo[WAVES], ehi[WAVES];
+};
+
+template <class T>
+__device__ __forceinline__ T wave_reduce_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_reduce_min(T v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One 16-row tile of the row pass. F: 0 E4M3, 1 E5M2, 4 FP32.  C: log2 of
+// complex values per MX block.  KIND:
+//   ROW_PLAIN  input scaled by 2^(kin_mul * kp) (kp per slice, may be absent)
+//   ROW_STATS  input unscaled; also the Alg. 1 statistics of the tile (with the
+//              range of the block exponents used) into parts[slice][tile]
+//   ROW_FIX    input scaled by 2^kp: the literal pass for a listed slice
+template <int F, int C, bool INV, int KIND>
+__device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, RowLds<F, C, KIND>& L)
 {
     constexpr int CB = 1 << C;
-    constexpr int NSB = (F == FP32) ? 1 : LINES / CB;     // column blocks (of CB rows) per work-group
-    __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; then column maxima
-    __shared__ __align__(16) float s_sc[NSB * N];         // column block scales 2^E (MX)
+    constexpr int NSB = RowLds<F, C, KIND>::NSB;
+    constexpr bool ST = (KIND == ROW_STATS);
+    static_assert(!ST || F != FP32, "statistics ride on the MX row pass only");
+    float* s_plane = L.plane;
+    float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int line = lane >> 4, m = lane & 15;
-    const int slice = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
-    const int rl = wave * LPW + line;                     // row within the work-group
+    const int rl = wave * LPW + line;                     // row within the tile
     const int row = rb * LINES + rl;
     const int kp = slice_k(g, slice);
-    const int kin = g.kin_mul * kp;
-    if (g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
+    const int kin = ST ? 0 : g.kin_mul * kp;
+    if (KIND == ROW_PLAIN && g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
     const float2* x = g.src + ((size_t)slice * N + row) * N;
     float* plane = s_plane + wave * WPL + line * XLINE;
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
+    ERange er;
 
     if constexpr (F == FP32) {
         // layout 0 directly: natural 16k + rev4(m) -> offset rev5(k)
@@ -510,10 +565,48 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
         const float4* x4 = (const float4*)(x + P * m);
         sfor<P / 2>([&](auto I) {
             const float4 q = x4[I];
-            v[2 * I] = make_float2(ldexpf(q.x, kin), ldexpf(q.y, kin));
-            v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
+            if constexpr (ST) {
+                v[2 * I] = make_float2(q.x, q.y);
+                v[2 * I + 1] = make_float2(q.z, q.w);
+            } else {
+                v[2 * I] = make_float2(ldexpf(q.x, kin), ldexpf(q.y, kin));
+                v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
+            }
         });
-        sfor<P / CB>([&](auto G) { mx_requant<F, CB>(v + G * CB); });
+        float mc = 0.f;
+        if constexpr (ST) {
+            // Alg. 1 statistics of the unscaled input: |x|^2 in FP64 (both squares
+            // exact, one rounding), its maximum, a non-finite check (the sum of
+            // the squares is finite iff every part is), and the binade histogram
+            // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
+            // monotone and correctly rounded)
+            for (int i = tid; i < kStatsBins * 8 / 4; i += 256) ((uint4*)L.hist)[i] = make_uint4(0, 0, 0, 0);
+            if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
+            __syncthreads();
+            double m2max = 0.0, m2sum = 0.0;
+            sfor<P>([&](auto I) {
+                const double m2 = (double)v[I].x * (double)v[I].x + (double)v[I].y * (double)v[I].y;
+                m2max = fmax(m2max, m2);
+                m2sum += m2;
+                // biased exponent e of |x|^2 -> bin (e - 725) / 2 = floor(log2 |x|) + 149;
+                // zero (e = 0) and non-finite (e = 2047) land in the last bin
+                const uint32_t hi = (uint32_t)((unsigned long long)__double_as_longlong(m2) >> 32);
+                const uint32_t bin = min(((hi >> 20) - 725u) >> 1, (uint32_t)(kStatsBins - 1));
+                atomicAdd(&L.hist[bin * 8 + (lane & 7)], 1u);
+            });
+            m2max = wave_reduce_max(m2max);
+            const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
+            if (lane == 0) { L.m2[wave] = m2max; L.nf[wave] = nf; }
+        }
+        sfor<P / CB>([&](auto G) {
+            float am;
+            const int E = mx_requant<F, CB>(v + G * CB, am);
+            if constexpr (ST) { er.add(E); mc = fmaxf(mc, am); }
+        });
+        if constexpr (ST) {
+            mc = wave_reduce_max(mc);
+            if (lane == 0) L.mc[wave] = mc;
+        }
         // bit reversal into layout 0 through the LDS planes (32-bit stores:
         // lines RLINE words apart)
         float* rplane = s_plane + wave * WPL + line * RLINE;
@@ -530,7 +623,7 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
         });
     }
 
-    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane);
+    all_stages<F, (F == FP32 ? 1 : C), INV, ST>(a, m, t, plane, er);
 
     constexpr int CL = (F == FP32) ? 1 : C;
     constexpr int KL = Lay<CL>::NL - 1;
@@ -569,6 +662,7 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
                     m1 = fmaxf(m1, v.y);
                 });
                 const int E0 = mxd::block_exp<F>(__float_as_uint(m0)), E1 = mxd::block_exp<F>(__float_as_uint(m1));
+                if constexpr (ST) { er.add(E0); er.add(E1); }
                 *(uint16_t*)&ex[B * N + c2] = (uint16_t)((E0 + 127) | ((E1 + 127) << 8));
                 *(float2*)&s_sc[B * N + csw(c2)] = make_float2(e8(E0), e8(E1));
             });
@@ -618,7 +712,59 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
                 dstw[0] = w[0];
             }
         });
+        if constexpr (ST) {
+            const int lo = wave_reduce_min(er.lo), hi = wave_reduce_max(er.hi);
+            if (lane == 0) { L.elo[wave] = lo; L.ehi[wave] = hi; }
+            __syncthreads();
+            StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
+            // sum the 8 copies of bin i; copy order skewed by i / 4 so a wave's
+            // reads fall in 32 different banks
+            for (int i = tid; i < kStatsBins; i += 256) {
+                uint32_t h = 0;
+#pragma unroll
+                for (int c = 0; c < 8; c++) h += L.hist[i * 8 + ((c + (i >> 2)) & 7)];
+                pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
+            }
+            if (tid == 0) {
+                double m2 = L.m2[0];
+                float mcw = L.mc[0];
+                int nf = L.nf[0], elo = L.elo[0], ehi = L.ehi[0];
+#pragma unroll
+                for (int w = 1; w < WAVES; w++) {
+                    m2 = fmax(m2, L.m2[w]);
+                    mcw = fmaxf(mcw, L.mc[w]);
+                    nf |= L.nf[w];
+                    elo = min(elo, L.elo[w]);
+                    ehi = max(ehi, L.ehi[w]);
+                }
+                pt->max_m2 = (unsigned long long)__double_as_longlong(m2);
+                pt->count = 0;
+                pt->max_comp = __float_as_uint(mcw);
+                pt->nonfinite = (uint32_t)nf;
+                pt->emin = elo;
+                pt->emax = ehi;
+            }
+        }
     }
+}
+
+// Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).
+template <int F, int C, bool INV, int KIND>
+__global__ __launch_bounds__(256) void k_row(FastArgs g)
+{
+    __shared__ RowLds<F, C, KIND> L;
+    row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
+}
+
+// Row pass over the slices in fix_list only: one work-group per (list entry,
+// tile) of a batch-sized grid; entries past the list length return at once.
+template <int F, int C, bool INV>
+__global__ __launch_bounds__(256) void k_row_fix(FastArgs g)
+{
+    __shared__ RowLds<F, C, ROW_FIX> L;
+    const int j = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
+    if (j >= *g.fix_count) return;
+    row_tile<F, C, INV, ROW_FIX>(g, g.fix_list[j], rb, L);
 }
 
 // Column pass.
@@ -680,17 +826,20 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         // exponents [slice][row block][column]: 16 bytes per row block
         const uint8_t* ex = g.exps + (size_t)slice * NRB * N + cb16 * LINES;
         for (int i = tid; i < NRB; i += 256) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
+        // stored exponents of a row pass that ran unscaled are offset by kadd
+        const int eadd = g.kadd ? g.kadd[slice] : 0;
         __syncthreads();
         sfor<P>([&](auto O) {
             const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
             const uint32_t wd = ctile[n * TSTR + cl / 2];
-            const float s = __uint_as_float((uint32_t)s_ex[(n / CB) * 16 + cl] << 23);
+            const float s = __uint_as_float((uint32_t)((int)s_ex[(n / CB) * 16 + cl] + eadd) << 23);
             a[O] = (cl & 1) ? dec2<F, true>(wd, s) : dec2<F, false>(wd, s);
         });
         __syncthreads();
     }
 
-    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane);
+    ERange er;
+    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane, er);
 
     // output: scaled by 2^kout, staged through an LDS tile 256 rows at a time
     // (row bit 8 is an in-lane bit of the last layout) and written as whole

@@ -2,6 +2,7 @@
 // launch sequences behind the C ABI of include/mxfft.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -90,6 +91,12 @@ struct mxfft_plan_s {
     float2* d_twf = nullptr;
     uint32_t* d_codes = nullptr;
     uint8_t* d_exps = nullptr;
+    // statistics gathered by the row pass (MX, n = 512): exponent offsets and
+    // the list of slices whose row pass is redone literally
+    bool fused = false;
+    int32_t* d_kadd = nullptr;
+    int32_t* d_fix_list = nullptr;
+    int32_t* d_fix_count = nullptr;
     uint64_t bytes = 0;
     int last_batch = 0;
     bool last_has_stats = false;
@@ -107,9 +114,9 @@ struct mxfft_plan_s {
 
 namespace {
 
-enum Role { ROLE_STATS = 0, ROLE_ROW, ROLE_COL, ROLE_INV_ROW, ROLE_INV_COL, ROLE_COUNT };
+enum Role { ROLE_STATS = 0, ROLE_ROW, ROLE_COL, ROLE_INV_ROW, ROLE_INV_COL, ROLE_FIX, ROLE_COUNT };
 const char* const kRoleNames[ROLE_COUNT] = {"prescale_stats", "row_pass", "column_pass", "inverse_row_pass",
-                                            "inverse_column_pass"};
+                                            "inverse_column_pass", "row_redo"};
 
 hipEvent_t take_event(mxfft_plan_s* pl)
 {
@@ -208,6 +215,9 @@ void release(mxfft_plan_s* pl)
     (void)hipFree(pl->d_twf);
     (void)hipFree(pl->d_codes);
     (void)hipFree(pl->d_exps);
+    (void)hipFree(pl->d_kadd);
+    (void)hipFree(pl->d_fix_list);
+    (void)hipFree(pl->d_fix_count);
     delete pl;
 }
 
@@ -246,10 +256,24 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
     if (tw_exp.empty()) tw_exp.push_back(0);
 }
 
+#define MX_TRY(expr)                          \
+    do {                                      \
+        mxfft_status st_ = (expr);            \
+        if (st_ != MXFFT_OK) return st_;      \
+    } while (0)
+
+// One pass over rows (axis 0) or columns (axis 1).  kind (row pass of the
+// register-resident path): ROW_PLAIN, ROW_STATS (unscaled, with the Alg. 1
+// statistics) or ROW_FIX (the listed slices only).  kadd: column pass offsets
+// of the stored exponents (after a ROW_STATS row pass), else nullptr.
 mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* kp, int32_t* k_out,
-                  int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s)
+                  int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s,
+                  int kind = mxk::ROW_PLAIN, const int32_t* kadd = nullptr)
 {
-    LaunchTimer timer(pl, inverse ? (axis ? ROLE_INV_COL : ROLE_INV_ROW) : (axis ? ROLE_COL : ROLE_ROW), s);
+    const int role = (kind == mxk::ROW_FIX) ? ROLE_FIX
+                     : inverse              ? (axis ? ROLE_INV_COL : ROLE_INV_ROW)
+                                            : (axis ? ROLE_COL : ROLE_ROW);
+    LaunchTimer timer(pl, role, s);
     if (pl->fast) {
         // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
         mxk::FastPassArgs f{};
@@ -265,8 +289,13 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
         f.tw = pl->d_twf;
         f.tw_exp = pl->d_tw_exp;
         for (int i = 0; i < 16; i++) f.tw_off[i] = i < mxk::kMaxLog2N + 2 ? pl->tw_exp_off[i] : 0;
-        return mxk::launch_fast(pl->mode, pl->cb, axis == 0, inverse != 0, f, batch, s) == hipSuccess ? MXFFT_OK
-                                                                                                     : MXFFT_EHIP;
+        f.parts = pl->d_parts;
+        f.kadd = kadd;
+        f.fix_list = pl->d_fix_list;
+        f.fix_count = pl->d_fix_count;
+        return mxk::launch_fast(pl->mode, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
+                   ? MXFFT_OK
+                   : MXFFT_EHIP;
     }
     mxk::LineArgs a{};
     a.src = (const float2*)src;
@@ -290,7 +319,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
-mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
+mxk::PrescaleArgs prescale_args(const mxfft_plan_s* pl)
 {
     mxk::PrescaleArgs pa{};
     pa.target = pl->p.target;
@@ -300,10 +329,41 @@ mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
     pa.log2_tau_min = e - 1;
     pa.k_min = pl->p.k_min;
     pa.k_max = pl->p.k_max;
+    return pa;
+}
+
+// Literal Alg. 1: a statistics pass over the input, then kp per slice.
+mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
+{
+    const mxk::PrescaleArgs pa = prescale_args(pl);
     LaunchTimer timer(pl, ROLE_STATS, s);
     if (mxk::launch_stats((const float2*)in, pl->n, batch, pl->d_parts, pl->d_kp, pl->d_status, pa, s) != hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
+}
+
+// Row pass with Alg. 1 folded in (register-resident MX path).  MX encoding
+// and the radix-2 stages are exactly equivariant under power-of-two scaling
+// while no block exponent reaches the E8M0 limits and no FP32 value leaves
+// the normal range, so the row pass runs on the unscaled input and gathers
+// the prescale statistics on the way.  kp then follows per slice; where the
+// block exponents of that pass (and the same plus kp) stay inside
+// [kEquivLo, kEquivHi], the stored intermediate is the scaled row pass with
+// its exponents offset by -kp, which the column pass adds back (kadd = kp);
+// any other slice gets the literal row pass of x * 2^kp (kadd = 0).
+mxfft_status row_with_stats(mxfft_plan_s* pl, const void* in, int32_t* k_out, int inverse, int batch,
+                            hipStream_t s)
+{
+    MX_TRY(pass(pl, in, nullptr, nullptr, nullptr, 0, 0, 0, 0, inverse, batch, s, mxk::ROW_STATS));
+    {
+        const mxk::PrescaleArgs pa = prescale_args(pl);
+        LaunchTimer timer(pl, ROLE_STATS, s);
+        if (mxk::launch_stats_final((const float2*)in, pl->n, batch, mxk::fast_row_tiles(pl->n), pl->d_parts,
+                                    pl->d_kp, pl->d_status, pa, pl->d_kadd, pl->d_fix_list, pl->d_fix_count,
+                                    k_out, s) != hipSuccess)
+            return MXFFT_EHIP;
+    }
+    return pass(pl, in, nullptr, pl->d_kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
 }
 
 mxfft_status check_call(const mxfft_plan_s* pl, const void* in, const void* out, int32_t batch)
@@ -313,11 +373,6 @@ mxfft_status check_call(const mxfft_plan_s* pl, const void* in, const void* out,
     return MXFFT_OK;
 }
 
-#define MX_TRY(expr)                          \
-    do {                                      \
-        mxfft_status st_ = (expr);            \
-        if (st_ != MXFFT_OK) return st_;      \
-    } while (0)
 
 }  // namespace
 
@@ -366,7 +421,13 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw, tw.size(), &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw_exp, tw_exp.size(), &pl->bytes);
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_parts, mxk::stats_parts(n, max_batch), &pl->bytes);
+    {
+        // chunk statistics: the literal statistics pass, or one part per row tile
+        size_t parts = mxk::stats_parts(n, max_batch);
+        if (mxk::fast_supported(pl->mode, n, pl->cb) && pl->mode != mxk::MODE_FP32)
+            parts = std::max(parts, (size_t)max_batch * mxk::fast_row_tiles(n));
+        if (st == MXFFT_OK) st = dev_alloc(&pl->d_parts, parts, &pl->bytes);
+    }
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_kp, (size_t)max_batch, &pl->bytes);
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
@@ -379,6 +440,10 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
         if (st == MXFFT_OK && pl->mode != mxk::MODE_FP32) {
             st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n / 2, &pl->bytes);
             if (st == MXFFT_OK) st = dev_alloc(&pl->d_exps, (size_t)max_batch * n * (n / pl->cb), &pl->bytes);
+            pl->fused = true;
+            if (st == MXFFT_OK) st = dev_alloc(&pl->d_kadd, (size_t)max_batch, &pl->bytes);
+            if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_list, (size_t)max_batch, &pl->bytes);
+            if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_count, 1, &pl->bytes);
         }
     }
     if (st != MXFFT_OK) {
@@ -413,11 +478,16 @@ mxfft_status mxfft_forward(mxfft_plan_t pl, const void* in, void* out, int32_t b
     if (batch == 0) return MXFFT_OK;
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
-    if (pre) MX_TRY(stats(pl, in, batch, s));
     const int32_t* kp = pre ? pl->d_kp : nullptr;
     const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
-    MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
+    if (pre && pl->fused) {
+        MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+    } else {
+        if (pre) MX_TRY(stats(pl, in, batch, s));
+        MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
+    }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     return MXFFT_OK;
@@ -434,13 +504,18 @@ mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t b
     const int32_t* kp = k_in;
     int kin_mul = 0;
     if (!k_in && !(pl->p.flags & MXFFT_NO_PRESCALE)) {
-        MX_TRY(stats(pl, in, batch, s));
         pre = true;
         kp = pl->d_kp;
         kin_mul = 1;
     }
-    MX_TRY(pass(pl, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
+    if (pre && pl->fused) {
+        MX_TRY(row_with_stats(pl, in, nullptr, 1, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+    } else {
+        if (pre) MX_TRY(stats(pl, in, batch, s));
+        MX_TRY(pass(pl, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
+    }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     return MXFFT_OK;
@@ -453,10 +528,15 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
     if (batch == 0) return MXFFT_OK;
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
-    if (pre) MX_TRY(stats(pl, in, batch, s));
     const int32_t* kp = pre ? pl->d_kp : nullptr;
-    MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+    if (pre && pl->fused) {
+        MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+    } else {
+        if (pre) MX_TRY(stats(pl, in, batch, s));
+        MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+        MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+    }
     MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
     MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     pl->last_batch = batch;

@@ -14,13 +14,22 @@ constexpr int kBinOffset = 149;
 // Prescale statistics of one chunk of one slice (device workspace, written
 // in full by every call; summed per slice by the finalize kernel).
 struct alignas(16) StatPart {
-    uint32_t hist[kStatsBins];      // nonzero |x| per binade floor(log2 |x|)
+    uint32_t hist[kStatsBins];      // nonzero finite |x| per binade floor(log2 |x|)
     unsigned long long max_m2;      // bits of max |x|^2 (FP64, non-negative)
-    uint32_t count;                 // nonzero elements
+    uint32_t count;                 // unused (the count is the histogram's sum)
     uint32_t max_comp;              // bits of max(|re|, |im|) (FP32)
     uint32_t nonfinite;             // any Inf/NaN part
-    uint32_t pad[3];
+    int32_t emin, emax;             // range of the MX block exponents the unscaled row pass used
+    uint32_t pad;
 };
+
+// Window of block exponents inside which an unscaled row pass times 2^k is
+// bit-identical to the row pass of the input scaled by 2^k (checked for the
+// exponents both before and after adding k): no E8M0 clamp at +-127, and
+// every FP32 value of the pass stays zero or normal and finite (element
+// grids are at least 2^(E - 32) for either FP8 format, values below
+// 2^(E + 17)).
+constexpr int kEquivLo = -90, kEquivHi = 90;
 
 // Chunks per slice for a batch: enough work-groups to fill the chip, at
 // least 8192 elements each.
@@ -71,13 +80,31 @@ struct FastPassArgs {
     const float2* tw;        // stage s (h = 2^(s-1)) index j at [h + j]
     const int32_t* tw_exp;
     int32_t tw_off[16];
+    StatPart* parts;         // row pass with statistics: one part per 16-row tile, [slice][tile]
+    const int32_t* kadd;     // column pass: per-slice offset added to the stored block exponents, or nullptr
+    const int32_t* fix_list; // list-driven row pass: slices to redo
+    int32_t* fix_count;      // number of list entries (zeroed by the row pass with statistics)
 };
 
+// Row pass kinds of the register-resident passes.
+enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2 };
+
 bool fast_supported(int mode, int n, int cb);
-hipError_t launch_fast(int mode, int cb, bool row, bool inverse, const FastPassArgs& p, int batch, hipStream_t s);
+// row: kind is one of RowKind; columns ignore it
+hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const FastPassArgs& p, int batch,
+                       hipStream_t s);
+// Tiles (row chunks) per slice of the row pass with statistics.
+int fast_row_tiles(int n);
 
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s);
+// Alg. 1 from chunk statistics already in `parts` ([slice][chunks]) that the
+// row pass wrote; also the equivariance check: kadd[slice] = kp when the
+// unscaled row pass may stand, else 0 with the slice appended to fix_list.
+// k_out (nullable) receives kp.
+hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, const StatPart* parts, int32_t* kp,
+                              int32_t* slice_status, const PrescaleArgs& pa, int32_t* kadd, int32_t* fix_list,
+                              int32_t* fix_count, int32_t* k_out, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);
 

@@ -117,36 +117,51 @@ __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x
         pt->count = s_count;
         pt->max_comp = s_maxc;
         pt->nonfinite = s_nonfin;
+        pt->emin = 0;
+        pt->emax = 0;
     }
 }
 
 // Alg. 1 for one slice from its chunk statistics (one work-group per slice).
+// With kadd given (chunk statistics from the row pass, which ran unscaled):
+// also decide whether that row pass stands for the scaled one -- every block
+// exponent it used, and that exponent plus kp, inside [kEquivLo, kEquivHi] --
+// and list the slice for a redo otherwise.
 __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ x, int nn, int chunks,
                                                       const StatPart* __restrict__ parts,
                                                       int32_t* __restrict__ kp, int32_t* __restrict__ slice_status,
-                                                      PrescaleArgs pa)
+                                                      PrescaleArgs pa, int32_t* __restrict__ kadd,
+                                                      int32_t* __restrict__ fix_list, int32_t* __restrict__ fix_count,
+                                                      int32_t* __restrict__ k_out)
 {
 #pragma clang fp contract(off)
     __shared__ uint32_t hist[kStatsBins];
     __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
     __shared__ uint32_t s_count, s_maxc, s_nonfin;
-    __shared__ int s_refine, s_bin_lo, s_bin_hi;
+    __shared__ int s_refine, s_bin_lo, s_bin_hi, s_emin, s_emax;
     const int tid = threadIdx.x, slice = blockIdx.x;
     const float2* xs = x + (size_t)slice * nn;
     const StatPart* pt = parts + (size_t)slice * chunks;
 
-    if (tid == 0) { s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0; }
+    if (tid == 0) {
+        s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0;
+        s_emin = 0; s_emax = 0;
+    }
     __syncthreads();
+    uint32_t cnt = 0;
     for (int i = tid; i < kStatsBins; i += blockDim.x) {
         uint32_t h = 0;
         for (int c = 0; c < chunks; c++) h += pt[c].hist[i];
         hist[i] = h;
+        cnt += h;
     }
+    atomicAdd(&s_count, cnt);
     for (int c = tid; c < chunks; c += blockDim.x) {
         atomicMax(&s_m2, pt[c].max_m2);
-        atomicAdd(&s_count, pt[c].count);
         atomicMax(&s_maxc, pt[c].max_comp);
         atomicOr(&s_nonfin, pt[c].nonfinite);
+        atomicMin(&s_emin, pt[c].emin);
+        atomicMax(&s_emax, pt[c].emax);
     }
     __syncthreads();
 
@@ -220,6 +235,17 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
         }
         kp[slice] = st ? INT32_MIN : k;
         slice_status[slice] = st;
+        if (k_out) k_out[slice] = st ? INT32_MIN : k;
+        if (kadd) {
+            const bool inside = s_emin >= kEquivLo && s_emax <= kEquivHi && s_emin + (long long)k >= kEquivLo &&
+                                s_emax + (long long)k <= kEquivHi;
+            if (st == 0 && !inside) {
+                kadd[slice] = 0;
+                fix_list[atomicAdd(fix_count, 1)] = slice;
+            } else {
+                kadd[slice] = st ? 0 : k;
+            }
+        }
     }
 }
 
@@ -249,7 +275,17 @@ hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int3
     hipLaunchKernelGGL(k_stats_part, dim3(chunks, batch), dim3(256), 0, s, x, nn, nn / chunks, chunks, parts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, nn, chunks, parts, kp, slice_status, pa);
+    hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, nn, chunks, parts, kp, slice_status, pa,
+                       nullptr, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, const StatPart* parts, int32_t* kp,
+                              int32_t* slice_status, const PrescaleArgs& pa, int32_t* kadd, int32_t* fix_list,
+                              int32_t* fix_count, int32_t* k_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, n * n, chunks, parts, kp, slice_status, pa,
+                       kadd, fix_list, fix_count, k_out);
     return hipGetLastError();
 }
 

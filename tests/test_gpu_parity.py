@@ -252,3 +252,65 @@ def test_n512_all_blocks(op, fmt, B):
     if kg is not None:
         np.testing.assert_array_equal(kg, ko)
     assert_bitexact(yg, yo, "512^2 %s %s B=%d" % (op, fmt, B))
+
+
+def mixed_512_batch():
+    """Slices inside and outside the window where the statistics ride on the
+    unscaled row pass: k-space, tiny, all-zero, huge, single value, heavy-tailed."""
+    ks = synth.kspace_batch(512, 4, 1, 2)
+    one = np.zeros((512, 512), np.complex64)
+    one[7, 300] = 2.5 - 1.0j
+    return np.stack([ks[0],
+                     ks[1] * np.float32(1e-30),
+                     np.zeros((512, 512), np.complex64),
+                     ks[1] * np.float32(1e25),
+                     one,
+                     synth.random_complex((512, 512), seed=41, dist="lognormal")]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e5m2", 8)])
+def test_n512_prescale_paths(op, fmt, B):
+    """512^2 with the prescale: slices whose block exponents stay inside the
+    equivariance window and slices redone literally, in one batch."""
+    x = mixed_512_batch()
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "512^2 mixed %s %s B=%d" % (op, fmt, B))
+
+
+def test_n512_prescale_limits_and_errors():
+    """k pushed outside the window for every slice (k_min), a refinement case,
+    and the non-finite / range errors on the 512^2 path."""
+    ks = synth.kspace_batch(512, 4, 1, 2)
+    yg, kg, st = gpu_run(ks, fmt="e4m3", block=32, k_min=60)
+    so, yo, ko = orc_run(ks, fmt="e4m3", block=32, k_min=60)
+    assert st == mxfft.OK and so == O.OK and (kg == 60).all()
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "512^2 k_min=60")
+    # order statistics either side of a power of two (refinement) at 512^2
+    st2 = np.full(512 * 512, 3.0, np.float32)
+    st2[:8913] = 1.75              # S[8912] = 1.75 and S[8913] = 3.0 straddle a power of two
+    np.random.default_rng(5).shuffle(st2)
+    xs = st2.reshape(1, 512, 512).astype(np.complex64)
+    yg, kg, st = gpu_run(xs, fmt="e4m3", block=16, tau=3.4, tau_min=2.0 ** 10)
+    so, yo, ko = orc_run(xs, fmt="e4m3", block=16, tau=3.4, tau_min=2.0 ** 10)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "512^2 refinement")
+    # non-finite value in one slice; its neighbours unaffected
+    xn = ks.copy()
+    xn[1, 100, 200] = np.inf
+    yg, kg, st = gpu_run(xn, fmt="e4m3", block=32)
+    assert st == mxfft.ENONFINITE and kg[1] == mxfft.INT32_MIN and kg[0] != mxfft.INT32_MIN
+    so, yo, ko = orc_run(xn[:1], fmt="e4m3", block=32)
+    assert_bitexact(yg[:1], yo, "512^2 finite slice beside a non-finite one")
+    # largest component near 2^k limit: ERANGE exactly where the oracle says so
+    kmax_ok = 127 - int(np.floor(np.log2(np.abs(ks[0].view(np.float32)).max())))
+    yg, kg, st = gpu_run(ks[:1], fmt="e4m3", block=32, k_min=kmax_ok)
+    assert st == mxfft.OK and O.prescale(ks[0], k_min=kmax_ok)[0] == O.OK
+    yg, kg, st = gpu_run(ks[:1], fmt="e4m3", block=32, k_min=kmax_ok + 1)
+    assert st == mxfft.ERANGE and O.prescale(ks[0], k_min=kmax_ok + 1)[0] == O.ERANGE
