@@ -305,6 +305,42 @@ struct ERange {
     __device__ __forceinline__ void add(int e) { lo = min(lo, e); hi = max(hi, e); }
 };
 
+// max over the groups of G consecutive lanes (G = 1, 2, 4, 8; within a DPP
+// row) of non-negative values given as bits, every lane receiving its
+// group's value: quad_perm swaps of lanes 1 and 2 apart, then the half-row
+// mirror (lane i <-> 7 - i), which after the first two steps meets the other
+// quad of the 8.  Integer max: non-negative floats order like their bits.
+template <int G>
+__device__ __forceinline__ uint32_t group_max_bits(uint32_t v)
+{
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1..8 lanes");
+    if constexpr (G >= 2) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+    if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+    if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+    return v;
+}
+
+// MX-encode a block of CB consecutive values held two per lane by CB / 2
+// consecutive lanes (v0, v1 of this lane), in place.  Returns E; am is the
+// block maximum.
+template <int F, int CB>
+__device__ __forceinline__ int mx_requant_pair(float2& v0, float2& v1, float& am)
+{
+    uint32_t a;
+    asm("v_max3_f32 %0, |%1|, |%2|, |%3|\n\t"
+        "v_max_f32_e64 %0, %0, |%4|"
+        : "=&v"(a)
+        : "v"(v0.x), "v"(v0.y), "v"(v1.x), "v"(v1.y));
+    a = group_max_bits<CB / 2>(a);
+    am = __uint_as_float(a);
+    const int E = mxd::block_exp<F>(a);
+    const float s = e8(E), lim = lim_of<F>(E);
+    const uint32_t c = enc4<F>(clamp2(v0, lim), clamp2(v1, lim), s);
+    v0 = dec2<F, false>(c, s);
+    v1 = dec2<F, true>(c, s);
+    return E;
+}
+
 struct Tw {
     const float2* tw;      // stage s = b+1, index j at [2^b + j]
     const int32_t* ex;     // twiddle block exponents
@@ -505,7 +541,7 @@ struct alignas(16) RowLds {
     // 8 copies (bin * 8 + lane % 8); bin kStatsBins - 1 collects zeros and non-finite values
     uint32_t hist[KIND == ROW_STATS ? kStatsBins * 8 : 4];
     double m2[WAVES];
-    float mc[WAVES];
+    uint32_t mc[WAVES];
     int nf[WAVES], elo[WAVES], ehi[WAVES];
 };
 
@@ -560,11 +596,12 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             a[rev(Kk, 5)] = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
         });
     } else {
-        // 32 consecutive naturals per lane: MX-encode the pass input in-lane
+        // coalesced loads: lane m of a line holds naturals 32 I + 2 m + e
+        // (e = 0, 1) as v[2 I + e]
         float2 v[P];
-        const float4* x4 = (const float4*)(x + P * m);
+        const float4* x4 = (const float4*)x;
         sfor<P / 2>([&](auto I) {
-            const float4 q = x4[I];
+            const float4 q = x4[16 * I + m];
             if constexpr (ST) {
                 v[2 * I] = make_float2(q.x, q.y);
                 v[2 * I + 1] = make_float2(q.z, q.w);
@@ -573,7 +610,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                 v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
             }
         });
-        float mc = 0.f;
+        uint32_t mcb = 0;   // bits of the largest |part| (statistics)
         if constexpr (ST) {
             // Alg. 1 statistics of the unscaled input: |x|^2 in FP64 (both squares
             // exact, one rounding), its maximum, a non-finite check (the sum of
@@ -598,22 +635,26 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
             if (lane == 0) { L.m2[wave] = m2max; L.nf[wave] = nf; }
         }
-        sfor<P / CB>([&](auto G) {
+        // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive lanes
+        sfor<P / 2>([&](auto I) {
             float am;
-            const int E = mx_requant<F, CB>(v + G * CB, am);
-            if constexpr (ST) { er.add(E); mc = fmaxf(mc, am); }
+            const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);
+            if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
         });
         if constexpr (ST) {
-            mc = wave_reduce_max(mc);
-            if (lane == 0) L.mc[wave] = mc;
+            mcb = wave_reduce_max(mcb);
+            if (lane == 0) L.mc[wave] = mcb;
         }
         // bit reversal into layout 0 through the LDS planes (32-bit stores:
         // lines RLINE words apart)
         float* rplane = s_plane + wave * WPL + line * RLINE;
         sfor<2>([&](auto R) {
             wave_sync();
-            // natural 32m + i sits at position rev5(i) * 16 + rev4(m)
-            sfor<P>([&](auto I) { rplane[swz((rev(I, 5) << 4) | rm)] = R ? v[I].y : v[I].x; });
+            // natural 32 I + 2 m + e sits at position e * 256 + rev4(m) * 16 + rev4(I)
+            sfor<P>([&](auto J) {
+                constexpr int I = J / 2, e = J % 2;
+                rplane[swz((e << 8) | (rm << 4) | rev(I, 4))] = R ? v[J].y : v[J].x;
+            });
             wave_sync();
             sfor<P / 2>([&](auto I) {
                 const float2 q = *(const float2*)&rplane[swz(P * m + 2 * I)];
@@ -727,19 +768,19 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             }
             if (tid == 0) {
                 double m2 = L.m2[0];
-                float mcw = L.mc[0];
+                uint32_t mcw = L.mc[0];
                 int nf = L.nf[0], elo = L.elo[0], ehi = L.ehi[0];
 #pragma unroll
                 for (int w = 1; w < WAVES; w++) {
                     m2 = fmax(m2, L.m2[w]);
-                    mcw = fmaxf(mcw, L.mc[w]);
+                    mcw = max(mcw, L.mc[w]);
                     nf |= L.nf[w];
                     elo = min(elo, L.elo[w]);
                     ehi = max(ehi, L.ehi[w]);
                 }
                 pt->max_m2 = (unsigned long long)__double_as_longlong(m2);
                 pt->count = 0;
-                pt->max_comp = __float_as_uint(mcw);
+                pt->max_comp = mcw;
                 pt->nonfinite = (uint32_t)nf;
                 pt->emin = elo;
                 pt->emax = ehi;
