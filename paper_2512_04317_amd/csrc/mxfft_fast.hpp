@@ -132,23 +132,28 @@ __device__ __forceinline__ int posM(int m)
     return p;
 }
 
-// LDS plane index of position p of a line: bits 1..4 XOR a linear function of
-// bits 5..8, chosen so that in every layout of every block size the 16 lanes
-// of a line reach 16 distinct 8-byte banks with their 64-bit accesses (the LDS
-// serves 64- and 128-bit accesses from 32 banks of 8 bytes, 32-bit ones from
-// 32 banks of 4 bytes); bit 0 is kept so pairs stay adjacent.  Lines sit
-// XLINE words apart (32 words = 16 banks of padding), so the 4 lines of a wave
-// fill all 32 banks twice: conflict-free.
-__device__ __forceinline__ int swz(int p)
+// LDS plane slot of position p of a line: 32-word rows (p >> 5) padded by a
+// sum of per-bit amounts, slot(p) = p + 2 b5 + 4 b6 + 12 b7 + 18 b8 (b_j bit
+// j of p).  The padding grows with the row index, so rows never overlap (548
+// words per line), and it is additive: for p = c | m with disjoint in-lane
+// bits c and lane bits m, slot(p) = slot(c) + slot(m), so every access is a
+// per-lane base plus a compile-time offset, with no address arithmetic per
+// access.  The amounts and the line bases (lines 584 words apart, odd pairs
+// 16 words further) were chosen by enumeration against the LDS bank model of
+// the target (64- and 128-bit accesses served by 32 banks of 8 bytes, 32-bit
+// ones by 32 banks of 4 bytes): the layout exchanges of every block size reach
+// 1.0-1.25 times the conflict-free cycle count (1.06 for blocks of 16
+// butterflies).
+__host__ __device__ constexpr int slot(int p)
 {
-    const int b5 = (p >> 5) & 1, b6 = (p >> 6) & 1, b7 = (p >> 7) & 1, b8 = (p >> 8) & 1;
-    const int s = (b5 ^ b8) | ((b6 ^ b7) << 1) | ((b7 ^ b8) << 2) | (b8 << 3);
-    return p ^ (s << 1);
+    return p + 2 * ((p >> 5) & 1) + 4 * ((p >> 6) & 1) + 12 * ((p >> 7) & 1) + 18 * ((p >> 8) & 1);
 }
 
-constexpr int XLINE = N + 32;            // words per line in the layout exchanges
-constexpr int RLINE = N + 16;            // words per line in the 32-bit bit-reversal stores
-constexpr int WPL = 3 * XLINE + N;       // words of one wave's planes (covers both)
+constexpr int PLINE = 548;               // words spanned by one line's slots
+constexpr int WPL = 3 * 584 + 16 + PLINE; // words of one wave's planes (4 lines)
+static_assert(slot(511) == PLINE - 1, "slot range");
+// base of line l within its wave's planes
+__device__ __forceinline__ int line_base(int l) { return 584 * l + 16 * (l >> 1); }
 
 // pext: the bits of v at the set positions of MASK, packed from bit 0
 template <int MASK>
@@ -188,6 +193,12 @@ __device__ __forceinline__ int tslot(int r, int c)
 // row pass: bits 2..5 XOR bits 4..7, so the 16 lanes of a line (16 different
 // 4-column groups in every final layout) cover all banks.
 __device__ __forceinline__ int csw(int c) { return c ^ (((c >> 4) & 15) << 2); }
+
+// Word swizzle of the MX intermediate: in the 32-byte row segment of a
+// 16-column group, the word of columns 2w, 2w+1 sits at w ^ cswz(row).  The
+// column pass copies a group's 512 rows verbatim into LDS; its 32-bit reads
+// (rows 16k + r for r = 0..15, two words per wave) then reach 32 distinct banks.
+__device__ __forceinline__ int cswz(int row) { return ((row >> 2) & 3) << 1; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -462,32 +473,32 @@ __device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t, ERang
     sfor<b1 - b0>([&](auto I) { stage<F, C, K, b0 + I, INV, TR>(a, m, t, er); });
 }
 
-// Layout K -> K+1 through this wave's LDS planes (re, then im).
+// Layout K -> K+1 through this line's LDS plane (re, then im); addresses are
+// a per-lane base (the lane bits' slot) plus the in-lane bits' slot.
 template <int C, int K>
 __device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
 {
     using Ly = Lay<C>;
-    const int pm0 = posM<C, K>(m), pm1 = posM<C, K + 1>(m);
+    float* w = plane + slot(posM<C, K>(m));
+    const float* r = plane + slot(posM<C, K + 1>(m));
     sfor<2>([&](auto R) {
         wave_sync();
         sfor<P / 2>([&](auto I) {
             constexpr int o = 2 * I;
-            const int p = Ly::posF(K, o) | pm0;
             const float2 v = R ? make_float2(a[o].y, a[o + 1].y) : make_float2(a[o].x, a[o + 1].x);
-            *(float2*)&plane[swz(p)] = v;
+            *(float2*)&w[slot(Ly::posF(K, o))] = v;
         });
         wave_sync();
         sfor<P / 2>([&](auto I) {
             constexpr int o = 2 * I;
-            const int p = Ly::posF(K + 1, o) | pm1;
-            const float2 v = *(const float2*)&plane[swz(p)];
+            const float2 v = *(const float2*)&r[slot(Ly::posF(K + 1, o))];
             if (R) { a[o].y = v.x; a[o + 1].y = v.y; }
             else { a[o].x = v.x; a[o + 1].x = v.y; }
         });
     });
 }
 
-// plane: this line's exchange plane (XLINE words apart per line)
+// plane: this line's exchange plane (line_base within the wave's planes)
 template <int F, int C, bool INV, bool TR = false>
 __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane, ERange& er)
 {
@@ -505,7 +516,7 @@ __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, f
 struct FastArgs {
     const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
     float2* dst;             // complex64 output (row pass FP32 form / column pass)
-    uint32_t* codes;         // MX intermediate: [slice][cg][row][cb] code pairs (2 bytes each)
+    uint32_t* codes;         // MX intermediate: [slice][16-column group][row][8 words of 2 code pairs], swizzled
     uint8_t* exps;           // MX intermediate: [slice][row block][column] E8M0 bytes
     const int32_t* kp;       // per-slice prescale exponent or nullptr
     int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
@@ -583,7 +594,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     const int kin = ST ? 0 : g.kin_mul * kp;
     if (KIND == ROW_PLAIN && g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
     const float2* x = g.src + ((size_t)slice * N + row) * N;
-    float* plane = s_plane + wave * WPL + line * XLINE;
+    float* plane = s_plane + wave * WPL + line_base(line);
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
@@ -645,19 +656,19 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
         }
-        // bit reversal into layout 0 through the LDS planes (32-bit stores:
-        // lines RLINE words apart)
-        float* rplane = s_plane + wave * WPL + line * RLINE;
+        // bit reversal into layout 0 through the LDS plane
+        float* wb = plane + slot(rm << 4);
+        const float* rbp = plane + slot(P * m);
         sfor<2>([&](auto R) {
             wave_sync();
             // natural 32 I + 2 m + e sits at position e * 256 + rev4(m) * 16 + rev4(I)
             sfor<P>([&](auto J) {
                 constexpr int I = J / 2, e = J % 2;
-                rplane[swz((e << 8) | (rm << 4) | rev(I, 4))] = R ? v[J].y : v[J].x;
+                wb[slot((e << 8) | rev(I, 4))] = R ? v[J].y : v[J].x;
             });
             wave_sync();
             sfor<P / 2>([&](auto I) {
-                const float2 q = *(const float2*)&rplane[swz(P * m + 2 * I)];
+                const float2 q = *(const float2*)&rbp[slot(2 * I)];
                 if (R) { a[2 * I].y = q.x; a[2 * I + 1].y = q.y; }
                 else { a[2 * I].x = q.x; a[2 * I + 1].x = q.y; }
             });
@@ -740,17 +751,17 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                                   __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), sb);
                 w[H] = r;
             });
-            // [cg][row][cb] with cg = col0 / CB
-            uint32_t* dstw = cd + (((size_t)(col0 / CB) * N + row) * CB) / 2;
-            if constexpr (CB == 16) {
-                ((uint4*)dstw)[0] = make_uint4(w[0], w[1], w[2], w[3]);
-                ((uint4*)dstw)[1] = make_uint4(w[4], w[5], w[6], w[7]);
-            } else if constexpr (CB == 8) {
-                ((uint4*)dstw)[0] = make_uint4(w[0], w[1], w[2], w[3]);
-            } else if constexpr (CB == 4) {
-                ((uint2*)dstw)[0] = make_uint2(w[0], w[1]);
+            // [16-column group][row][8 words], word of columns 2w, 2w+1 of the
+            // group at position w ^ cswz(row)
+            uint32_t* dstw = cd + ((size_t)(col0 / 16) * N + row) * 8;
+            const int sw = cswz(row);
+            if constexpr (CB >= 4) {
+                sfor<CB / 4>([&](auto Q) {
+                    const int q = ((col0 % 16) / 4 + Q) ^ (sw >> 1);
+                    ((uint2*)dstw)[q] = make_uint2(w[2 * Q], w[2 * Q + 1]);
+                });
             } else {
-                dstw[0] = w[0];
+                dstw[((col0 % 16) / 2) ^ sw] = w[0];
             }
         });
         if constexpr (ST) {
@@ -812,7 +823,6 @@ __global__ __launch_bounds__(256) void k_row_fix(FastArgs g)
 template <int F, int C, bool INV>
 __global__ __launch_bounds__(256) void k_col(FastArgs g)
 {
-    constexpr int TSTR = 9;                            // LDS words per code-tile row (8 + pad)
     constexpr int CB = 1 << C;
     constexpr int NRB = N / CB;                        // row blocks per column
     __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; input and output tiles
@@ -823,7 +833,7 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
     const int cl = wave * LPW + line;                  // column within the work-group
     const int kp = slice_k(g, slice);
     const int kout = g.kout_mul * kp + g.kout_add;
-    float* plane = s_plane + wave * WPL + line * XLINE;
+    float* plane = s_plane + wave * WPL + line_base(line);
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
@@ -850,29 +860,25 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         });
         __syncthreads();
     } else {
-        // code tile of the 16 columns: 16 / CB column groups of [row][CB] pairs
+        // code tile of the 16 columns ([row][8 words], swizzled by the row
+        // pass): copied verbatim, 16 bytes per thread and step
         uint32_t* ctile = (uint32_t*)s_plane;
-        const uint32_t* cd = g.codes + ((size_t)slice * N * N + (size_t)cb16 * LINES * N) / 2;
-        for (int i = tid; i < LINES * N / 8; i += 256) {            // 16-byte pieces
-            const uint4 q = ((const uint4*)cd)[i];
-            const int word0 = i * 4;                                // in units of code pairs / 2
-            sfor<4>([&](auto W) {
-                const int pair = 2 * (word0 + W);                  // first code pair of this word
-                const int cgi = pair / (N * CB), rem = pair % (N * CB);
-                const int r = rem / CB, c = cgi * CB + rem % CB;   // row and column (0..15)
-                const uint32_t val = W == 0 ? q.x : W == 1 ? q.y : W == 2 ? q.z : q.w;
-                ctile[r * TSTR + c / 2] = val;
-            });
-        }
+        const uint4* cd = (const uint4*)(g.codes + ((size_t)slice * N * N + (size_t)cb16 * LINES * N) / 2);
+        static_assert(LINES * N / 8 == 4 * 256, "four 16-byte pieces per thread");
+        const uint4 q0 = cd[tid], q1 = cd[256 + tid], q2 = cd[512 + tid], q3 = cd[768 + tid];
         // exponents [slice][row block][column]: 16 bytes per row block
         const uint8_t* ex = g.exps + (size_t)slice * NRB * N + cb16 * LINES;
         for (int i = tid; i < NRB; i += 256) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
         // stored exponents of a row pass that ran unscaled are offset by kadd
         const int eadd = g.kadd ? g.kadd[slice] : 0;
+        ((uint4*)ctile)[tid] = q0;
+        ((uint4*)ctile)[256 + tid] = q1;
+        ((uint4*)ctile)[512 + tid] = q2;
+        ((uint4*)ctile)[768 + tid] = q3;
         __syncthreads();
         sfor<P>([&](auto O) {
             const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
-            const uint32_t wd = ctile[n * TSTR + cl / 2];
+            const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
             const float s = __uint_as_float((uint32_t)((int)s_ex[(n / CB) * 16 + cl] + eadd) << 23);
             a[O] = (cl & 1) ? dec2<F, true>(wd, s) : dec2<F, false>(wd, s);
         });

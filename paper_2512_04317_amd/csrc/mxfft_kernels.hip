@@ -147,15 +147,22 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
         s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0;
         s_emin = 0; s_emax = 0;
     }
+    for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    uint32_t cnt = 0;
-    for (int i = tid; i < kStatsBins; i += blockDim.x) {
-        uint32_t h = 0;
-        for (int c = 0; c < chunks; c++) h += pt[c].hist[i];
-        hist[i] = h;
-        cnt += h;
+    // histograms of all chunks, read as one coalesced sweep (many loads in
+    // flight per thread) and summed per bin in LDS
+    {
+        const int total = chunks * kStatsBins;
+        uint32_t cnt = 0;
+#pragma unroll 8
+        for (int w = tid; w < total; w += blockDim.x) {
+            const int c = w / kStatsBins, i = w - c * kStatsBins;
+            const uint32_t h = pt[c].hist[i];
+            if (h) atomicAdd(&hist[i], h);
+            cnt += h;
+        }
+        atomicAdd(&s_count, cnt);
     }
-    atomicAdd(&s_count, cnt);
     for (int c = tid; c < chunks; c += blockDim.x) {
         atomicMax(&s_m2, pt[c].max_m2);
         atomicMax(&s_maxc, pt[c].max_comp);
