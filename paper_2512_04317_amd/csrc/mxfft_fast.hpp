@@ -361,22 +361,38 @@ struct Tw {
 // ---------------------------------------------------------------------------
 // one radix-2 stage (butterfly position bit B) in layout K
 // ---------------------------------------------------------------------------
-template <int F, int C, int K, int B, bool INV, bool TR>
+// LC: layout family (Lay<LC>); BC: log2 of butterflies per MX block.  With
+// BC = LC + 1 the layouts after the first hold LC block bits in-lane and the
+// last block bit in lane bit 0 (position bit LC is the lowest lane bit there):
+// each lane then works on half-blocks and the two block maxima (of v and of
+// the products) are completed with one DPP exchange between lanes m, m ^ 1.
+template <int F, int LC, int BC, int K, int B, bool INV, bool TR>
 __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
-    using Ly = Lay<C>;
+    using Ly = Lay<LC>;
+    constexpr bool SPLIT = (K > 0) && (BC > LC);
+    static_assert(BC <= LC + 1, "a block spans at most two lanes");
+    static_assert(!SPLIT || Ly::xbit(K, 0) == LC, "last block bit in lane bit 0");
+    constexpr int C = SPLIT ? LC : BC;                 // block bits held in-lane
     constexpr int ob = Ly::index_of(K, B);
     static_assert(ob >= 0, "butterfly bit must be in-lane");
     constexpr int h = 1 << B;
-    constexpr int CB = 1 << C;
+    constexpr int CB = 1 << C;                         // butterflies per (half-)block in a lane
     constexpr int fbb = (B > C) ? B : C;
     constexpr int obb = Ly::index_of(K, fbb);
     static_assert(obb >= 0, "block must be in-lane");
+    static_assert(!SPLIT || B > BC, "split blocks only in the later layouts");
     constexpr int FREE = (CB - 1) | (1 << obb);        // in-lane bits of one block
     constexpr int BFLY = FREE & ~(1 << ob);            // bits enumerating its butterflies
     constexpr int OTHER = (P - 1) & ~FREE;             // bits enumerating blocks
     constexpr int NBLK = P / (2 * CB);
-    const int jm = posM<C, K>(m) & (h - 1);           // lane part of j
+    const int jm = posM<LC, K>(m) & (h - 1);          // lane part of j
+    // block maximum (bits of a non-negative float): across the lane pair when split
+    auto bmax = [&](float v) -> uint32_t {
+        uint32_t u = __float_as_uint(v);
+        if constexpr (SPLIT) u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, true));
+        return u;
+    };
 
     sfor<NBLK>([&](auto BLK) {
         constexpr int base = deposit(BLK, OTHER);
@@ -400,6 +416,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
         } else if constexpr (B <= 1) {
             // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
             // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
+            static_assert(!SPLIT, "stages 1 and 2 run in the first layout");
             const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
             if constexpr (TR) er.add(Ev);
@@ -416,10 +433,9 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
             });
         } else {
             constexpr int jc0 = Ly::posF(K, base) & (h - 1);
-            const int Ew = t.ex[t.off[B + 1] + ((CB <= h) ? ((jm | jc0) >> C) : 0)];
+            const int Ew = t.ex[t.off[B + 1] + (((1 << BC) <= h) ? ((jm | jc0) >> BC) : 0)];
             // operand v: EncodeBlockMX, element values as FP32 mantissas
-            const float am = amax_of<CB>(V);
-            const int Ev = mxd::block_exp<F>(__float_as_uint(am));
+            const int Ev = mxd::block_exp<F>(bmax(amax_of<CB>(V)));
             if constexpr (TR) er.add(Ev);
             const float s = e8(Ev), lim = lim_of<F>(Ev);
             float2 Pp[CB];
@@ -435,8 +451,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
                 Pp[T].x = x.x * y.x - xi * y.y;
                 Pp[T].y = x.x * y.y + xi * y.x;
             });
-            const float ap = amax_of<CB>(Pp);
-            const int kr = mxd::renorm_exp<F>(__float_as_uint(ap));
+            const int kr = mxd::renorm_exp<F>(bmax(amax_of<CB>(Pp)));
             const float sp = e8(kr);
             const int Eo = Ew + Ev + kr;
             if (__builtin_expect(Eo >= -127, 1)) {
@@ -466,11 +481,11 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
 }
 
 // all stages of layout K
-template <int F, int C, int K, bool INV, bool TR>
+template <int F, int LC, int BC, int K, bool INV, bool TR>
 __device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
-    constexpr int b0 = Lay<C>::bfirst(K), b1 = Lay<C>::blast(K);
-    sfor<b1 - b0>([&](auto I) { stage<F, C, K, b0 + I, INV, TR>(a, m, t, er); });
+    constexpr int b0 = Lay<LC>::bfirst(K), b1 = Lay<LC>::blast(K);
+    sfor<b1 - b0>([&](auto I) { stage<F, LC, BC, K, b0 + I, INV, TR>(a, m, t, er); });
 }
 
 // Layout K -> K+1 through this line's LDS plane (re, then im); addresses are
@@ -499,15 +514,21 @@ __device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
 }
 
 // plane: this line's exchange plane (line_base within the wave's planes)
-template <int F, int C, bool INV, bool TR = false>
+template <int F, int LC, int BC, bool INV, bool TR = false>
 __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane, ERange& er)
 {
-    using Ly = Lay<C>;
+    using Ly = Lay<LC>;
     sfor<Ly::NL>([&](auto K) {
-        if constexpr (K > 0) exchange<C, K - 1>(a, m, plane);
-        stages<F, C, K, INV, TR>(a, m, t, er);
+        if constexpr (K > 0) exchange<LC, K - 1>(a, m, plane);
+        stages<F, LC, BC, K, INV, TR>(a, m, t, er);
     });
 }
+
+// Layout family of a pass with blocks of 2^C butterflies: blocks of 16 use
+// the layouts of blocks of 8 (two layout exchanges instead of four) with each
+// block split over a lane pair.
+template <int F, int C>
+constexpr int layout_family() { return F == FP32 ? 1 : (C == 4 ? 3 : C); }
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -546,11 +567,11 @@ __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
 template <int F, int C, int KIND>
 struct alignas(16) RowLds {
     static constexpr int NSB = (F == FP32) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
-    float plane[WAVES * WPL];          // exchange planes; then column maxima
+    // exchange planes; before them the statistics histogram (row pass with
+    // statistics only: 8 copies, bin * 8 + lane % 8; bin kStatsBins - 1 collects
+    // zeros and non-finite values); after them the column maxima
+    float plane[WAVES * WPL];
     float sc[NSB * N];                 // column block scales 2^E (MX)
-    // prescale statistics (row pass with statistics only): binade histogram,
-    // 8 copies (bin * 8 + lane % 8); bin kStatsBins - 1 collects zeros and non-finite values
-    uint32_t hist[KIND == ROW_STATS ? kStatsBins * 8 : 4];
     double m2[WAVES];
     uint32_t mc[WAVES];
     int nf[WAVES], elo[WAVES], ehi[WAVES];
@@ -595,6 +616,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     if (KIND == ROW_PLAIN && g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
     const float2* x = g.src + ((size_t)slice * N + row) * N;
     float* plane = s_plane + wave * WPL + line_base(line);
+    uint32_t* hist = (uint32_t*)s_plane;                 // statistics only, before the planes are used
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
     Tw t{g.tw, g.tw_exp, g.tw_off};
     float2 a[P];
@@ -628,7 +650,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // the squares is finite iff every part is), and the binade histogram
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
-            for (int i = tid; i < kStatsBins * 8 / 4; i += 256) ((uint4*)L.hist)[i] = make_uint4(0, 0, 0, 0);
+            static_assert(kStatsBins * 8 <= WAVES * WPL, "histogram fits the planes");
+            for (int i = tid; i < kStatsBins * 8 / 4; i += 256) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
             double m2max = 0.0, m2sum = 0.0;
@@ -640,7 +663,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                 // zero (e = 0) and non-finite (e = 2047) land in the last bin
                 const uint32_t hi = (uint32_t)((unsigned long long)__double_as_longlong(m2) >> 32);
                 const uint32_t bin = min(((hi >> 20) - 725u) >> 1, (uint32_t)(kStatsBins - 1));
-                atomicAdd(&L.hist[bin * 8 + (lane & 7)], 1u);
+                atomicAdd(&hist[bin * 8 + (lane & 7)], 1u);
             });
             m2max = wave_reduce_max(m2max);
             const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
@@ -655,6 +678,18 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         if constexpr (ST) {
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
+            // the tile's histogram to its part (the planes are needed next):
+            // sum the 8 copies of bin i, copy order skewed by i / 4 so a wave's
+            // reads fall in 32 different banks
+            __syncthreads();
+            StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
+            for (int i = tid; i < kStatsBins; i += 256) {
+                uint32_t h = 0;
+#pragma unroll
+                for (int c = 0; c < 8; c++) h += hist[i * 8 + ((c + (i >> 2)) & 7)];
+                pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
+            }
+            __syncthreads();
         }
         // bit reversal into layout 0 through the LDS plane
         float* wb = plane + slot(rm << 4);
@@ -675,9 +710,9 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         });
     }
 
-    all_stages<F, (F == FP32 ? 1 : C), INV, ST>(a, m, t, plane, er);
+    constexpr int CL = layout_family<F, C>();
+    all_stages<F, CL, (F == FP32 ? 1 : C), INV, ST>(a, m, t, plane, er);
 
-    constexpr int CL = (F == FP32) ? 1 : C;
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
     if constexpr (F == FP32) {
@@ -688,12 +723,12 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         // rows of one column; this work-group holds NSB such blocks.
         // 1. per-element max(|re|, |im|) into a [16][512] array (column-swizzled);
         //    VW consecutive columns per lane are in-lane offset bits 0..log2(VW)-1
-        constexpr int VW = (C >= 2) ? 4 : 2;
+        constexpr int VW = (CL >= 2) ? 4 : 2;
         float* s_m = s_plane;
         __syncthreads();                                   // every wave is done with its planes
         sfor<P / VW>([&](auto G) {
             constexpr int o0 = deposit(G, (P - 1) & ~(VW - 1));
-            const int c0 = Lay<C>::posF(KL, o0) | pmL;
+            const int c0 = Lay<CL>::posF(KL, o0) | pmL;
             float mv[VW];
             sfor<VW>([&](auto J) { mv[J] = fmaxf(fabsf(a[o0 + J].x), fabsf(a[o0 + J].y)); });
             float* d = &s_m[rl * N + csw(c0)];
@@ -724,12 +759,13 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         constexpr uint32_t LIMADD = ((uint32_t)mxd::Elem<F>::EMAX << 23) | 0x00600000u;
         const float* my_sc = s_sc + (rl / CB) * N;
         uint32_t* cd = g.codes + ((size_t)slice * N * N) / 2;
-        // in-lane column groups: offsets with bits 0..C-1 consecutive columns
-        sfor<P / CB>([&](auto G) {
-            constexpr int o0 = deposit(G, (P - 1) & ~(CB - 1));
-            const int col0 = Lay<C>::posF(KL, o0) | pmL;      // first column of the group
-            float sc[CB];
-            sfor<CB / VW>([&](auto J) {
+        // in-lane column groups: CG consecutive columns (in-lane offset bits 0..CL-1)
+        constexpr int CG = 1 << CL;
+        sfor<P / CG>([&](auto G) {
+            constexpr int o0 = deposit(G, (P - 1) & ~(CG - 1));
+            const int col0 = Lay<CL>::posF(KL, o0) | pmL;      // first column of the group
+            float sc[CG];
+            sfor<CG / VW>([&](auto J) {
                 const float* src = &my_sc[csw(col0 + VW * J)];
                 if constexpr (VW == 4) {
                     const float4 q = *(const float4*)src;
@@ -739,8 +775,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                     sc[2 * J] = q.x; sc[2 * J + 1] = q.y;
                 }
             });
-            uint32_t w[CB / 2];
-            sfor<CB / 2>([&](auto H) {
+            uint32_t w[CG / 2];
+            sfor<CG / 2>([&](auto H) {
                 constexpr int oa = o0 + 2 * H, obx = oa + 1;
                 const float sa = sc[2 * H], sb = sc[2 * H + 1];
                 const float la = __uint_as_float(__float_as_uint(sa) + LIMADD);
@@ -755,8 +791,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // group at position w ^ cswz(row)
             uint32_t* dstw = cd + ((size_t)(col0 / 16) * N + row) * 8;
             const int sw = cswz(row);
-            if constexpr (CB >= 4) {
-                sfor<CB / 4>([&](auto Q) {
+            if constexpr (CG >= 4) {
+                sfor<CG / 4>([&](auto Q) {
                     const int q = ((col0 % 16) / 4 + Q) ^ (sw >> 1);
                     ((uint2*)dstw)[q] = make_uint2(w[2 * Q], w[2 * Q + 1]);
                 });
@@ -769,14 +805,6 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             if (lane == 0) { L.elo[wave] = lo; L.ehi[wave] = hi; }
             __syncthreads();
             StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
-            // sum the 8 copies of bin i; copy order skewed by i / 4 so a wave's
-            // reads fall in 32 different banks
-            for (int i = tid; i < kStatsBins; i += 256) {
-                uint32_t h = 0;
-#pragma unroll
-                for (int c = 0; c < 8; c++) h += L.hist[i * 8 + ((c + (i >> 2)) & 7)];
-                pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
-            }
             if (tid == 0) {
                 double m2 = L.m2[0];
                 uint32_t mcw = L.mc[0];
@@ -886,12 +914,12 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
     }
 
     ERange er;
-    all_stages<F, (F == FP32 ? 1 : C), INV>(a, m, t, plane, er);
+    constexpr int CL = layout_family<F, C>();
+    all_stages<F, CL, (F == FP32 ? 1 : C), INV>(a, m, t, plane, er);
 
     // output: scaled by 2^kout, staged through an LDS tile 256 rows at a time
     // (row bit 8 is an in-lane bit of the last layout) and written as whole
     // 128-byte row pieces
-    constexpr int CL = (F == FP32) ? 1 : C;
     constexpr int KL = Lay<CL>::NL - 1;
     constexpr int HB = Lay<CL>::index_of(KL, LOGN - 1);
     constexpr int LM = lane_mask<CL, KL>();
