@@ -124,6 +124,12 @@ mxfft_status mxfft_plan_last_status(mxfft_plan_t plan, void* stream);
  * Enabling resets the accumulated times; disabling keeps them. */
 mxfft_status mxfft_plan_profile(mxfft_plan_t plan, int32_t enable);
 
+/* As mxfft_plan_profile, timing only the launches whose role bit is set in
+ * role_mask (0 disables): bit 0 prescale_stats, 1 row_pass, 2 column_pass,
+ * 3 inverse_row_pass, 4 inverse_column_pass, 5 row_redo.  Fewer event pairs
+ * disturb the timed launches less. */
+mxfft_status mxfft_plan_profile_roles(mxfft_plan_t plan, uint32_t role_mask);
+
 typedef struct {
     char name[32];       /* kernel role, e.g. "prescale_stats", "row_pass" */
     uint64_t launches;   /* launches timed since profiling was enabled */

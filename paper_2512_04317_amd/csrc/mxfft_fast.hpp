@@ -568,8 +568,9 @@ template <int F, int C, int KIND>
 struct alignas(16) RowLds {
     static constexpr int NSB = (F == FP32) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
     // exchange planes; before them the statistics histogram (row pass with
-    // statistics only: 8 copies, bin * 8 + lane % 8; bin kStatsBins - 1 collects
-    // zeros and non-finite values); after them the column maxima
+    // statistics only: 32 copies, bin * 32 + lane % 32, so only lanes l and
+    // l + 32 can meet on an address; bin kStatsBins - 1 collects zeros and
+    // non-finite values); after them the column maxima
     float plane[WAVES * WPL];
     float sc[NSB * N];                 // column block scales 2^E (MX)
     double m2[WAVES];
@@ -650,8 +651,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // the squares is finite iff every part is), and the binade histogram
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
-            static_assert(kStatsBins * 8 <= WAVES * WPL, "histogram fits the planes");
-            for (int i = tid; i < kStatsBins * 8 / 4; i += 256) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
+            static_assert(kStatsBins * 32 <= WAVES * WPL, "histogram fits the planes");
+            for (int i = tid; i < kStatsBins * 32 / 4; i += 256) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
             double m2max = 0.0, m2sum = 0.0;
@@ -663,7 +664,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                 // zero (e = 0) and non-finite (e = 2047) land in the last bin
                 const uint32_t hi = (uint32_t)((unsigned long long)__double_as_longlong(m2) >> 32);
                 const uint32_t bin = min(((hi >> 20) - 725u) >> 1, (uint32_t)(kStatsBins - 1));
-                atomicAdd(&hist[bin * 8 + (lane & 7)], 1u);
+                atomicAdd(&hist[bin * 32 + (lane & 31)], 1u);
             });
             m2max = wave_reduce_max(m2max);
             const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
@@ -679,14 +680,14 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
             // the tile's histogram to its part (the planes are needed next):
-            // sum the 8 copies of bin i, copy order skewed by i / 4 so a wave's
+            // sum the 32 copies of bin i, copy order skewed by i so a wave's
             // reads fall in 32 different banks
             __syncthreads();
             StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
             for (int i = tid; i < kStatsBins; i += 256) {
                 uint32_t h = 0;
-#pragma unroll
-                for (int c = 0; c < 8; c++) h += hist[i * 8 + ((c + (i >> 2)) & 7)];
+#pragma unroll 8
+                for (int c = 0; c < 32; c++) h += hist[i * 32 + ((c + i) & 31)];
                 pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
             }
             __syncthreads();
@@ -904,11 +905,18 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         ((uint4*)ctile)[512 + tid] = q2;
         ((uint4*)ctile)[768 + tid] = q3;
         __syncthreads();
+        // exponent bytes of this wave's 4 columns come as one dword per row
+        // block (every lane of the wave reads the same dword: a broadcast;
+        // byte reads of one dword by many lanes serialise)
+        const uint32_t* s_ex4 = (const uint32_t*)s_ex + wave;
+        const int exsh = 8 * line;
+        const int cdsh = 16 * (cl & 1);                     // this column's code pair within the word
         sfor<P>([&](auto O) {
             const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
             const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
-            const float s = __uint_as_float((uint32_t)((int)s_ex[(n / CB) * 16 + cl] + eadd) << 23);
-            a[O] = (cl & 1) ? dec2<F, true>(wd, s) : dec2<F, false>(wd, s);
+            const int eb = (int)((s_ex4[(n / CB) * 4] >> exsh) & 0xffu);
+            const float s = __uint_as_float((uint32_t)(eb + eadd) << 23);
+            a[O] = dec2<F, false>(wd >> cdsh, s);
         });
         __syncthreads();
     }

@@ -106,6 +106,7 @@ struct mxfft_plan_s {
         hipEvent_t start, stop;
     };
     bool profiling = false;
+    uint32_t profile_mask = 0;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> spare;
     uint64_t launches[8] = {};
@@ -138,14 +139,14 @@ struct LaunchTimer {
     hipEvent_t a = nullptr, b = nullptr;
     LaunchTimer(mxfft_plan_s* p, int r, hipStream_t st) : pl(p), role(r), s(st)
     {
-        if (!pl->profiling) return;
+        if (!pl->profiling || !((pl->profile_mask >> r) & 1u)) return;
         a = take_event(pl);
         b = take_event(pl);
         if (a && b) (void)hipEventRecord(a, s);
     }
     ~LaunchTimer()
     {
-        if (!pl->profiling || !a || !b) return;
+        if (!a || !b) return;
         (void)hipEventRecord(b, s);
         pl->pending.push_back({role, a, b});
     }
@@ -557,19 +558,26 @@ mxfft_status mxfft_plan_last_status(mxfft_plan_t pl, void* stream)
     return MXFFT_OK;
 }
 
-mxfft_status mxfft_plan_profile(mxfft_plan_t pl, int32_t enable)
+mxfft_status mxfft_plan_profile_roles(mxfft_plan_t pl, uint32_t role_mask)
 {
     if (!pl) return MXFFT_EINVAL;
     if (hipDeviceSynchronize() != hipSuccess) return MXFFT_EHIP;
     collect_times(pl);
-    if (enable) {
+    role_mask &= (1u << ROLE_COUNT) - 1u;
+    if (role_mask) {
         for (int r = 0; r < ROLE_COUNT; r++) {
             pl->launches[r] = 0;
             pl->total_ms[r] = 0.0;
         }
     }
-    pl->profiling = enable != 0;
+    pl->profiling = role_mask != 0;
+    pl->profile_mask = role_mask;
     return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_profile(mxfft_plan_t pl, int32_t enable)
+{
+    return mxfft_plan_profile_roles(pl, enable ? ~0u : 0u);
 }
 
 mxfft_status mxfft_plan_kernel_times(mxfft_plan_t pl, mxfft_kernel_time* out, int32_t cap, int32_t* count)

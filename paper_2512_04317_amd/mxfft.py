@@ -21,7 +21,12 @@ INT32_MIN, INT32_MAX = -(2 ** 31), 2 ** 31 - 1
 # Every entry point declared in include/mxfft.h.
 EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_forward",
            "mxfft_inverse", "mxfft_roundtrip", "mxfft_plan_last_status", "mxfft_plan_profile",
+           "mxfft_plan_profile_roles",
            "mxfft_plan_kernel_times", "mxfft_plan_device_bytes", "mxfft_status_string", "mxfft_version")
+
+
+# kernel roles reported by Plan.kernel_times (bit order of mxfft_plan_profile_roles)
+ROLES = ("prescale_stats", "row_pass", "column_pass", "inverse_row_pass", "inverse_column_pass", "row_redo")
 
 
 class Params(ctypes.Structure):
@@ -66,6 +71,8 @@ def lib():
         L.mxfft_plan_last_status.argtypes = [P, P]
         L.mxfft_plan_profile.restype = i32
         L.mxfft_plan_profile.argtypes = [P, i32]
+        L.mxfft_plan_profile_roles.restype = i32
+        L.mxfft_plan_profile_roles.argtypes = [P, ctypes.c_uint32]
         L.mxfft_plan_kernel_times.restype = i32
         L.mxfft_plan_kernel_times.argtypes = [P, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
         L.mxfft_plan_device_bytes.restype = ctypes.c_uint64
@@ -174,9 +181,16 @@ class Plan:
     def last_status(self, stream=None):
         return lib().mxfft_plan_last_status(self.handle, _stream(stream))
 
-    def profile(self, enable=True):
-        """Start (resetting) or stop event timing of every kernel launch."""
-        st = lib().mxfft_plan_profile(self.handle, int(bool(enable)))
+    def profile(self, enable=True, roles=None):
+        """Start (resetting) or stop event timing of the kernel launches: all
+        of them, or only those whose role is named in `roles`."""
+        if roles is None:
+            st = lib().mxfft_plan_profile(self.handle, int(bool(enable)))
+        else:
+            mask = 0
+            for r in roles:
+                mask |= 1 << ROLES.index(r)
+            st = lib().mxfft_plan_profile_roles(self.handle, mask if enable else 0)
         if st != OK:
             raise MxfftError(st, "mxfft_plan_profile")
 
