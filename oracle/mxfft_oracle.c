@@ -137,6 +137,7 @@ double orc_decode_code(int f, int c)
 static double sum_round_odd(double a, double b)
 {
     double s = a + b;
+    if (!isfinite(s)) return s;         /* IEEE: infinite and NaN sums need no rounding */
     double bb = s - a;
     double err = (a - (s - bb)) + (b - bb);
     if (err != 0.0) {

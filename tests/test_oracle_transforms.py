@@ -180,6 +180,19 @@ def test_fp16_bf16_controls_are_accurate():
     assert nrmse(y16, ref) < 5e-3 and nrmse(yb16, ref) < 3e-2
 
 
+def test_fp16_overflow_follows_ieee():
+    """Infinities from the half form's overflow propagate as IEEE FP32 sums
+    do: -inf + finite = -inf, never NaN.  Hand-worked 2 x 2 case (forward, no
+    prescale): row 0 sums to -120000, which rounds to -inf in half; the column
+    butterfly then adds and subtracts the finite 2 of row 1."""
+    x = np.array([[[-60000.0, -60000.0], [1.0, 1.0]]], np.complex64)
+    st, y, _ = O.transform(x, mode=O.MODE_FP16, flags=O.NO_PRESCALE)
+    assert st == O.OK
+    assert y[0, 0, 0].real == -np.inf and y[0, 1, 0].real == -np.inf
+    assert not np.isnan(y).any()
+    assert y[0, 0, 1].real == 0.0 and y[0, 1, 1].real == 0.0
+
+
 def test_errors():
     x = np.zeros((8, 8), np.complex64)
     assert O.transform(x, B=16)[0] == O.EINVAL            # B > N
