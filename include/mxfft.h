@@ -33,13 +33,18 @@ extern "C" {
 #endif
 
 /* Element / arithmetic format (Sec. 2.2; Fig. 1C).  E4M3 and E5M2 are the OCP
- * 8-bit elements of MXFP8.  FP32 is the plain single-precision form of the same
- * radix-2 FFT (the comparison baseline, no quantisation). */
+ * 8-bit elements of MXFP8.  FP16 and BF16 are the 16-bit forms the paper
+ * compares against (Sec. 2.3): every pass input, every twiddle (rounded once
+ * from FP64), each stage's v operand and each product and sum of the complex
+ * product are rounded to the format (IEEE round to nearest even, overflow to
+ * infinity); u +/- p stays FP32 and the output is rounded to the format.  The
+ * block size is ignored for them.  FP32 is the plain single-precision form of
+ * the same radix-2 FFT (the comparison baseline, no quantisation). */
 typedef enum {
     MXFFT_E4M3 = 0,
     MXFFT_E5M2 = 1,
-    MXFFT_FP16 = 2,   /* reserved: the 16-bit positive control of Sec. 2.2 */
-    MXFFT_BF16 = 3,   /* reserved */
+    MXFFT_FP16 = 2,
+    MXFFT_BF16 = 3,
     MXFFT_FP32 = 4
 } mxfft_format;
 

@@ -6,6 +6,7 @@
 // FP32), so codes need never be materialised except where they are stored.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -75,5 +76,60 @@ __device__ __forceinline__ uint32_t group_max(uint32_t v, int width)
     for (int o = 1; o < width; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
+
+// ---------------------------------------------------------------------------
+// IEEE half and bfloat16 (the 16-bit forms of the comparison, Sec. 2.3):
+// round to nearest even, overflow to infinity, subnormals kept.
+// ---------------------------------------------------------------------------
+
+// x rounded to IEEE half (hardware conversion, round to nearest even)
+__device__ __forceinline__ float round_fp16(float x) { return __half2float(__float2half_rn(x)); }
+
+// x rounded to bfloat16: round to nearest even on the FP32 bits (NaN kept)
+__device__ __forceinline__ float round_bf16(float x)
+{
+    uint32_t b = __float_as_uint(x);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return x;
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return __uint_as_float(b & 0xffff0000u);
+}
+
+// M: 2 half, 3 bfloat16
+template <int M>
+__device__ __forceinline__ float round16(float x)
+{
+    if constexpr (M == 2) return round_fp16(x);
+    else return round_bf16(x);
+}
+
+// The format's rounding of the exact product of two of its values.  Half
+// products are exact in FP32 (22 significant bits, at least 2^-48).  Bfloat16
+// products are exact in FP32 while normal (16 bits); below 2^-126 the FP32
+// product may already be rounded, so the exact FP64 product is rounded to the
+// bfloat16 subnormal grid 2^-133 instead.
+template <int M>
+__device__ __forceinline__ float mul16(float a, float b)
+{
+    // the empty asm keeps the product an FP32 multiply: folded into the
+    // conversion it becomes a mixed FMA with a +0 addend, which turns a -0
+    // product into +0
+    float p = a * b;
+    asm volatile("" : "+v"(p));
+    if constexpr (M == 3) {
+        if (__builtin_expect(fabsf(p) < 0x1p-126f, 0) && a != 0.f && b != 0.f) {
+            const double q = __builtin_rint((double)a * (double)b * 0x1p133) * 0x1p-133;
+            return (float)q;
+        }
+    }
+    return round16<M>(p);
+}
+
+// The format's rounding of the sum of two of its values: the FP32 sum is
+// exact unless the exponents differ by more than the FP32 spare bits, and
+// then the smaller operand is far below half a unit in the last place of the
+// format, where FP32 rounding cannot move the result across a rounding
+// boundary of the format.
+template <int M>
+__device__ __forceinline__ float add16(float a, float b) { return round16<M>(a + b); }
 
 }  // namespace mxd

@@ -11,6 +11,7 @@ bool fast_supported(int mode, int n, int cb)
 {
     if (n != mxf::N) return false;
     if (mode == MODE_FP32) return true;
+    if (mode != MODE_E4M3 && mode != MODE_E5M2) return false;
     return cb >= 2 && cb <= 16;
 }
 

@@ -15,13 +15,16 @@ namespace {
 
 constexpr uint32_t kKnownFlags = MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE;
 
-// Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2).
+// Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2) and the
+// 16-bit forms (IEEE half, bfloat16; twiddles never reach their overflow).
 struct HostElem {
     int mbits, emin, emax;
     double maxv;
 };
 const HostElem kE4M3 = {3, -6, 8, 448.0};
 const HostElem kE5M2 = {2, -14, 15, 57344.0};
+const HostElem kFP16 = {10, -14, 15, 65504.0};
+const HostElem kBF16 = {7, -126, 127, 3.3895313892515355e38};
 
 // Nearest element value (ties to the even multiple of the grid step),
 // saturating at the largest finite element.
@@ -176,9 +179,9 @@ mxfft_status check_params(const mxfft_params* p, int n)
         if (!is_pow2(p->block) || p->block < 2 || p->block > n) return MXFFT_EINVAL;
         if (p->block > 128) return MXFFT_EUNSUPPORTED;
         break;
-    case MXFFT_FP32: break;
+    case MXFFT_FP32:
     case MXFFT_FP16:
-    case MXFFT_BF16: return MXFFT_EUNSUPPORTED;
+    case MXFFT_BF16: break;
     default: return MXFFT_EINVAL;
     }
     if (!(p->flags & MXFFT_NO_PRESCALE)) {
@@ -239,6 +242,13 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
         for (long j = 0; j < h; j++) twiddle(j, m, &wr[j], &wi[j]);
         if (pl->mode == mxk::MODE_FP32) {
             for (long j = 0; j < h; j++) tw[h - 1 + j] = make_float2((float)wr[j], (float)wi[j]);
+            continue;
+        }
+        if (pl->mode == mxk::MODE_FP16 || pl->mode == mxk::MODE_BF16) {
+            // FP64 rounded once to the 16-bit format
+            const HostElem& h16 = (pl->mode == mxk::MODE_FP16) ? kFP16 : kBF16;
+            for (long j = 0; j < h; j++)
+                tw[h - 1 + j] = make_float2((float)round_to_elem(wr[j], h16), (float)round_to_elem(wi[j], h16));
             continue;
         }
         const long tb = (pl->cb < h) ? pl->cb : h;
@@ -316,7 +326,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     a.lines = mxk::line_lines_per_group(pl->n);
     a.axis = axis;
     a.inverse = inverse;
-    a.encode = (pl->mode != mxk::MODE_FP32);
+    a.encode = (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2);
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -407,8 +417,12 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     pl->logn = ilog2(n);
     pl->max_batch = max_batch;
     pl->p = *p;
-    pl->mode = (p->format == MXFFT_E4M3) ? mxk::MODE_E4M3 : (p->format == MXFFT_E5M2) ? mxk::MODE_E5M2 : mxk::MODE_FP32;
-    if (pl->mode != mxk::MODE_FP32) {
+    pl->mode = (p->format == MXFFT_E4M3)   ? mxk::MODE_E4M3
+               : (p->format == MXFFT_E5M2) ? mxk::MODE_E5M2
+               : (p->format == MXFFT_FP16) ? mxk::MODE_FP16
+               : (p->format == MXFFT_BF16) ? mxk::MODE_BF16
+                                           : mxk::MODE_FP32;
+    if (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2) {
         pl->cb = p->block / 2;
         pl->logcb = ilog2(pl->cb);
     }
@@ -425,7 +439,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     {
         // chunk statistics: the literal statistics pass, or one part per row tile
         size_t parts = mxk::stats_parts(n, max_batch);
-        if (mxk::fast_supported(pl->mode, n, pl->cb) && pl->mode != mxk::MODE_FP32)
+        if (mxk::fast_supported(pl->mode, n, pl->cb) && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2))
             parts = std::max(parts, (size_t)max_batch * mxk::fast_row_tiles(n));
         if (st == MXFFT_OK) st = dev_alloc(&pl->d_parts, parts, &pl->bytes);
     }
@@ -438,7 +452,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
         for (long h = 1; h < n; h <<= 1)
             for (long j = 0; j < h; j++) twf[h + j] = tw[h - 1 + j];
         st = dev_alloc(&pl->d_twf, twf.size(), &pl->bytes);
-        if (st == MXFFT_OK && pl->mode != mxk::MODE_FP32) {
+        if (st == MXFFT_OK && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2)) {
             st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n / 2, &pl->bytes);
             if (st == MXFFT_OK) st = dev_alloc(&pl->d_exps, (size_t)max_batch * n * (n / pl->cb), &pl->bytes);
             pl->fused = true;

@@ -66,7 +66,8 @@ struct LineArgs {
     int32_t encode;          // MX-encode the pass input
 };
 
-enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP32 = 4 };
+// MX formats, the 16-bit positive controls (per-operation rounding) and plain FP32
+enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP16 = 2, MODE_BF16 = 3, MODE_FP32 = 4 };
 
 // Register-resident passes for n = 512 (see mxfft_fast.hip).
 struct FastPassArgs {

@@ -311,6 +311,14 @@ __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float
     if constexpr (MODE == MODE_FP32) {
         pr = w.x * v.x - w.y * v.y;
         pi = w.x * v.y + w.y * v.x;
+    } else if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
+        // 16-bit form: v rounded to the format, each product and each sum of
+        // the complex product rounded to the format (twiddles are format values)
+        const float vr = mxd::round16<MODE>(v.x), vi = mxd::round16<MODE>(v.y);
+        const float rr = mxd::mul16<MODE>(w.x, vr), ii = mxd::mul16<MODE>(w.y, vi);
+        const float ri = mxd::mul16<MODE>(w.x, vi), ir = mxd::mul16<MODE>(w.y, vr);
+        pr = mxd::add16<MODE>(rr, -ii);
+        pi = mxd::add16<MODE>(ri, ir);
     } else {
         constexpr int F = MODE;
         // twiddle block: min(cb, h) consecutive j share one exponent
@@ -370,7 +378,14 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     }
     __syncthreads();
 
-    if constexpr (MODE != MODE_FP32) {
+    if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
+        // pass input rounded to the format
+        for (int idx = tid; idx < total; idx += blockDim.x) {
+            const float2 v = lds[idx];
+            lds[idx] = make_float2(mxd::round16<MODE>(v.x), mxd::round16<MODE>(v.y));
+        }
+        __syncthreads();
+    } else if constexpr (MODE != MODE_FP32) {
         if (a.encode) {
             // pass input: blocks of cb consecutive values along the line
             for (int idx = tid; idx < total; idx += blockDim.x) {
@@ -426,6 +441,11 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
             g = sbase + (size_t)e * N + line0 + r;
         }
         float2 v = lds[r * N + e];
+        if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
+            // the 16-bit form ends each pass rounded to the format (a column
+            // pass input would be rounded anyway; the output must be)
+            v = make_float2(mxd::round16<MODE>(v.x), mxd::round16<MODE>(v.y));
+        }
         v.x = ldexpf(v.x, kout);
         v.y = ldexpf(v.y, kout);
         a.dst[g] = v;
@@ -447,6 +467,8 @@ hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s)
     switch (mode) {
     case MODE_E4M3: hipLaunchKernelGGL(k_lines<MODE_E4M3>, grid, block, lds, s, a); break;
     case MODE_E5M2: hipLaunchKernelGGL(k_lines<MODE_E5M2>, grid, block, lds, s, a); break;
+    case MODE_FP16: hipLaunchKernelGGL(k_lines<MODE_FP16>, grid, block, lds, s, a); break;
+    case MODE_BF16: hipLaunchKernelGGL(k_lines<MODE_BF16>, grid, block, lds, s, a); break;
     case MODE_FP32: hipLaunchKernelGGL(k_lines<MODE_FP32>, grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
     }

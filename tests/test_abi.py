@@ -51,7 +51,7 @@ def plan_status(n, max_batch, **kw):
     (64, 1, dict(block=1), mxfft.EINVAL),
     (16, 1, dict(block=32), mxfft.EINVAL),           # B > n
     (512, 1, dict(block=256), mxfft.EUNSUPPORTED),   # B > 128 not built
-    (64, 1, dict(fmt="fp16"), mxfft.EUNSUPPORTED),
+    (64, 1, dict(fmt="fp16", tau=-1.0), mxfft.EINVAL),
     (64, 1, dict(fmt=9), mxfft.EINVAL),
     (64, 1, dict(tau=101.0), mxfft.EINVAL),
     (64, 1, dict(target=0.0), mxfft.EINVAL),

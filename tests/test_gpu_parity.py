@@ -53,6 +53,8 @@ def orc_run(x, op="forward", fmt="e4m3", block=32, k_in=None, flags=0, **kw):
     opcode = {"forward": O.FORWARD, "inverse": O.INVERSE, "roundtrip": O.ROUNDTRIP}[op]
     if fmt == "fp32":
         mode, f = O.MODE_FP32, O.E4M3
+    elif fmt in ("fp16", "bf16"):
+        mode, f = (O.MODE_FP16 if fmt == "fp16" else O.MODE_BF16), O.E4M3
     else:
         mode, f = O.MODE_MX, FMTS[fmt]
     return O.transform(x, op=opcode, mode=mode, fmt=f, B=block, kp=k_in, flags=flags, nthreads=NTHREADS, **kw)
@@ -63,8 +65,10 @@ def nrmse(y, r):
 
 
 def assert_bitexact(yg, yo, what=""):
+    """Bit for bit; a NaN matches any NaN (payloads carry no meaning)."""
     yg = np.ascontiguousarray(yg).reshape(yo.shape)
     bad = yg.view(np.uint32) != yo.view(np.uint32)
+    bad &= ~(np.isnan(yg.view(np.float32)) & np.isnan(yo.view(np.float32)))
     if bad.any():
         idx = np.argwhere(bad)[:5]
         raise AssertionError("%s: %d of %d words differ (NRMSE %.3g); first at %s: gpu %s oracle %s"
@@ -314,3 +318,42 @@ def test_n512_prescale_limits_and_errors():
     assert st == mxfft.OK and O.prescale(ks[0], k_min=kmax_ok)[0] == O.OK
     yg, kg, st = gpu_run(ks[:1], fmt="e4m3", block=32, k_min=kmax_ok + 1)
     assert st == mxfft.ERANGE and O.prescale(ks[0], k_min=kmax_ok + 1)[0] == O.ERANGE
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+@pytest.mark.parametrize("N", [2, 8, 32, 64, 128, 256, 512])
+def test_16bit_forms(fmt, N):
+    """The 16-bit forms (Sec. 2.3): rounding of every pass input, v operand,
+    product and sum to the format, bit for bit against the oracle; forward
+    with the prescale, inverse with its own prescale, round trip."""
+    if N >= 64:
+        x = synth.kspace_batch(N, 5, 1, 2)
+    else:
+        x = synth.random_complex((3, N, N), seed=N + 7, dist="lognormal")
+    for op in ("forward", "inverse", "roundtrip"):
+        yg, kg, st = gpu_run(x, op=op, fmt=fmt)
+        so, yo, ko = orc_run(x, op=op, fmt=fmt)
+        assert st == mxfft.OK and so == O.OK
+        if kg is not None:
+            np.testing.assert_array_equal(kg, ko)
+        assert_bitexact(yg, yo, "%s N=%d %s" % (fmt, N, op))
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+def test_16bit_range_edges(fmt):
+    """Values that overflow the half range and bfloat16 products below the
+    FP32 normal range (no prescale, so the data reaches the kernels as is)."""
+    rng = np.random.default_rng(3)
+    big = (rng.standard_normal((2, 32, 32)) + 1j * rng.standard_normal((2, 32, 32))) * 3e4
+    tiny = (rng.standard_normal((2, 32, 32)) + 1j * rng.standard_normal((2, 32, 32))) * 3e-39
+    x = np.concatenate([big, tiny]).astype(np.complex64)
+    yg, kg, st = gpu_run(x, fmt=fmt, flags=mxfft.NO_PRESCALE)
+    so, yo, ko = orc_run(x, fmt=fmt, flags=O.NO_PRESCALE)
+    # overflow makes NaN (inf - inf) in the half form: NaNs must sit at the
+    # same places (their payloads are not compared); every other value bit for bit
+    yg = np.ascontiguousarray(yg).reshape(yo.shape)
+    ng, no = np.isnan(yg), np.isnan(yo)
+    np.testing.assert_array_equal(ng, no)
+    assert_bitexact(np.where(ng, 0, yg), np.where(no, 0, yo), "%s range edges" % fmt)
+    if fmt == "bf16":
+        assert np.count_nonzero(yo[2:]) > 0            # the subnormal products left a trace
