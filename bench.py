@@ -5,7 +5,9 @@ Default workload: 1024 slices (64 slices x 16 coils) of 512 x 512 complex64
 synthetic k-space, MXFP8-E4M3 with B = 32, forward transform with the Alg. 1
 prescale (T = 2^7, tau = 5 %, tau_min = 2^-6).  A step is one forward call over
 the whole resident batch.  Also timed: the plain FP32 form of the same FFT on
-the same batch, and the CPU oracle on a bounded sample (host cores).
+the same batch, the other formats of the precision sweep (the other MX element
+format, FP16, BF16; forward, slices/s and accuracy against FP64 each), and the
+CPU oracle on a bounded sample (host cores).
 
 Prints one JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload kspace512_64x16]
@@ -43,7 +45,7 @@ def parse():
     ap.add_argument("--fmt", default="e4m3", choices=["e4m3", "e5m2"])
     ap.add_argument("--block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the other formats (E5M2/E4M3, FP16, BF16, FP32)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="slices the CPU oracle transforms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of the input (known bytes) to scale HBM counters")
@@ -180,19 +182,31 @@ def main():
         "psnr_db_vs_fp64": round(float(psnr.mean()), 2),
     }
 
-    if not args.no_fp32:
-        # the plain FP32 form needs no prescale (its result is scale-equivariant)
-        plan32 = mxfft.Plan(N, batch, fmt="fp32", flags=mxfft.NO_PRESCALE)
-        f32 = lambda: plan32.forward(xd, out=out, k_out=kout)   # noqa: E731
-        wall32, per32 = timed_steps(f32, args.steps, args.warmup, torch)
-        y32 = out[pick].cpu().numpy().astype(np.complex128)
-        e32 = np.linalg.norm((y32 - ref).reshape(len(pick), -1), axis=1) / np.linalg.norm(ref.reshape(len(pick), -1), axis=1)
-        sps32 = batch * args.steps / wall32
-        result["fp32_plain"] = {"value": round(sps32, 1), "unit": "slices/s", "ms_per_step": round(1e3 * wall32 / args.steps, 4),
-                                "prescale": "off",
-                                "nrmse_vs_fp64_max": float("%.3g" % e32.max())}
-        result["speedup_vs_fp32"] = round(slices_per_s / sps32, 3)
-        plan32.close()
+    if not args.no_sweep:
+        # Precision sweep on the same batch: the other MX element format, the
+        # 16-bit forms (literal prescale pass: not scale-equivariant) and plain
+        # FP32 (no prescale: its result is scale-equivariant).  Same step count.
+        sweep = {"%s_b%d" % (args.fmt, args.block): {
+            "value": result["value"], "ms_per_step": result["ms_per_step"],
+            "nrmse_vs_fp64": result["nrmse_vs_fp64"], "psnr_db_vs_fp64": result["psnr_db_vs_fp64"]}}
+        other = "e5m2" if args.fmt == "e4m3" else "e4m3"
+        for name, kw in ((other + "_b%d" % args.block, dict(fmt=other, block=args.block)),
+                         ("fp16", dict(fmt="fp16")), ("bf16", dict(fmt="bf16")),
+                         ("fp32", dict(fmt="fp32", flags=mxfft.NO_PRESCALE))):
+            pl = mxfft.Plan(N, batch, **kw)
+            fn = lambda: pl.forward(xd, out=out, k_out=kout)   # noqa: E731
+            wall_f, _ = timed_steps(fn, args.steps, args.warmup, torch)
+            assert pl.last_status() == mxfft.OK, name
+            yf = out[pick].cpu().numpy().astype(np.complex128)
+            ef = np.linalg.norm((yf - ref).reshape(len(pick), -1), axis=1) / np.linalg.norm(ref.reshape(len(pick), -1), axis=1)
+            msef = np.mean(np.abs(yf - ref) ** 2, axis=(1, 2))
+            psf = 20 * np.log10(np.abs(ref).max(axis=(1, 2)) / np.sqrt(msef))
+            sweep[name] = {"value": round(batch * args.steps / wall_f, 1), "ms_per_step": round(1e3 * wall_f / args.steps, 4),
+                           "nrmse_vs_fp64": {"mean": float("%.4g" % ef.mean()), "max": float("%.4g" % ef.max())},
+                           "psnr_db_vs_fp64": round(float(psf.mean()), 2)}
+            pl.close()
+        result["precision_sweep"] = {"unit": "slices/s", "direction": "forward", "formats": sweep}
+        result["speedup_vs_fp32"] = round(slices_per_s / sweep["fp32"]["value"], 3)
 
     if not args.no_cpu_baseline:
         import oracle

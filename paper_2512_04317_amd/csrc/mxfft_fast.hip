@@ -6,11 +6,13 @@ namespace mxk {
 hipError_t launch_fast_e4m3(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_fp32(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_fp16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_bf16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 
 bool fast_supported(int mode, int n, int cb)
 {
     if (n != mxf::N) return false;
-    if (mode == MODE_FP32) return true;
+    if (mode == MODE_FP32 || mode == MODE_FP16 || mode == MODE_BF16) return true;
     if (mode != MODE_E4M3 && mode != MODE_E5M2) return false;
     return cb >= 2 && cb <= 16;
 }
@@ -40,10 +42,13 @@ hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const
     g.kadd = p.kadd;
     g.fix_list = p.fix_list;
     g.fix_count = p.fix_count;
+    g.tw16 = p.tw16;
     switch (mode) {
     case MODE_E4M3: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
     case MODE_E5M2: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);
     case MODE_FP32: return launch_fast_fp32(cb, row, inverse, kind, g, batch, s);
+    case MODE_FP16: return launch_fast_fp16(cb, row, inverse, kind, g, batch, s);
+    case MODE_BF16: return launch_fast_bf16(cb, row, inverse, kind, g, batch, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,7 +21,11 @@
 // Column pass (MX): codes -> decode (this is the column input encode) -> bit
 //                  reversal -> 9 stages -> 2^kout -> complex64.
 // The FP32 plain form uses the same skeleton without quantisation and keeps
-// an FP32 intermediate.
+// an FP32 intermediate.  The FP16 and BF16 forms use it with every pass input,
+// v operand, product and product sum rounded to the format (packed half
+// arithmetic for FP16, FP32 products and packed conversions for BF16) and a
+// 16-bit intermediate: the column pass input is the row pass output rounded
+// to the format, so storing it rounded loses nothing.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,6 +40,8 @@ namespace mxf {
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
 
 constexpr int LOGN = 9;
 constexpr int N = 1 << LOGN;
@@ -44,7 +50,11 @@ constexpr int LPL = N / P;       // lanes per line (16)
 constexpr int LPW = 64 / LPL;    // lines per wave (4)
 constexpr int WAVES = 4;
 constexpr int LINES = LPW * WAVES;  // lines per work-group (16)
-constexpr int FP32 = 4;          // format id of the plain form (mxk::MODE_FP32)
+constexpr int FP16 = 2;          // format ids of the plain forms (mxk::MODE_FP16,
+constexpr int BF16 = 3;          // mxk::MODE_BF16, mxk::MODE_FP32); 0 and 1 are
+constexpr int FP32 = 4;          // the MX element formats E4M3 and E5M2
+constexpr bool is_mx(int F) { return F < FP16; }
+constexpr bool is_16(int F) { return F == FP16 || F == BF16; }
 
 // ---------------------------------------------------------------------------
 // compile-time helpers
@@ -310,9 +320,11 @@ __device__ __forceinline__ int mx_requant(float2* v, float& am)
 }
 
 // Running range of the MX block exponents a pass uses (only tracked by the
-// row pass that runs unscaled while it gathers the prescale statistics).
+// row pass that runs unscaled while it gathers the prescale statistics), and
+// for BF16 whether some product fell below the FP32 normal range.
 struct ERange {
     int lo = 0, hi = 0;
+    bool sub = false;
     __device__ __forceinline__ void add(int e) { lo = min(lo, e); hi = max(hi, e); }
 };
 
@@ -356,7 +368,87 @@ struct Tw {
     const float2* tw;      // stage s = b+1, index j at [2^b + j]
     const int32_t* ex;     // twiddle block exponents
     const int32_t* off;    // per stage s: offset into ex
+    const uint32_t* tw16;  // FP16 form: the same twiddles as packed halves
 };
+
+// ---------------------------------------------------------------------------
+// FP16 / BF16 arithmetic
+// ---------------------------------------------------------------------------
+
+// (a, b) rounded to nearest even in the 16-bit format, packed (a low); one
+// v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32 (overflow to infinity, NaN kept)
+template <int F>
+__device__ __forceinline__ uint32_t pack16(float a, float b)
+{
+    if constexpr (F == FP16) return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, half2v));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf162v));
+}
+
+// the two values of a packed pair as FP32 (exact)
+template <int F>
+__device__ __forceinline__ float2 unpack16(uint32_t w)
+{
+    if constexpr (F == FP16) {
+        const half2v h = __builtin_bit_cast(half2v, w);
+        return make_float2((float)h.x, (float)h.y);
+    } else {
+        return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+}
+
+// FP16 complex product w v of packed halves: the four products and the two
+// sums each round once to half (packed half multiplies and adds are correctly
+// rounded; contraction into fused multiply-adds is off).  Three packed
+// instructions; p = (wr vr - wi vi, wr vi + wi vr), wi negated for the inverse.
+template <bool INV>
+__device__ __forceinline__ float2 cmul_fp16(uint32_t wb, uint32_t vb)
+{
+#pragma clang fp contract(off)
+    const half2v w = __builtin_bit_cast(half2v, wb), v = __builtin_bit_cast(half2v, vb);
+    const half2v p1 = w.xx * v;                              // wr vr, wr vi
+    const half2v p2 = (INV ? -w.yy : w.yy) * v.yx;           // wi vi, wi vr
+    const half2v p = p1 + (half2v){-p2.x, p2.y};
+    return make_float2((float)p.x, (float)p.y);
+}
+
+// BF16 product a b rounded to bfloat16 later by pack16: the FP32 product of
+// two bfloat16 values (16 significant bits) is exact unless it is an FP32
+// subnormal.  EX: such products are replaced by the exact value rounded to the
+// bfloat16 subnormal grid 2^-133; else they are only flagged.  The exact
+// rounding: both factors are then below 2^7 in magnitude (each is at least
+// 2^-133), so q = (a 2^64) b is an exact normal FP32 value below 2^-62; adding
+// and subtracting 1.5 * 2^-46 rounds it to the grid 2^-69 (nearest even), and
+// 2^-64 scales back exactly.  The sign of a zero result is that of q.
+template <bool EX>
+__device__ __forceinline__ float mul_bf16(float a, float b, bool& sub)
+{
+#pragma clang fp contract(off)
+    float p = a * b;
+    const bool tiny = __builtin_isfpclass(p, 0x90);          // -subnormal | +subnormal
+    if constexpr (EX) {
+        const float q = (a * 0x1p64f) * b;
+        const float r = __builtin_copysignf(((q + 0x1.8p-46f) - 0x1.8p-46f) * 0x1p-64f, q);
+        if (tiny) p = r;
+    } else {
+        sub |= tiny;
+    }
+    return p;
+}
+
+// BF16 complex product w v (v packed bfloat16): products and sums each round
+// once to bfloat16.  A sum of two bfloat16 values rounded to FP32 and then to
+// bfloat16 equals its direct rounding (24 >= 2 * 8 + 2 bits).
+template <bool INV, bool EX>
+__device__ __forceinline__ float2 cmul_bf16(float2 w, uint32_t vb, bool& sub)
+{
+#pragma clang fp contract(off)
+    const float2 v = unpack16<BF16>(vb);
+    const float wi = INV ? -w.y : w.y;
+    const uint32_t q1 = pack16<BF16>(mul_bf16<EX>(w.x, v.x, sub), mul_bf16<EX>(w.x, v.y, sub));   // wr vr, wr vi
+    const uint32_t q2 = pack16<BF16>(mul_bf16<EX>(wi, v.y, sub), mul_bf16<EX>(wi, v.x, sub));     // wi vi, wi vr
+    const float2 a = unpack16<BF16>(q1), b = unpack16<BF16>(q2);
+    return unpack16<BF16>(pack16<BF16>(a.x - b.x, a.y + b.y));
+}
 
 // ---------------------------------------------------------------------------
 // one radix-2 stage (butterfly position bit B) in layout K
@@ -366,7 +458,8 @@ struct Tw {
 // last block bit in lane bit 0 (position bit LC is the lowest lane bit there):
 // each lane then works on half-blocks and the two block maxima (of v and of
 // the products) are completed with one DPP exchange between lanes m, m ^ 1.
-template <int F, int LC, int BC, int K, int B, bool INV, bool TR>
+// EX (BF16): products below the FP32 normal range computed exactly.
+template <int F, int LC, int BC, int K, int B, bool INV, bool TR, bool EX = false>
 __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     using Ly = Lay<LC>;
@@ -412,6 +505,18 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
                 const float pi = w.x * V[T].y + wi * V[T].x;
                 a[ou] = make_float2(U[T].x + pr, U[T].y + pi);
                 a[ou | (1 << ob)] = make_float2(U[T].x - pr, U[T].y - pi);
+            });
+        } else if constexpr (is_16(F)) {
+            // v rounded to the format, the product in the format, u +/- p in FP32
+            sfor<CB>([&](auto T) {
+                constexpr int ou = base | deposit(T, BFLY);
+                constexpr int jc = Ly::posF(K, ou) & (h - 1);
+                const uint32_t vb = pack16<F>(V[T].x, V[T].y);
+                float2 p;
+                if constexpr (F == FP16) p = cmul_fp16<INV>(t.tw16[h + (jm | jc)], vb);
+                else p = cmul_bf16<INV, EX>(t.tw[h + (jm | jc)], vb, er.sub);
+                a[ou] = make_float2(U[T].x + p.x, U[T].y + p.y);
+                a[ou | (1 << ob)] = make_float2(U[T].x - p.x, U[T].y - p.y);
             });
         } else if constexpr (B <= 1) {
             // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
@@ -481,11 +586,11 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
 }
 
 // all stages of layout K
-template <int F, int LC, int BC, int K, bool INV, bool TR>
+template <int F, int LC, int BC, int K, bool INV, bool TR, bool EX>
 __device__ __forceinline__ void stages(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     constexpr int b0 = Lay<LC>::bfirst(K), b1 = Lay<LC>::blast(K);
-    sfor<b1 - b0>([&](auto I) { stage<F, LC, BC, K, b0 + I, INV, TR>(a, m, t, er); });
+    sfor<b1 - b0>([&](auto I) { stage<F, LC, BC, K, b0 + I, INV, TR, EX>(a, m, t, er); });
 }
 
 // Layout K -> K+1 through this line's LDS plane (re, then im); addresses are
@@ -514,13 +619,13 @@ __device__ __forceinline__ void exchange(float2 (&a)[P], int m, float* plane)
 }
 
 // plane: this line's exchange plane (line_base within the wave's planes)
-template <int F, int LC, int BC, bool INV, bool TR = false>
+template <int F, int LC, int BC, bool INV, bool TR = false, bool EX = false>
 __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, float* plane, ERange& er)
 {
     using Ly = Lay<LC>;
     sfor<Ly::NL>([&](auto K) {
         if constexpr (K > 0) exchange<LC, K - 1>(a, m, plane);
-        stages<F, LC, BC, K, INV, TR>(a, m, t, er);
+        stages<F, LC, BC, K, INV, TR, EX>(a, m, t, er);
     });
 }
 
@@ -528,7 +633,7 @@ __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, f
 // the layouts of blocks of 8 (two layout exchanges instead of four) with each
 // block split over a lane pair.
 template <int F, int C>
-constexpr int layout_family() { return F == FP32 ? 1 : (C == 4 ? 3 : C); }
+constexpr int layout_family() { return !is_mx(F) ? 1 : (C == 4 ? 3 : C); }
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -537,7 +642,8 @@ constexpr int layout_family() { return F == FP32 ? 1 : (C == 4 ? 3 : C); }
 struct FastArgs {
     const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
     float2* dst;             // complex64 output (row pass FP32 form / column pass)
-    uint32_t* codes;         // MX intermediate: [slice][16-column group][row][8 words of 2 code pairs], swizzled
+    uint32_t* codes;         // intermediate, [slice][16-column group][row][...]: MX, 8 words of 2 code
+                             // pairs (swizzled); FP16/BF16, 16 words of one packed complex value
     uint8_t* exps;           // MX intermediate: [slice][row block][column] E8M0 bytes
     const int32_t* kp;       // per-slice prescale exponent or nullptr
     int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
@@ -549,6 +655,7 @@ struct FastArgs {
     const int32_t* kadd;     // column pass: per-slice offset of the stored exponents, or nullptr
     const int32_t* fix_list; // list-driven row pass: slices to redo
     int32_t* fix_count;      // list length (zeroed by the row pass with statistics)
+    const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
 };
 
 using mxk::kStatsBins;
@@ -566,7 +673,7 @@ __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
 // Shared memory of the row pass.
 template <int F, int C, int KIND>
 struct alignas(16) RowLds {
-    static constexpr int NSB = (F == FP32) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
+    static constexpr int NSB = !is_mx(F) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
     // exchange planes; before them the statistics histogram (row pass with
     // statistics only: 32 copies, bin * 32 + lane % 32, so only lanes l and
     // l + 32 can meet on an address; bin kStatsBins - 1 collects zeros and
@@ -593,8 +700,8 @@ __device__ __forceinline__ T wave_reduce_min(T v)
     return v;
 }
 
-// One 16-row tile of the row pass. F: 0 E4M3, 1 E5M2, 4 FP32.  C: log2 of
-// complex values per MX block.  KIND:
+// One 16-row tile of the row pass. F: 0 E4M3, 1 E5M2, 2 FP16, 3 BF16, 4 FP32.
+// C: log2 of complex values per MX block (1 for the plain forms).  KIND:
 //   ROW_PLAIN  input scaled by 2^(kin_mul * kp) (kp per slice, may be absent)
 //   ROW_STATS  input unscaled; also the Alg. 1 statistics of the tile (with the
 //              range of the block exponents used) into parts[slice][tile]
@@ -605,7 +712,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr int CB = 1 << C;
     constexpr int NSB = RowLds<F, C, KIND>::NSB;
     constexpr bool ST = (KIND == ROW_STATS);
-    static_assert(!ST || F != FP32, "statistics ride on the MX row pass only");
+    static_assert(!ST || is_mx(F), "statistics ride on the MX row pass only");
     float* s_plane = L.plane;
     float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -619,16 +726,22 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     float* plane = s_plane + wave * WPL + line_base(line);
     uint32_t* hist = (uint32_t*)s_plane;                 // statistics only, before the planes are used
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
-    Tw t{g.tw, g.tw_exp, g.tw_off};
+    Tw t{g.tw, g.tw_exp, g.tw_off, g.tw16};
     float2 a[P];
     ERange er;
-
-    if constexpr (F == FP32) {
-        // layout 0 directly: natural 16k + rev4(m) -> offset rev5(k)
+    // plain forms: layout 0 directly, natural 16k + rev4(m) -> offset rev5(k);
+    // the 16-bit forms round the pass input to the format
+    auto load_plain = [&]() {
         sfor<P>([&](auto Kk) {
-            float2 v = x[16 * Kk + rm];
-            a[rev(Kk, 5)] = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
+            const float2 v = x[16 * Kk + rm];
+            float2 s = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
+            if constexpr (is_16(F)) s = unpack16<F>(pack16<F>(s.x, s.y));
+            a[rev(Kk, 5)] = s;
         });
+    };
+
+    if constexpr (!is_mx(F)) {
+        load_plain();
     } else {
         // coalesced loads: lane m of a line holds naturals 32 I + 2 m + e
         // (e = 0, 1) as v[2 I + e]
@@ -712,13 +825,33 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     }
 
     constexpr int CL = layout_family<F, C>();
-    all_stages<F, CL, (F == FP32 ? 1 : C), INV, ST>(a, m, t, plane, er);
+    all_stages<F, CL, (is_mx(F) ? C : 1), INV, ST>(a, m, t, plane, er);
+    if constexpr (F == BF16) {
+        // some product of this wave's lines fell below the FP32 normal range:
+        // the wave redoes its lines with such products computed exactly
+        if (__builtin_amdgcn_ballot_w64(er.sub) != 0) {
+            load_plain();
+            all_stages<F, CL, 1, INV, false, true>(a, m, t, plane, er);
+        }
+    }
 
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
     if constexpr (F == FP32) {
         float2* y = g.dst + ((size_t)slice * N + row) * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
+    } else if constexpr (is_16(F)) {
+        // 16-bit intermediate [slice][16-column group][row][16 words]: in-lane
+        // offset bit 0 is position bit 0, so a lane holds pairs of adjacent
+        // columns (one 8-byte store each; a line's 8 lanes of one group write
+        // the row's 64 bytes).  Packing rounds to the format.
+        uint32_t* cd = g.codes + (size_t)slice * N * N;
+        sfor<P / 2>([&](auto I) {
+            constexpr int o = 2 * I;
+            const int c = Lay<CL>::posF(KL, o) | pmL;
+            *(uint2*)&cd[((size_t)(c >> 4) * N + row) * 16 + (c & 15)] =
+                make_uint2(pack16<F>(a[o].x, a[o].y), pack16<F>(a[o + 1].x, a[o + 1].y));
+        });
     } else {
         // Column MX encode of the next pass's input: blocks of CB consecutive
         // rows of one column; this work-group holds NSB such blocks.
@@ -855,7 +988,7 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
     constexpr int CB = 1 << C;
     constexpr int NRB = N / CB;                        // row blocks per column
     __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; input and output tiles
-    __shared__ __align__(16) uint8_t s_ex[(F == FP32) ? 16 : LINES * NRB];  // [row block][16 columns]
+    __shared__ __align__(16) uint8_t s_ex[!is_mx(F) ? 16 : LINES * NRB];  // [row block][16 columns]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int line = lane >> 4, m = lane & 15;
     const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
@@ -864,9 +997,11 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
     const int kout = g.kout_mul * kp + g.kout_add;
     float* plane = s_plane + wave * WPL + line_base(line);
     const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
-    Tw t{g.tw, g.tw_exp, g.tw_off};
+    Tw t{g.tw, g.tw_exp, g.tw_off, g.tw16};
     float2 a[P];
     float2* tile = (float2*)s_plane;                   // 256 x 16 complex (32 KiB)
+    // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
+    const uint32_t* c16 = g.codes + (size_t)slice * N * N + (size_t)cb16 * LINES * N;
 
     if constexpr (F == FP32) {
         // rows are read whole (128 bytes = the work-group's 16 columns) into an
@@ -886,6 +1021,32 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
                 constexpr int Kk = H * 16 + Kl;
                 a[rev(Kk, 5)] = tile[tslot<0xF>(16 * Kl + rm, cl)];
             });
+        });
+        __syncthreads();
+    } else if constexpr (is_16(F)) {
+        // the 512 rows of 64 bytes into LDS, the four 16-byte pieces of row n
+        // rotated by XOR ((n >> 1) & 3): the 32-bit reads below (16 rows x 4
+        // columns per wave) then reach every bank exactly twice
+        uint32_t* ctile = (uint32_t*)s_plane;
+        static_assert(LINES * N / 4 == 8 * 256, "eight 16-byte pieces per thread");
+        const uint4* src = (const uint4*)c16;
+        auto put = [&](int i, const uint4& v) {
+            const int n = i >> 2;
+            ((uint4*)ctile)[n * 4 + ((i & 3) ^ ((n >> 1) & 3))] = v;
+        };
+        sfor<2>([&](auto H) {   // four loads in flight, then their stores
+            constexpr int J = 4 * H;
+            const uint4 q0 = src[J * 256 + tid], q1 = src[(J + 1) * 256 + tid];
+            const uint4 q2 = src[(J + 2) * 256 + tid], q3 = src[(J + 3) * 256 + tid];
+            put(J * 256 + tid, q0);
+            put((J + 1) * 256 + tid, q1);
+            put((J + 2) * 256 + tid, q2);
+            put((J + 3) * 256 + tid, q3);
+        });
+        __syncthreads();
+        sfor<P>([&](auto O) {
+            const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
+            a[O] = unpack16<F>(ctile[n * 16 + (cl ^ (((n >> 1) & 3) << 2))]);
         });
         __syncthreads();
     } else {
@@ -923,7 +1084,15 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
 
     ERange er;
     constexpr int CL = layout_family<F, C>();
-    all_stages<F, CL, (F == FP32 ? 1 : C), INV>(a, m, t, plane, er);
+    all_stages<F, CL, (is_mx(F) ? C : 1), INV>(a, m, t, plane, er);
+    if constexpr (F == BF16) {
+        // a product below the FP32 normal range: the wave redoes its columns
+        // (input read again from the intermediate) with such products exact
+        if (__builtin_amdgcn_ballot_w64(er.sub) != 0) {
+            sfor<P>([&](auto O) { a[O] = unpack16<F>(c16[(size_t)((rev(O, 5) << 4) | rm) * 16 + cl]); });
+            all_stages<F, CL, 1, INV, false, true>(a, m, t, plane, er);
+        }
+    }
 
     // output: scaled by 2^kout, staged through an LDS tile 256 rows at a time
     // (row bit 8 is an in-lane bit of the last layout) and written as whole
@@ -939,7 +1108,9 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         sfor<P>([&](auto O) {
             if constexpr (((O >> HB) & 1) == H) {
                 const int r = (Lay<CL>::posF(KL, O) | pmL) & 255;
-                tile[tslot<LM>(r, cl)] = make_float2(ldexpf(a[O].x, kout), ldexpf(a[O].y, kout));
+                float2 v = a[O];
+                if constexpr (is_16(F)) v = unpack16<F>(pack16<F>(v.x, v.y));   // output in the format
+                tile[tslot<LM>(r, cl)] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));
             }
         });
         __syncthreads();

@@ -92,6 +92,7 @@ struct mxfft_plan_s {
     // register-resident path (n = 512): twiddles at [h + j], MX intermediate
     bool fast = false;
     float2* d_twf = nullptr;
+    uint32_t* d_tw16 = nullptr;      // FP16 form: the same twiddles as packed halves
     uint32_t* d_codes = nullptr;
     uint8_t* d_exps = nullptr;
     // statistics gathered by the row pass (MX, n = 512): exponent offsets and
@@ -217,6 +218,7 @@ void release(mxfft_plan_s* pl)
     (void)hipFree(pl->d_kp);
     (void)hipFree(pl->d_status);
     (void)hipFree(pl->d_twf);
+    (void)hipFree(pl->d_tw16);
     (void)hipFree(pl->d_codes);
     (void)hipFree(pl->d_exps);
     (void)hipFree(pl->d_kadd);
@@ -298,6 +300,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
         f.kout_mul = kout_mul;
         f.kout_add = kout_add;
         f.tw = pl->d_twf;
+        f.tw16 = pl->d_tw16;
         f.tw_exp = pl->d_tw_exp;
         for (int i = 0; i < 16; i++) f.tw_off[i] = i < mxk::kMaxLog2N + 2 ? pl->tw_exp_off[i] : 0;
         f.parts = pl->d_parts;
@@ -447,6 +450,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     std::vector<float2> twf;
+    std::vector<uint32_t> tw16;
     if (st == MXFFT_OK && pl->fast) {
         twf.assign((size_t)n, make_float2(0.f, 0.f));
         for (long h = 1; h < n; h <<= 1)
@@ -460,6 +464,20 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
             if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_list, (size_t)max_batch, &pl->bytes);
             if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_count, 1, &pl->bytes);
         }
+        if (st == MXFFT_OK && (pl->mode == mxk::MODE_FP16 || pl->mode == mxk::MODE_BF16))
+            st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n, &pl->bytes);   // one packed pair per value
+        if (st == MXFFT_OK && pl->mode == mxk::MODE_FP16) {
+            // the twiddles are halves already: packed exactly
+            tw16.assign((size_t)n, 0u);
+            for (size_t i = 0; i < twf.size(); i++) {
+                const _Float16 re = (_Float16)twf[i].x, im = (_Float16)twf[i].y;
+                uint16_t br, bi;
+                std::memcpy(&br, &re, 2);
+                std::memcpy(&bi, &im, 2);
+                tw16[i] = (uint32_t)br | ((uint32_t)bi << 16);
+            }
+            st = dev_alloc(&pl->d_tw16, tw16.size(), &pl->bytes);
+        }
     }
     if (st != MXFFT_OK) {
         release(pl);
@@ -469,6 +487,8 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     ok = ok && hipMemcpyAsync(pl->d_tw_exp, tw_exp.data(), tw_exp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) == hipSuccess;
     if (pl->fast)
         ok = ok && hipMemcpyAsync(pl->d_twf, twf.data(), twf.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (pl->d_tw16)
+        ok = ok && hipMemcpyAsync(pl->d_tw16, tw16.data(), tw16.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemsetAsync(pl->d_status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {

@@ -73,7 +73,7 @@ enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP16 = 2, MODE_BF16 = 3, MODE_FP3
 struct FastPassArgs {
     const float2* src;
     float2* dst;
-    uint32_t* codes;         // MX intermediate codes, 2 bytes per complex value
+    uint32_t* codes;         // intermediate: MX codes (2 bytes per complex value) or packed FP16/BF16 (4)
     uint8_t* exps;           // MX intermediate block exponents (E8M0)
     const int32_t* kp;
     int32_t* k_out;
@@ -85,6 +85,7 @@ struct FastPassArgs {
     const int32_t* kadd;     // column pass: per-slice offset added to the stored block exponents, or nullptr
     const int32_t* fix_list; // list-driven row pass: slices to redo
     int32_t* fix_count;      // number of list entries (zeroed by the row pass with statistics)
+    const uint32_t* tw16;    // FP16 form: twiddles as packed halves at [h + j]
 };
 
 // Row pass kinds of the register-resident passes.
