@@ -149,6 +149,83 @@ mxfft_status mxfft_plan_kernel_times(mxfft_plan_t plan, mxfft_kernel_time* out, 
 /* Bytes of device memory the plan holds (tables and workspace). */
 uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
 
+/* ---- Launch tuning ------------------------------------------------------
+ * Sizes and formats without register-resident passes (every n other than 512,
+ * and B in {2, 64, 128} at 512) run the generic line kernels: one work-group
+ * holds `lines` whole lines of a pass in LDS, one thread per butterfly.  The
+ * best `lines` depends on n, the format and the GPU, so it is measured. */
+typedef struct {
+    int32_t lines;   /* lines per work-group: a power of two, 1 <= lines <= n,
+                        lines * n * 8 <= 65536; 0 = the default (8192 / n, at most n) */
+    int32_t fast;    /* out: 1 when the plan runs the register-resident passes,
+                        which have no such parameter (lines is then ignored) */
+    double ms;       /* out (tuner): time of one forward call over its sample */
+} mxfft_tuning;
+
+/* Set / read a plan's launch tuning.  Set: MXFFT_EINVAL for an invalid
+ * `lines`; takes effect from the next call (no synchronisation). */
+mxfft_status mxfft_plan_set_tuning(mxfft_plan_t plan, const mxfft_tuning* t);
+mxfft_status mxfft_plan_get_tuning(mxfft_plan_t plan, mxfft_tuning* t);
+
+/* Autotuner.  Looks up (GPU architecture name, n, format, B) in the cache file
+ * `cache_path` (NULL: no cache); on a miss, or with MXFFT_TUNE_FORCE, it times
+ * one forward call of a plan of `sample` slices of synthetic data for every
+ * candidate `lines` (the default and its halvings, at least 1), keeps the
+ * fastest and records it in the cache (the file is rewritten whole through a
+ * temporary file and a rename; entries of other keys are kept).  Allocates and
+ * frees device memory and synchronises `stream`.  *out gets the choice. */
+#define MXFFT_TUNE_FORCE 0x1u
+mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const char* cache_path,
+                        uint32_t tune_flags, mxfft_tuning* out, void* stream);
+
+/* Host-only cache lookup (no GPU call): MXFFT_OK and *out filled when the file
+ * holds an entry for (arch, n, p->format, p->block), MXFFT_EINVAL when it does
+ * not or the file cannot be read.  The file is plain text, one entry per line:
+ *   {"arch": "gfx950", "n": 256, "format": 0, "block": 32, "lines": 8, "ms": 0.1}
+ * (format as mxfft_format; block 0 for FP16/BF16/FP32). */
+mxfft_status mxfft_tune_cache_lookup(const char* cache_path, const char* arch, int32_t n,
+                                     const mxfft_params* p, mxfft_tuning* out);
+
+/* ---- Uneven batches -----------------------------------------------------
+ * A work list of slice groups of different sizes, transformed by one call
+ * that launches one HIP graph.  Group g holds `count` slices of n x n at
+ * element offset `offset` (complex values from the pool base) of both the
+ * input and the output pool; groups must not overlap.  The graph holds one
+ * independent branch per group (its own plan, workspace and stream), so small
+ * groups run beside large ones; it is captured on the first call for a given
+ * (operation, input, output, k) and replayed while those stay the same.
+ * k per slice goes to k_out[kbase_g + i], kbase_g = the slices of the groups
+ * before g.  Every slice's result is bit-identical to a single-plan call. */
+typedef struct {
+    int32_t n;        /* slice size (power of two, 2..4096) */
+    int32_t count;    /* slices in the group (>= 1) */
+    uint64_t offset;  /* complex-value offset of the group's first slice */
+} mxfft_group;
+
+typedef struct mxfft_batch_s* mxfft_batch_t;
+
+/* Plans every group (params p for all; n = 512 groups use the register-
+ * resident passes), autotunes each distinct n that runs the generic kernels
+ * through mxfft_tune with `tune_cache` (may be NULL: tune without a cache),
+ * and creates the branch streams.  Allocates device memory; synchronises. */
+mxfft_status mxfft_batch_create(mxfft_batch_t* out, const mxfft_group* groups, int32_t ngroups,
+                                const mxfft_params* p, const char* tune_cache, void* stream);
+
+/* op: 0 forward (k_out written), 1 inverse with its own prescale, 2 round trip
+ * (k_out written).  in, out: the pools (in == out allowed); k_out: device
+ * int32[total slices] or NULL.  One graph launch on `stream`. */
+mxfft_status mxfft_batch_execute(mxfft_batch_t b, int32_t op, const void* in, void* out, int32_t* k_out,
+                                 void* stream);
+
+/* Synchronise `stream`; the first non-OK device status of the last call. */
+mxfft_status mxfft_batch_last_status(mxfft_batch_t b, void* stream);
+
+/* Tuning chosen for group g (lines, fast, ms). */
+mxfft_status mxfft_batch_group_tuning(mxfft_batch_t b, int32_t g, mxfft_tuning* out);
+
+/* Release the batch, its plans, streams and graphs (synchronises the device). */
+mxfft_status mxfft_batch_destroy(mxfft_batch_t b);
+
 /* Static text for a status code. */
 const char* mxfft_status_string(mxfft_status st);
 

@@ -89,6 +89,8 @@ struct mxfft_plan_s {
     mxk::StatPart* d_parts = nullptr;
     int32_t* d_kp = nullptr;
     int32_t* d_status = nullptr;
+    // generic line kernels: lines per work-group (0 = line_lines_per_group)
+    int lines = 0;
     // register-resident path (n = 512): twiddles at [h + j], MX intermediate
     bool fast = false;
     float2* d_twf = nullptr;
@@ -326,7 +328,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     a.logn = pl->logn;
     a.cb = pl->cb;
     a.logcb = pl->logcb;
-    a.lines = mxk::line_lines_per_group(pl->n);
+    a.lines = pl->lines ? pl->lines : mxk::line_lines_per_group(pl->n);
     a.axis = axis;
     a.inverse = inverse;
     a.encode = (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2);
@@ -635,6 +637,24 @@ mxfft_status mxfft_plan_kernel_times(mxfft_plan_t pl, mxfft_kernel_time* out, in
 }
 
 uint64_t mxfft_plan_device_bytes(mxfft_plan_t pl) { return pl ? pl->bytes : 0; }
+
+mxfft_status mxfft_plan_set_tuning(mxfft_plan_t pl, const mxfft_tuning* t)
+{
+    if (!pl || !t) return MXFFT_EINVAL;
+    const int r = t->lines;
+    if (r != 0 && (r < 1 || r > pl->n || (r & (r - 1)) != 0 || (long)r * pl->n * 8 > 65536)) return MXFFT_EINVAL;
+    pl->lines = r;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_plan_get_tuning(mxfft_plan_t pl, mxfft_tuning* t)
+{
+    if (!pl || !t) return MXFFT_EINVAL;
+    t->lines = pl->fast ? 0 : (pl->lines ? pl->lines : mxk::line_lines_per_group(pl->n));
+    t->fast = pl->fast ? 1 : 0;
+    t->ms = 0.0;
+    return MXFFT_OK;
+}
 
 const char* mxfft_status_string(mxfft_status st)
 {

@@ -452,6 +452,24 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     }
 }
 
+// Synthetic data for launch tuning: both parts uniform in [-1, 1) from a
+// counter hash (timing only; the values do not matter beyond being finite).
+__global__ void k_fill(float2* x, size_t count, uint32_t seed)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ seed;
+        h ^= h >> 16; h *= 0x7FEB352Du; h ^= h >> 15; h *= 0x846CA68Bu; h ^= h >> 16;
+        const uint32_t g = h * 0x2C1B3C6Du + 0x297A2D39u;
+        x[i] = make_float2((float)(int32_t)h * 0x1p-31f, (float)(int32_t)g * 0x1p-31f);
+    }
+}
+
+hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, x, count, seed);
+    return hipGetLastError();
+}
+
 int line_lines_per_group(int n)
 {
     int r = 8192 / n;

@@ -22,7 +22,12 @@ INT32_MIN, INT32_MAX = -(2 ** 31), 2 ** 31 - 1
 EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_forward",
            "mxfft_inverse", "mxfft_roundtrip", "mxfft_plan_last_status", "mxfft_plan_profile",
            "mxfft_plan_profile_roles",
-           "mxfft_plan_kernel_times", "mxfft_plan_device_bytes", "mxfft_status_string", "mxfft_version")
+           "mxfft_plan_kernel_times", "mxfft_plan_device_bytes", "mxfft_status_string", "mxfft_version",
+           "mxfft_plan_set_tuning", "mxfft_plan_get_tuning", "mxfft_tune", "mxfft_tune_cache_lookup",
+           "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
+           "mxfft_batch_destroy")
+TUNE_FORCE = 0x1
+FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 
 
 # kernel roles reported by Plan.kernel_times (bit order of mxfft_plan_profile_roles)
@@ -33,6 +38,14 @@ class Params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("format", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("target", ctypes.c_double), ("tau_pct", ctypes.c_double), ("tau_min", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("lines", ctypes.c_int32), ("fast", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class Group(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("count", ctypes.c_int32), ("offset", ctypes.c_uint64)]
 
 
 class KernelTime(ctypes.Structure):
@@ -81,6 +94,25 @@ def lib():
         L.mxfft_status_string.argtypes = [i32]
         L.mxfft_version.restype = i32
         L.mxfft_version.argtypes = []
+        TP = ctypes.POINTER(Tuning)
+        for name in ("mxfft_plan_set_tuning", "mxfft_plan_get_tuning"):
+            getattr(L, name).restype = i32
+            getattr(L, name).argtypes = [P, TP]
+        L.mxfft_tune.restype = i32
+        L.mxfft_tune.argtypes = [i32, ctypes.POINTER(Params), i32, ctypes.c_char_p, u32, TP, P]
+        L.mxfft_tune_cache_lookup.restype = i32
+        L.mxfft_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, ctypes.POINTER(Params), TP]
+        L.mxfft_batch_create.restype = i32
+        L.mxfft_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Group), i32, ctypes.POINTER(Params),
+                                         ctypes.c_char_p, P]
+        L.mxfft_batch_execute.restype = i32
+        L.mxfft_batch_execute.argtypes = [P, i32, P, P, P, P]
+        L.mxfft_batch_last_status.restype = i32
+        L.mxfft_batch_last_status.argtypes = [P, P]
+        L.mxfft_batch_group_tuning.restype = i32
+        L.mxfft_batch_group_tuning.argtypes = [P, i32, TP]
+        L.mxfft_batch_destroy.restype = i32
+        L.mxfft_batch_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -206,9 +238,114 @@ class Plan:
     def device_bytes(self):
         return lib().mxfft_plan_device_bytes(self.handle)
 
+    def tuning(self):
+        t = Tuning()
+        st = lib().mxfft_plan_get_tuning(self.handle, ctypes.byref(t))
+        if st != OK:
+            raise MxfftError(st, "mxfft_plan_get_tuning")
+        return {"lines": t.lines, "fast": bool(t.fast)}
+
+    def set_tuning(self, lines):
+        t = Tuning(int(lines), 0, 0.0)
+        st = lib().mxfft_plan_set_tuning(self.handle, ctypes.byref(t))
+        if st != OK:
+            raise MxfftError(st, "mxfft_plan_set_tuning")
+
     def close(self):
         if getattr(self, "handle", None):
             lib().mxfft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cpath(path):
+    return None if path is None else os.fsencode(path)
+
+
+def tune(n, sample=16, cache=None, force=False, stream=None, **params):
+    """Autotune the generic line kernels for n (see mxfft_tune)."""
+    p = make_params(**params)
+    t = Tuning()
+    st = lib().mxfft_tune(int(n), ctypes.byref(p), int(sample), _cpath(cache), TUNE_FORCE if force else 0,
+                          ctypes.byref(t), _stream(stream))
+    if st != OK:
+        raise MxfftError(st, "mxfft_tune")
+    return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms}
+
+
+def tune_cache_lookup(cache, arch, n, **params):
+    """Host-only lookup in a tuning cache file; None when there is no entry."""
+    p = make_params(**params)
+    t = Tuning()
+    st = lib().mxfft_tune_cache_lookup(_cpath(cache), arch.encode(), int(n), ctypes.byref(p), ctypes.byref(t))
+    return None if st != OK else {"lines": t.lines, "ms": t.ms}
+
+
+class Batch:
+    """An uneven batch: groups [(n, count), ...] laid out one after another in
+    a flat complex64 pool (or with explicit offsets: (n, count, offset)),
+    executed as one HIP graph launch (mxfft_batch_*)."""
+
+    def __init__(self, groups, tune_cache=None, stream=None, **params):
+        self.params = make_params(**params)
+        arr = (Group * len(groups))()
+        off = 0
+        self.groups = []
+        for i, g in enumerate(groups):
+            n, count = int(g[0]), int(g[1])
+            o = int(g[2]) if len(g) > 2 else off
+            arr[i] = Group(n, count, o)
+            self.groups.append((n, count, o))
+            off = max(off, o + count * n * n)
+        self.pool_elems = off
+        self.slices = sum(c for _, c, _ in self.groups)
+        h = ctypes.c_void_p()
+        st = lib().mxfft_batch_create(ctypes.byref(h), arr, len(groups), ctypes.byref(self.params),
+                                      _cpath(tune_cache), _stream(stream))
+        if st != OK:
+            raise MxfftError(st, "mxfft_batch_create")
+        self.handle = h
+
+    def views(self, pool):
+        """The [count, n, n] view of each group inside a flat pool."""
+        return [pool[o:o + c * n * n].view(c, n, n) for n, c, o in self.groups]
+
+    def execute(self, op, x, out=None, k_out=None, stream=None):
+        if not (x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous() and x.numel() >= self.pool_elems):
+            raise ValueError("x must be a contiguous complex64 CUDA pool of >= %d values" % self.pool_elems)
+        out = torch.empty_like(x) if out is None else out
+        if not (out.is_cuda and out.dtype == torch.complex64 and out.is_contiguous() and out.numel() >= self.pool_elems):
+            raise ValueError("out must be a contiguous complex64 CUDA pool of >= %d values" % self.pool_elems)
+        if k_out is None and op != INVERSE:
+            k_out = torch.empty(self.slices, dtype=torch.int32, device=x.device)
+        if k_out is not None and not (k_out.is_cuda and k_out.dtype == torch.int32 and k_out.numel() >= self.slices):
+            raise ValueError("k_out must be an int32 CUDA tensor with >= %d entries" % self.slices)
+        st = lib().mxfft_batch_execute(self.handle, int(op), _ptr(x), _ptr(out), _ptr(k_out), _stream(stream))
+        if st != OK:
+            raise MxfftError(st, "mxfft_batch_execute")
+        return out, k_out
+
+    def forward(self, x, out=None, k_out=None, stream=None):
+        return self.execute(FORWARD, x, out, k_out, stream)
+
+    def last_status(self, stream=None):
+        return lib().mxfft_batch_last_status(self.handle, _stream(stream))
+
+    def group_tuning(self, g):
+        t = Tuning()
+        st = lib().mxfft_batch_group_tuning(self.handle, int(g), ctypes.byref(t))
+        if st != OK:
+            raise MxfftError(st, "mxfft_batch_group_tuning")
+        return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mxfft_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -75,3 +75,44 @@ def test_bad_struct_size_and_nulls():
     assert mxfft.lib().mxfft_roundtrip(None, None, None, 1, None, None) == mxfft.EINVAL
     assert mxfft.lib().mxfft_plan_last_status(None, None) == mxfft.EINVAL
     assert mxfft.lib().mxfft_plan_destroy(None) == mxfft.OK
+
+
+def test_tune_cache_lookup_host(tmp_path):
+    """The tuning cache is plain text, one entry per line; lookups match on
+    (arch, n, format, block), block counting only for the MX formats, and
+    skip malformed lines."""
+    path = tmp_path / "tune.json"
+    path.write_text(
+        '{"arch": "gfx950:sramecc+:xnack-", "n": 256, "format": 0, "block": 32, "lines": 8, "ms": 0.25}\n'
+        'not an entry\n'
+        '{"arch": "gfx950:sramecc+:xnack-", "n": 256, "format": 0, "block": 16, "lines": 4, "ms": 0.5}\n'
+        '{"arch": "gfx942", "n": 256, "format": 0, "block": 32, "lines": 2, "ms": 1.0}\n'
+        '{"arch": "gfx950:sramecc+:xnack-", "n": 64, "format": 2, "block": 0, "lines": 16, "ms": 0.125}\n')
+    arch = "gfx950:sramecc+:xnack-"
+    assert mxfft.tune_cache_lookup(str(path), arch, 256) == {"lines": 8, "ms": 0.25}
+    assert mxfft.tune_cache_lookup(str(path), arch, 256, block=16) == {"lines": 4, "ms": 0.5}
+    assert mxfft.tune_cache_lookup(str(path), "gfx942", 256) == {"lines": 2, "ms": 1.0}
+    assert mxfft.tune_cache_lookup(str(path), arch, 64, fmt="fp16", block=8) == {"lines": 16, "ms": 0.125}
+    assert mxfft.tune_cache_lookup(str(path), arch, 128) is None
+    assert mxfft.tune_cache_lookup(str(path), arch, 256, fmt="e5m2") is None
+    assert mxfft.tune_cache_lookup(str(tmp_path / "missing.json"), arch, 256) is None
+
+
+def batch_status(groups, **kw):
+    p = mxfft.make_params(**kw)
+    arr = (mxfft.Group * max(1, len(groups)))(*[mxfft.Group(*g) for g in groups])
+    h = ctypes.c_void_p()
+    return mxfft.lib().mxfft_batch_create(ctypes.byref(h), arr, len(groups), ctypes.byref(p), None, None)
+
+
+@pytest.mark.parametrize("groups", [
+    [],                                          # no group
+    [(63, 1, 0)],                                # not a power of two
+    [(64, 0, 0)],                                # empty group
+    [(8192, 1, 0)],                              # above 4096
+    [(64, 2, 0), (32, 1, 64 * 64)],              # second group starts inside the first
+    [(16, 1, 1000), (16, 4, 800)],               # overlap in the other order
+])
+def test_batch_create_rejects_bad_groups(groups):
+    """Group lists are checked on the host before any device call."""
+    assert batch_status(groups) == mxfft.EINVAL
