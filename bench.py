@@ -7,7 +7,9 @@ prescale (T = 2^7, tau = 5 %, tau_min = 2^-6).  A step is one forward call over
 the whole resident batch.  Also timed: the plain FP32 form of the same FFT on
 the same batch, the other formats of the precision sweep (the other MX element
 format, FP16, BF16; forward, slices/s and accuracy against FP64 each), and the
-CPU oracle on a bounded sample (host cores).
+CPU oracle on a bounded sample (host cores), a device copy and rocFFT's FP32
+FFT of the same batch (context), and one graph launch over an uneven work list
+of 128^2..1024^2 slices.
 
 Prints one JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload kspace512_64x16]
@@ -46,6 +48,8 @@ def parse():
     ap.add_argument("--block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the other formats (E5M2/E4M3, FP16, BF16, FP32)")
+    ap.add_argument("--no-context", action="store_true", help="skip the device copy and rocFFT context timings")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven work list (sizes 128..1024)")
     ap.add_argument("--cpu-sample", type=int, default=32, help="slices the CPU oracle transforms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of the input (known bytes) to scale HBM counters")
@@ -78,6 +82,51 @@ def timed_steps(fn, steps, warmup, torch):
     wall = time.perf_counter() - t0
     per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     return wall, per
+
+
+def uneven_workload(seed=20251204):
+    """The uneven work list: 512 reconstructions whose sizes follow 4:3:2:1
+    over 128^2, 256^2, 512^2, 1024^2 (largest-remainder counts 205, 154, 102,
+    51), shuffled, each with U{1..16} coils.  Returns [(n, coils)] in order."""
+    rng = np.random.default_rng([seed, 4])
+    sizes = [128] * 205 + [256] * 154 + [512] * 102 + [1024] * 51
+    rng.shuffle(sizes)
+    coils = rng.integers(1, 17, size=len(sizes))
+    return list(zip(sizes, coils.tolist()))
+
+
+def uneven_batch(args, torch, mxfft, synth):
+    """One graph launch over the uneven work list.  The pool holds the slices
+    grouped by size (one group per size, as a scheduler that packs same-size
+    slices would lay them out); its data repeats 8 distinct synthetic coil
+    slices per size (the transform's time does not depend on the values)."""
+    recon = uneven_workload()
+    counts = {}
+    for n, c in recon:
+        counts[n] = counts.get(n, 0) + c
+    groups = [(n, counts[n]) for n in sorted(counts)]
+    b = mxfft.Batch(groups, fmt=args.fmt, block=args.block)
+    pool = torch.empty(b.pool_elems, dtype=torch.complex64, device="cuda")
+    for (n, c, o) in b.groups:
+        distinct = torch.from_numpy(synth.kspace_batch(n, 4, 1, 8)).cuda()
+        reps = (c + 7) // 8
+        pool[o:o + c * n * n].view(c, n, n).copy_(distinct.repeat(reps, 1, 1)[:c])
+    out = torch.empty_like(pool)
+    k = torch.empty(b.slices, dtype=torch.int32, device="cuda")
+    run = lambda: b.forward(pool, out, k)   # noqa: E731
+    wall, per = timed_steps(run, args.steps, args.warmup, torch)
+    assert b.last_status() == mxfft.OK
+    elems = sum(n * n * c for n, c in groups)
+    res = {"metric": "slices/s of one graph launch over the uneven work list", "value": round(b.slices * args.steps / wall, 1),
+           "unit": "slices/s", "ms_per_step": round(1e3 * wall / args.steps, 4),
+           "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4), "p99": round(float(np.percentile(per, 99)), 4)},
+           "hbm_frac_algorithmic": round(elems * 16.0 * args.steps / wall / (HBM_PEAK_GBS * 1e9), 4),
+           "reconstructions": len(recon), "slices": b.slices,
+           "groups": [{"n": n, "slices": c, "tuning": b.group_tuning(i)} for i, (n, c) in enumerate(groups)],
+           "format": args.fmt, "block": args.block, "direction": "forward",
+           "data": "synthetic: 8 distinct coil slices per size, repeated"}
+    b.close()
+    return res
 
 
 def main():
@@ -207,6 +256,23 @@ def main():
             pl.close()
         result["precision_sweep"] = {"unit": "slices/s", "direction": "forward", "formats": sweep}
         result["speedup_vs_fp32"] = round(slices_per_s / sweep["fp32"]["value"], 3)
+
+    if not args.no_context:
+        # Context, not the product: a device copy of the batch (measured HBM
+        # bandwidth) and the FP32 C2C FFT of the vendor library (torch.fft on
+        # ROCm calls rocFFT) on the same batch.
+        wall_c, _ = timed_steps(lambda: out.copy_(xd), args.steps, args.warmup, torch)
+        copy_gbs = 2.0 * xd.numel() * 8 * args.steps / wall_c / 1e9
+        wall_r, _ = timed_steps(lambda: torch.fft.fft2(xd, out=out), args.steps, args.warmup, torch)
+        result["context"] = {
+            "device_copy": {"GB_per_s": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                            "what": "out.copy_(in) of the 2 GiB batch: read + write"},
+            "rocfft_fp32_c2c": {"value": round(batch * args.steps / wall_r, 1), "unit": "slices/s",
+                                "ms_per_step": round(1e3 * wall_r / args.steps, 4),
+                                "what": "torch.fft.fft2 (rocFFT) on the same batch, FP32"}}
+
+    if not args.no_uneven:
+        result["uneven_batch"] = uneven_batch(args, torch, mxfft, synth)
 
     if not args.no_cpu_baseline:
         import oracle

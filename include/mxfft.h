@@ -94,6 +94,11 @@ void mxfft_params_default(mxfft_params* p);
 mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch,
                         const mxfft_params* p, void* stream);
 
+/* Device bytes mxfft_plan would allocate for (n, max_batch, p), computed on
+ * the host without any HIP call (for capacity planning and admission).  The
+ * same argument checks as mxfft_plan. */
+mxfft_status mxfft_plan_bytes(int32_t n, int32_t max_batch, const mxfft_params* p, uint64_t* bytes);
+
 /* Release a plan (synchronises the device first).  NULL is accepted. */
 mxfft_status mxfft_plan_destroy(mxfft_plan_t plan);
 
@@ -225,6 +230,73 @@ mxfft_status mxfft_batch_group_tuning(mxfft_batch_t b, int32_t g, mxfft_tuning* 
 
 /* Release the batch, its plans, streams and graphs (synchronises the device). */
 mxfft_status mxfft_batch_destroy(mxfft_batch_t b);
+
+/* ---- Serving ------------------------------------------------------------
+ * A server accepts transform requests from any host thread and runs them on
+ * the device as capacity frees up.  One scheduler thread admits queued
+ * requests in arrival order (no overtaking) while a stream slot is free and
+ * the device memory of the plans it holds stays within the budget: plans
+ * (tables and workspace) are pooled by (n, parameters, batch capacity: the
+ * coil count rounded up to a power of two) and reused; idle plans are evicted,
+ * least recently used first, when a new one would exceed the budget.  Up to
+ * `slots` requests run at once, each on its own stream, so transfers of
+ * results and the kernels of different requests overlap.  A request's input
+ * and output stay caller-owned (pre-staged device buffers); each request is
+ * computed exactly as a single mxfft_forward / mxfft_inverse / mxfft_roundtrip
+ * call on its coils would be, so its result does not depend on what else
+ * runs. */
+typedef struct mxfft_server_s* mxfft_server_t;
+
+typedef struct {
+    const void* in;       /* device complex64 [coils][n][n] */
+    void* out;            /* device complex64 [coils][n][n] (may equal in) */
+    int32_t* k_out;       /* device int32[coils] or NULL (forward and round trip) */
+    int32_t n;            /* slice size (power of two, 2..4096) */
+    int32_t coils;        /* slices in the request, 1..65535 */
+    int32_t op;           /* 0 forward, 1 inverse (own prescale), 2 round trip */
+    mxfft_params params;  /* format, block, prescale parameters, flags */
+} mxfft_request;
+
+typedef struct {
+    int32_t status;       /* MXFFT_OK, or the request's device status (ENONFINITE, ERANGE) */
+    int32_t slot;         /* stream slot it ran on */
+    double t_submit_ms;   /* host steady clock, ms since the server was created */
+    double t_start_ms;    /* launched */
+    double t_done_ms;     /* completion seen by the scheduler */
+} mxfft_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected;
+    uint64_t queued, in_flight;           /* now */
+    uint64_t plan_bytes, peak_plan_bytes; /* device bytes of the pooled plans: now, highest */
+    uint64_t plans_created, plans_evicted;
+    uint64_t budget;
+} mxfft_serve_counters;
+
+/* Create a server with `slots` concurrent requests (1..16; each its own
+ * non-blocking stream of default priority) and a device-memory budget for its
+ * plans.  Starts the scheduler thread. */
+mxfft_status mxfft_serve_create(mxfft_server_t* out, uint64_t hbm_budget_bytes, int32_t slots);
+
+/* Queue a request (non-blocking; any thread).  *ticket identifies it.
+ * MXFFT_EINVAL for bad arguments and MXFFT_EBUDGET when its plan alone would
+ * exceed the budget (counted as rejected; nothing is queued). */
+mxfft_status mxfft_serve_submit(mxfft_server_t srv, const mxfft_request* req, uint64_t* ticket);
+
+/* Block until the request is done and fill *res; a ticket is answered once
+ * (then MXFFT_EINVAL).  The returned status is that of the call (MXFFT_OK when
+ * *res is filled); the request's own status is res->status. */
+mxfft_status mxfft_serve_wait(mxfft_server_t srv, uint64_t ticket, mxfft_result* res);
+
+/* As mxfft_serve_wait without blocking: MXFFT_EBUSY while it is not done. */
+mxfft_status mxfft_serve_poll(mxfft_server_t srv, uint64_t ticket, mxfft_result* res);
+
+/* Counters (a consistent snapshot). */
+mxfft_status mxfft_serve_stats(mxfft_server_t srv, mxfft_serve_counters* out);
+
+/* Finish every queued and running request, stop the scheduler and release
+ * the plans, streams and host buffers.  Unanswered tickets are dropped. */
+mxfft_status mxfft_serve_destroy(mxfft_server_t srv);
 
 /* Static text for a status code. */
 const char* mxfft_status_string(mxfft_status st);

@@ -91,6 +91,8 @@ struct mxfft_plan_s {
     int32_t* d_status = nullptr;
     // generic line kernels: lines per work-group (0 = line_lines_per_group)
     int lines = 0;
+    // sizing only: nothing is allocated or uploaded
+    bool dry = false;
     // register-resident path (n = 512): twiddles at [h + j], MX intermediate
     bool fast = false;
     float2* d_twf = nullptr;
@@ -198,14 +200,17 @@ mxfft_status check_params(const mxfft_params* p, int n)
     return MXFFT_OK;
 }
 
+// Device allocation of a plan's table or workspace; a dry plan only counts
+// the bytes (mxfft_plan_bytes).
 template <class T>
-mxfft_status dev_alloc(T** ptr, size_t count, uint64_t* total)
+mxfft_status dev_alloc(mxfft_plan_s* pl, T** ptr, size_t count)
 {
-    if (hipMalloc((void**)ptr, count * sizeof(T)) != hipSuccess) {
+    *ptr = nullptr;
+    if (!pl->dry && hipMalloc((void**)ptr, count * sizeof(T)) != hipSuccess) {
         *ptr = nullptr;
         return MXFFT_ENOMEM;
     }
-    *total += count * sizeof(T);
+    pl->bytes += count * sizeof(T);
     return MXFFT_OK;
 }
 
@@ -409,7 +414,14 @@ void mxfft_params_default(mxfft_params* p)
     p->tau_min = 1.0 / 64.0;
 }
 
-mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const mxfft_params* p, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Plan creation; with dry set, only the device bytes the plan would hold are
+// counted (no HIP call is made) and returned in *dry_bytes.
+mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const mxfft_params* p, void* stream,
+                         bool dry, uint64_t* dry_bytes)
 {
     if (!out) return MXFFT_EINVAL;
     *out = nullptr;
@@ -418,6 +430,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     MX_TRY(check_params(p, n));
 
     mxfft_plan_s* pl = new mxfft_plan_s();
+    pl->dry = dry;
     pl->n = n;
     pl->logn = ilog2(n);
     pl->max_batch = max_batch;
@@ -431,7 +444,7 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
         pl->cb = p->block / 2;
         pl->logcb = ilog2(pl->cb);
     }
-    (void)hipGetDevice(&pl->device);
+    if (!dry) (void)hipGetDevice(&pl->device);
     hipStream_t s = (hipStream_t)stream;
 
     std::vector<float2> tw;
@@ -439,17 +452,17 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     build_twiddles(pl, tw, tw_exp, pl->tw_exp_off);
 
     mxfft_status st = MXFFT_OK;
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw, tw.size(), &pl->bytes);
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_tw_exp, tw_exp.size(), &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
+    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw_exp, tw_exp.size());
     {
         // chunk statistics: the literal statistics pass, or one part per row tile
         size_t parts = mxk::stats_parts(n, max_batch);
         if (mxk::fast_supported(pl->mode, n, pl->cb) && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2))
             parts = std::max(parts, (size_t)max_batch * mxk::fast_row_tiles(n));
-        if (st == MXFFT_OK) st = dev_alloc(&pl->d_parts, parts, &pl->bytes);
+        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_parts, parts);
     }
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_kp, (size_t)max_batch, &pl->bytes);
-    if (st == MXFFT_OK) st = dev_alloc(&pl->d_status, (size_t)max_batch, &pl->bytes);
+    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_kp, (size_t)max_batch);
+    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_status, (size_t)max_batch);
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     std::vector<float2> twf;
     std::vector<uint32_t> tw16;
@@ -457,17 +470,17 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
         twf.assign((size_t)n, make_float2(0.f, 0.f));
         for (long h = 1; h < n; h <<= 1)
             for (long j = 0; j < h; j++) twf[h + j] = tw[h - 1 + j];
-        st = dev_alloc(&pl->d_twf, twf.size(), &pl->bytes);
+        st = dev_alloc(pl, &pl->d_twf, twf.size());
         if (st == MXFFT_OK && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2)) {
-            st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n / 2, &pl->bytes);
-            if (st == MXFFT_OK) st = dev_alloc(&pl->d_exps, (size_t)max_batch * n * (n / pl->cb), &pl->bytes);
+            st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n / 2);
+            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_exps, (size_t)max_batch * n * (n / pl->cb));
             pl->fused = true;
-            if (st == MXFFT_OK) st = dev_alloc(&pl->d_kadd, (size_t)max_batch, &pl->bytes);
-            if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_list, (size_t)max_batch, &pl->bytes);
-            if (st == MXFFT_OK) st = dev_alloc(&pl->d_fix_count, 1, &pl->bytes);
+            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_kadd, (size_t)max_batch);
+            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_list, (size_t)max_batch);
+            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_count, 1);
         }
         if (st == MXFFT_OK && (pl->mode == mxk::MODE_FP16 || pl->mode == mxk::MODE_BF16))
-            st = dev_alloc(&pl->d_codes, (size_t)max_batch * n * n, &pl->bytes);   // one packed pair per value
+            st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n);   // one packed pair per value
         if (st == MXFFT_OK && pl->mode == mxk::MODE_FP16) {
             // the twiddles are halves already: packed exactly
             tw16.assign((size_t)n, 0u);
@@ -478,8 +491,13 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
                 std::memcpy(&bi, &im, 2);
                 tw16[i] = (uint32_t)br | ((uint32_t)bi << 16);
             }
-            st = dev_alloc(&pl->d_tw16, tw16.size(), &pl->bytes);
+            st = dev_alloc(pl, &pl->d_tw16, tw16.size());
         }
+    }
+    if (dry) {
+        *dry_bytes = pl->bytes;
+        delete pl;
+        return st;
     }
     if (st != MXFFT_OK) {
         release(pl);
@@ -499,6 +517,31 @@ mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const m
     }
     *out = pl;
     return MXFFT_OK;
+}
+
+}  // namespace
+
+namespace mxk {
+
+const int32_t* plan_status_words(mxfft_plan_t pl) { return pl->d_status; }
+
+bool plan_has_status(mxfft_plan_t pl) { return !(pl->p.flags & MXFFT_NO_PRESCALE); }
+
+}  // namespace mxk
+
+extern "C" {
+
+mxfft_status mxfft_plan(mxfft_plan_t* out, int32_t n, int32_t max_batch, const mxfft_params* p, void* stream)
+{
+    return plan_create(out, n, max_batch, p, stream, false, nullptr);
+}
+
+mxfft_status mxfft_plan_bytes(int32_t n, int32_t max_batch, const mxfft_params* p, uint64_t* bytes)
+{
+    if (!bytes) return MXFFT_EINVAL;
+    mxfft_plan_t tmp = nullptr;
+    *bytes = 0;
+    return plan_create(&tmp, n, max_batch, p, nullptr, true, bytes);
 }
 
 mxfft_status mxfft_plan_destroy(mxfft_plan_t plan)

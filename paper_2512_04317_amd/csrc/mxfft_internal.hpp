@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct mxfft_plan_s;
+
 namespace mxk {
 
 constexpr int kMaxLog2N = 12;       // n <= 4096
@@ -111,5 +113,10 @@ hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);
 // Synthetic finite data (tuning): count complex values, both parts in [-1, 1).
 hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s);
+
+// Device status words of a plan (one int32 per slice of its last call, written
+// by the prescale statistics), and whether its calls write them.
+const int32_t* plan_status_words(mxfft_plan_s* pl);
+bool plan_has_status(mxfft_plan_s* pl);
 
 }  // namespace mxk

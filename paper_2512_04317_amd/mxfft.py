@@ -25,7 +25,8 @@ EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_fo
            "mxfft_plan_kernel_times", "mxfft_plan_device_bytes", "mxfft_status_string", "mxfft_version",
            "mxfft_plan_set_tuning", "mxfft_plan_get_tuning", "mxfft_tune", "mxfft_tune_cache_lookup",
            "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
-           "mxfft_batch_destroy")
+           "mxfft_batch_destroy", "mxfft_plan_bytes", "mxfft_serve_create", "mxfft_serve_submit",
+           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy")
 TUNE_FORCE = 0x1
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 
@@ -46,6 +47,22 @@ class Tuning(ctypes.Structure):
 
 class Group(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("count", ctypes.c_int32), ("offset", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("k_out", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("coils", ctypes.c_int32), ("op", ctypes.c_int32), ("params", Params)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("t_submit_ms", ctypes.c_double),
+                ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+class ServeCounters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "submitted", "admitted", "completed", "rejected", "queued", "in_flight", "plan_bytes", "peak_plan_bytes",
+        "plans_created", "plans_evicted", "budget")]
 
 
 class KernelTime(ctypes.Structure):
@@ -113,6 +130,19 @@ def lib():
         L.mxfft_batch_group_tuning.argtypes = [P, i32, TP]
         L.mxfft_batch_destroy.restype = i32
         L.mxfft_batch_destroy.argtypes = [P]
+        L.mxfft_plan_bytes.restype = i32
+        L.mxfft_plan_bytes.argtypes = [i32, i32, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint64)]
+        L.mxfft_serve_create.restype = i32
+        L.mxfft_serve_create.argtypes = [ctypes.POINTER(P), ctypes.c_uint64, i32]
+        L.mxfft_serve_submit.restype = i32
+        L.mxfft_serve_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        for name in ("mxfft_serve_wait", "mxfft_serve_poll"):
+            getattr(L, name).restype = i32
+            getattr(L, name).argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.mxfft_serve_stats.restype = i32
+        L.mxfft_serve_stats.argtypes = [P, ctypes.POINTER(ServeCounters)]
+        L.mxfft_serve_destroy.restype = i32
+        L.mxfft_serve_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -346,6 +376,84 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().mxfft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_bytes(n, max_batch, **params):
+    """Device bytes a plan would hold (host-only computation)."""
+    p = make_params(**params)
+    b = ctypes.c_uint64()
+    st = lib().mxfft_plan_bytes(int(n), int(max_batch), ctypes.byref(p), ctypes.byref(b))
+    if st != OK:
+        raise MxfftError(st, "mxfft_plan_bytes")
+    return b.value
+
+
+class Server:
+    """A request server (mxfft_serve_*): submit() from any thread, wait()."""
+
+    def __init__(self, budget_bytes, slots=4):
+        h = ctypes.c_void_p()
+        st = lib().mxfft_serve_create(ctypes.byref(h), int(budget_bytes), int(slots))
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_create")
+        self.handle = h
+
+    def submit(self, x, out, k_out=None, op=FORWARD, **params):
+        """Queue one request over x = [coils, n, n]; returns its ticket.  Raises
+        MxfftError (status EBUDGET when its plan alone exceeds the budget)."""
+        if not (x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous() and x.dim() == 3):
+            raise ValueError("x must be a contiguous complex64 CUDA tensor [coils, n, n]")
+        if not (out.is_cuda and out.dtype == torch.complex64 and out.is_contiguous() and out.shape == x.shape):
+            raise ValueError("out must be a contiguous complex64 CUDA tensor shaped like x")
+        if k_out is not None and not (k_out.is_cuda and k_out.dtype == torch.int32 and k_out.numel() >= x.shape[0]):
+            raise ValueError("k_out must be an int32 CUDA tensor with >= coils entries")
+        r = Request(x.data_ptr(), out.data_ptr(), None if k_out is None else k_out.data_ptr(),
+                    int(x.shape[1]), int(x.shape[0]), int(op), make_params(**params))
+        t = ctypes.c_uint64()
+        st = lib().mxfft_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_submit")
+        return t.value
+
+    @staticmethod
+    def _res(r):
+        return {"status": r.status, "slot": r.slot, "t_submit_ms": r.t_submit_ms, "t_start_ms": r.t_start_ms,
+                "t_done_ms": r.t_done_ms}
+
+    def wait(self, ticket):
+        r = Result()
+        st = lib().mxfft_serve_wait(self.handle, int(ticket), ctypes.byref(r))
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_wait")
+        return self._res(r)
+
+    def poll(self, ticket):
+        """The result, or None while the request runs."""
+        r = Result()
+        st = lib().mxfft_serve_poll(self.handle, int(ticket), ctypes.byref(r))
+        if st == EBUSY:
+            return None
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_poll")
+        return self._res(r)
+
+    def stats(self):
+        c = ServeCounters()
+        st = lib().mxfft_serve_stats(self.handle, ctypes.byref(c))
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_stats")
+        return {name: getattr(c, name) for name, _ in ServeCounters._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mxfft_serve_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
