@@ -14,6 +14,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmxfft.so")
 
 SOURCES = ["mxfft_kernels.hip", "mxfft_fast.hip", "fast_e4m3.hip", "fast_e5m2.hip", "fast_fp32.hip",
+           "fast_e4m3_256.hip", "fast_e5m2_256.hip", "fast_e4m3_1024.hip", "fast_e5m2_1024.hip",
            "fast_fp16.hip", "fast_bf16.hip", "mxfft_host.cpp", "mxfft_tune.cpp", "mxfft_batch.cpp",
            "mxfft_serve.cpp"]
 HEADERS = ["mx_device.hpp", "mxfft_internal.hpp", "mxfft_fast.hpp"]
@@ -55,7 +56,7 @@ def build(verbose=False, incremental=False):
         if (not incremental or not os.path.exists(obj)
                 or os.path.getmtime(obj) < max(os.path.getmtime(os.path.join(CSRC, s)), newest_hdr)):
             todo.append(s)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
+    with ThreadPoolExecutor(min(len(SOURCES), os.cpu_count() or 4, 16)) as ex:
         list(ex.map(lambda s: _compile(s, verbose), todo))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + \

@@ -1,4 +1,6 @@
 // fast_e4m3.hip -- instantiations of the register-resident 512^2 passes for MXFP8-E4M3.
+#define MXF_LOGN 9
+#define MXF_NS mxf
 #include "mxfft_fast.hpp"
 
 namespace mxk {

@@ -1,0 +1,32 @@
+// fast_e4m3_1024.hip -- instantiations of the register-resident 1024^2 passes for MXFP8-E4M3.
+#define MXF_LOGN 10
+#define MXF_NS mxf1024
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+hipError_t launch_fast_e4m3_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch,
+                               hipStream_t s)
+{
+    const dim3 grid((mxf1024::N / mxf1024::LINES) * batch), block(mxf1024::THREADS);
+#define MXF_CASE(CC, INV)                                                                                  \
+    if (!row) hipLaunchKernelGGL((mxf1024::k_col<0, CC, INV>), grid, block, 0, s, g);                  \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf1024::k_row<0, CC, INV, ROW_STATS>), grid, block, 0, s, g);   \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf1024::k_row_fix<0, CC, INV>), grid, block, 0, s, g);           \
+    else hipLaunchKernelGGL((mxf1024::k_row<0, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
+    switch (cb * 2 + (inverse ? 1 : 0)) {
+    case 4: MXF_CASE(1, false) break;
+    case 5: MXF_CASE(1, true) break;
+    case 8: MXF_CASE(2, false) break;
+    case 9: MXF_CASE(2, true) break;
+    case 16: MXF_CASE(3, false) break;
+    case 17: MXF_CASE(3, true) break;
+    case 32: MXF_CASE(4, false) break;
+    case 33: MXF_CASE(4, true) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MXF_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mxk

@@ -1,4 +1,6 @@
 // fast_fp16.hip -- instantiations of the register-resident 512^2 passes for the FP16 form.
+#define MXF_LOGN 9
+#define MXF_NS mxf
 #include "mxfft_fast.hpp"
 
 namespace mxk {

@@ -1,4 +1,6 @@
 // mxfft_fast.hip -- dispatch of the register-resident 512^2 passes.
+#define MXF_LOGN 9
+#define MXF_NS mxf
 #include "mxfft_fast.hpp"
 
 namespace mxk {
@@ -8,22 +10,31 @@ hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, int kind, const mxf:
 hipError_t launch_fast_fp32(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_fp16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_bf16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e4m3_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e5m2_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e4m3_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e5m2_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 
 bool fast_supported(int mode, int n, int cb)
 {
-    if (n != mxf::N) return false;
-    if (mode == MODE_FP32 || mode == MODE_FP16 || mode == MODE_BF16) return true;
-    if (mode != MODE_E4M3 && mode != MODE_E5M2) return false;
-    return cb >= 2 && cb <= 16;
+    const bool mx = (mode == MODE_E4M3 || mode == MODE_E5M2) && cb >= 2 && cb <= 16;
+    if (n == 512) return mx || mode == MODE_FP32 || mode == MODE_FP16 || mode == MODE_BF16;
+    return (n == 256 || n == 1024) && mx;
+}
+
+bool fast_fused_stats(int mode, int n)
+{
+    // the statistics histogram lives in the exchange planes of the row pass
+    return (mode == MODE_E4M3 || mode == MODE_E5M2) && (n == 512 || n == 1024);
 }
 
 int fast_row_tiles(int n)
 {
-    return n / mxf::LINES;
+    return n / 16;   // 16 lines per work-group at every size
 }
 
-hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const FastPassArgs& p, int batch,
-                       hipStream_t s)
+hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind, const FastPassArgs& p,
+                       int batch, hipStream_t s)
 {
     mxf::FastArgs g{};
     g.src = p.src;
@@ -43,12 +54,16 @@ hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const
     g.fix_list = p.fix_list;
     g.fix_count = p.fix_count;
     g.tw16 = p.tw16;
-    switch (mode) {
-    case MODE_E4M3: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
-    case MODE_E5M2: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);
-    case MODE_FP32: return launch_fast_fp32(cb, row, inverse, kind, g, batch, s);
-    case MODE_FP16: return launch_fast_fp16(cb, row, inverse, kind, g, batch, s);
-    case MODE_BF16: return launch_fast_bf16(cb, row, inverse, kind, g, batch, s);
+    switch (mode * 4096 + n) {
+    case MODE_E4M3 * 4096 + 512: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
+    case MODE_E5M2 * 4096 + 512: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);
+    case MODE_FP32 * 4096 + 512: return launch_fast_fp32(cb, row, inverse, kind, g, batch, s);
+    case MODE_FP16 * 4096 + 512: return launch_fast_fp16(cb, row, inverse, kind, g, batch, s);
+    case MODE_BF16 * 4096 + 512: return launch_fast_bf16(cb, row, inverse, kind, g, batch, s);
+    case MODE_E4M3 * 4096 + 256: return launch_fast_e4m3_256(cb, row, inverse, kind, g, batch, s);
+    case MODE_E5M2 * 4096 + 256: return launch_fast_e5m2_256(cb, row, inverse, kind, g, batch, s);
+    case MODE_E4M3 * 4096 + 1024: return launch_fast_e4m3_1024(cb, row, inverse, kind, g, batch, s);
+    case MODE_E5M2 * 4096 + 1024: return launch_fast_e5m2_1024(cb, row, inverse, kind, g, batch, s);
     default: return hipErrorInvalidValue;
     }
 }

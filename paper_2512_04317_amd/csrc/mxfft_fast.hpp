@@ -26,7 +26,15 @@
 // arithmetic for FP16, FP32 products and packed conversions for BF16) and a
 // 16-bit intermediate: the column pass input is the row pass output rounded
 // to the format, so storing it rounded loses nothing.
-#pragma once
+//
+// The header is included once per slice size: the including file defines
+// MXF_LOGN (8, 9 or 10) and MXF_NS (the namespace of that size's kernels).
+// The size-independent part (element arithmetic, kernel arguments) is
+// compiled once per translation unit.
+
+#ifndef MXFFT_FAST_COMMON_HPP
+#define MXFFT_FAST_COMMON_HPP
+
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -35,7 +43,6 @@
 
 #include "mx_device.hpp"
 #include "mxfft_internal.hpp"
-
 namespace mxf {
 
 typedef short short2v __attribute__((ext_vector_type(2)));
@@ -43,13 +50,6 @@ typedef float float2v __attribute__((ext_vector_type(2)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
 
-constexpr int LOGN = 9;
-constexpr int N = 1 << LOGN;
-constexpr int P = 32;            // complex values per lane
-constexpr int LPL = N / P;       // lanes per line (16)
-constexpr int LPW = 64 / LPL;    // lines per wave (4)
-constexpr int WAVES = 4;
-constexpr int LINES = LPW * WAVES;  // lines per work-group (16)
 constexpr int FP16 = 2;          // format ids of the plain forms (mxk::MODE_FP16,
 constexpr int BF16 = 3;          // mxk::MODE_BF16, mxk::MODE_FP32); 0 and 1 are
 constexpr int FP32 = 4;          // the MX element formats E4M3 and E5M2
@@ -89,126 +89,6 @@ constexpr int rev(int v, int bits)
     for (int b = 0; b < bits; b++) r |= ((v >> b) & 1) << (bits - 1 - b);
     return r;
 }
-
-// Layouts for MX blocks of 2^C butterflies (1 <= C <= 4).
-template <int C>
-struct Lay {
-    static constexpr int NEW = 5 - C;
-    static constexpr int NL = 1 + (LOGN - 5 + NEW - 1) / NEW;
-    // position bit held by in-lane offset bit i in layout k
-    static constexpr int fbit(int k, int i)
-    {
-        if (k == 0 || i < C) return i;
-        const int b = 5 + (k - 1) * NEW + (i - C);
-        return b < LOGN ? b : C + (b - LOGN);
-    }
-    static constexpr int index_of(int k, int bit)
-    {
-        for (int i = 0; i < 5; i++)
-            if (fbit(k, i) == bit) return i;
-        return -1;
-    }
-    // q-th position bit fixed per lane (ascending), taken from lane bit q
-    static constexpr int xbit(int k, int q)
-    {
-        int cnt = 0;
-        for (int b = 0; b < LOGN; b++)
-            if (index_of(k, b) < 0) {
-                if (cnt == q) return b;
-                cnt++;
-            }
-        return -1;
-    }
-    static constexpr int posF(int k, int o)
-    {
-        int p = 0;
-        for (int i = 0; i < 5; i++)
-            if ((o >> i) & 1) p |= 1 << fbit(k, i);
-        return p;
-    }
-    static constexpr int bfirst(int k) { return k == 0 ? 0 : 5 + (k - 1) * NEW; }
-    static constexpr int blast(int k)
-    {
-        const int e = (k == 0) ? 5 : 5 + k * NEW;
-        return e < LOGN ? e : LOGN;
-    }
-};
-
-template <int C, int K>
-__device__ __forceinline__ int posM(int m)
-{
-    int p = 0;
-    sfor<LOGN - 5>([&](auto Q) { p |= ((m >> Q) & 1) << Lay<C>::xbit(K, Q); });
-    return p;
-}
-
-// LDS plane slot of position p of a line: 32-word rows (p >> 5) padded by a
-// sum of per-bit amounts, slot(p) = p + 2 b5 + 4 b6 + 12 b7 + 18 b8 (b_j bit
-// j of p).  The padding grows with the row index, so rows never overlap (548
-// words per line), and it is additive: for p = c | m with disjoint in-lane
-// bits c and lane bits m, slot(p) = slot(c) + slot(m), so every access is a
-// per-lane base plus a compile-time offset, with no address arithmetic per
-// access.  The amounts and the line bases (lines 584 words apart, odd pairs
-// 16 words further) were chosen by enumeration against the LDS bank model of
-// the target (64- and 128-bit accesses served by 32 banks of 8 bytes, 32-bit
-// ones by 32 banks of 4 bytes): the layout exchanges of every block size reach
-// 1.0-1.25 times the conflict-free cycle count (1.06 for blocks of 16
-// butterflies).
-__host__ __device__ constexpr int slot(int p)
-{
-    return p + 2 * ((p >> 5) & 1) + 4 * ((p >> 6) & 1) + 12 * ((p >> 7) & 1) + 18 * ((p >> 8) & 1);
-}
-
-constexpr int PLINE = 548;               // words spanned by one line's slots
-constexpr int WPL = 3 * 584 + 16 + PLINE; // words of one wave's planes (4 lines)
-static_assert(slot(511) == PLINE - 1, "slot range");
-// base of line l within its wave's planes
-__device__ __forceinline__ int line_base(int l) { return 584 * l + 16 * (l >> 1); }
-
-// pext: the bits of v at the set positions of MASK, packed from bit 0
-template <int MASK>
-__device__ __forceinline__ int pext(int v)
-{
-    int r = 0, q = 0;
-    sfor<LOGN>([&](auto B) {
-        if constexpr ((MASK >> B) & 1) { r |= ((v >> B) & 1) << q; q++; }
-    });
-    return r;
-}
-
-// position bits held by the lanes (not in-lane) in layout K
-template <int C, int K>
-constexpr int lane_mask()
-{
-    int mk = 0;
-    for (int q = 0; q < LOGN - 5; q++) mk |= 1 << Lay<C>::xbit(K, q);
-    return mk;
-}
-
-// Slot (in float2) of row r (0..255), column c (0..15) of a 256 x 16 complex
-// tile written by lanes whose rows differ in the bits LM (4 bits; x are those
-// bits of r): row bit 0 flips with x bit 0 (unless bit 0 is itself a lane
-// bit) and column bits 2..3 XOR x bits 1..2, so one 64-bit store by a wave
-// (4 columns x 16 rows) hits every 8-byte bank exactly twice, while a row of
-// the tile stays one contiguous 128-byte run with column pairs kept adjacent.
-template <int LM>
-__device__ __forceinline__ int tslot(int r, int c)
-{
-    const int x = pext<LM>(r);
-    const int R = (LM & 1) ? r : (r ^ (x & 1));
-    return R * 16 + (c ^ (((x >> 1) & 3) << 2));
-}
-
-// Column slot in the [row][512] maximum and [block][512] scale arrays of the
-// row pass: bits 2..5 XOR bits 4..7, so the 16 lanes of a line (16 different
-// 4-column groups in every final layout) cover all banks.
-__device__ __forceinline__ int csw(int c) { return c ^ (((c >> 4) & 15) << 2); }
-
-// Word swizzle of the MX intermediate: in the 32-byte row segment of a
-// 16-column group, the word of columns 2w, 2w+1 sits at w ^ cswz(row).  The
-// column pass copies a group's 512 rows verbatim into LDS; its 32-bit reads
-// (rows 16k + r for r = 0..15, two words per wave) then reach 32 distinct banks.
-__device__ __forceinline__ int cswz(int row) { return ((row >> 2) & 3) << 1; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -451,8 +331,215 @@ __device__ __forceinline__ float2 cmul_bf16(float2 w, uint32_t vb, bool& sub)
 }
 
 // ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+
+struct FastArgs {
+    const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
+    float2* dst;             // complex64 output (row pass FP32 form / column pass)
+    uint32_t* codes;         // intermediate, [slice][16-column group][row][...]: MX, 8 words of 2 code
+                             // pairs (swizzled); FP16/BF16, 16 words of one packed complex value
+    uint8_t* exps;           // MX intermediate: [slice][row block][column] E8M0 bytes
+    const int32_t* kp;       // per-slice prescale exponent or nullptr
+    int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
+    int32_t kin_mul, kout_mul, kout_add;
+    const float2* tw;
+    const int32_t* tw_exp;
+    int32_t tw_off[16];
+    mxk::StatPart* parts;    // row pass with statistics: [slice][tile]
+    const int32_t* kadd;     // column pass: per-slice offset of the stored exponents, or nullptr
+    const int32_t* fix_list; // list-driven row pass: slices to redo
+    int32_t* fix_count;      // list length (zeroed by the row pass with statistics)
+    const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
+};
+
+using mxk::kStatsBins;
+using mxk::StatPart;
+using mxk::ROW_PLAIN;
+using mxk::ROW_STATS;
+using mxk::ROW_FIX;
+
+__device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
+{
+    int k = g.kp ? g.kp[slice] : 0;
+    return k == INT32_MIN ? 0 : k;
+}
+
+
+template <class T>
+__device__ __forceinline__ T wave_reduce_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_reduce_min(T v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+}  // namespace mxf
+
+#endif  // MXFFT_FAST_COMMON_HPP
+
+#if !defined(MXF_LOGN) || !defined(MXF_NS)
+#error "define MXF_LOGN and MXF_NS before including mxfft_fast.hpp"
+#endif
+
+namespace MXF_NS {
+
+using namespace mxf;
+
+constexpr int LOGN = MXF_LOGN;
+constexpr int N = 1 << LOGN;
+constexpr int P = 32;               // complex values per lane
+constexpr int LOG_LPL = LOGN - 5;
+constexpr int LPL = N / P;          // lanes per line (16 at n = 512)
+constexpr int LPW = 64 / LPL;       // lines per wave (4 at n = 512)
+constexpr int LINES = 16;           // lines per work-group
+constexpr int WAVES = LINES / LPW;  // waves per work-group (4 at n = 512)
+constexpr int THREADS = 64 * WAVES;
+static_assert(LOGN >= 8 && LOGN <= 10, "register-resident passes for n = 256, 512, 1024");
+
+// Layouts for MX blocks of 2^C butterflies (1 <= C <= 4).
+template <int C>
+struct Lay {
+    static constexpr int NEW = 5 - C;
+    static constexpr int NL = 1 + (LOGN - 5 + NEW - 1) / NEW;
+    // position bit held by in-lane offset bit i in layout k
+    static constexpr int fbit(int k, int i)
+    {
+        if (k == 0 || i < C) return i;
+        const int b = 5 + (k - 1) * NEW + (i - C);
+        return b < LOGN ? b : C + (b - LOGN);
+    }
+    static constexpr int index_of(int k, int bit)
+    {
+        for (int i = 0; i < 5; i++)
+            if (fbit(k, i) == bit) return i;
+        return -1;
+    }
+    // q-th position bit fixed per lane (ascending), taken from lane bit q
+    static constexpr int xbit(int k, int q)
+    {
+        int cnt = 0;
+        for (int b = 0; b < LOGN; b++)
+            if (index_of(k, b) < 0) {
+                if (cnt == q) return b;
+                cnt++;
+            }
+        return -1;
+    }
+    static constexpr int posF(int k, int o)
+    {
+        int p = 0;
+        for (int i = 0; i < 5; i++)
+            if ((o >> i) & 1) p |= 1 << fbit(k, i);
+        return p;
+    }
+    static constexpr int bfirst(int k) { return k == 0 ? 0 : 5 + (k - 1) * NEW; }
+    static constexpr int blast(int k)
+    {
+        const int e = (k == 0) ? 5 : 5 + k * NEW;
+        return e < LOGN ? e : LOGN;
+    }
+};
+
+template <int C, int K>
+__device__ __forceinline__ int posM(int m)
+{
+    int p = 0;
+    sfor<LOGN - 5>([&](auto Q) { p |= ((m >> Q) & 1) << Lay<C>::xbit(K, Q); });
+    return p;
+}
+
+// LDS plane slot of position p of a line: 32-word rows (p >> 5) padded by a
+// sum of per-bit amounts, slot(p) = p + 2 b5 + 4 b6 + 12 b7 + 18 b8 (b_j bit
+// j of p).  The padding grows with the row index, so rows never overlap (548
+// words per line), and it is additive: for p = c | m with disjoint in-lane
+// bits c and lane bits m, slot(p) = slot(c) + slot(m), so every access is a
+// per-lane base plus a compile-time offset, with no address arithmetic per
+// access.  The amounts and the line bases (lines 584 words apart, odd pairs
+// 16 words further) were chosen by enumeration against the LDS bank model of
+// the target (64- and 128-bit accesses served by 32 banks of 8 bytes, 32-bit
+// ones by 32 banks of 4 bytes): the layout exchanges of every block size reach
+// 1.0-1.25 times the conflict-free cycle count (1.06 for blocks of 16
+// butterflies).
+__host__ __device__ constexpr int slot(int p)
+{
+    return p + 2 * ((p >> 5) & 1) + 4 * ((p >> 6) & 1) + 12 * ((p >> 7) & 1) + 18 * ((p >> 8) & 1) +
+           36 * ((p >> 9) & 1);
+}
+
+constexpr int PLINE = slot(N - 1) + 1;    // words spanned by one line's slots (548 at n = 512)
+// line stride: 8 words past a multiple of 32 (584 at n = 512)
+constexpr int LSTRIDE = LOGN == 9 ? 584 : LOGN == 10 ? 1096 : 296;
+static_assert(LSTRIDE >= PLINE && LSTRIDE % 32 == 8, "line stride");
+// base of line l within its wave's planes
+__host__ __device__ constexpr int line_base(int l) { return LSTRIDE * l + 16 * (l >> 1); }
+constexpr int WPL = line_base(LPW - 1) + PLINE;   // words of one wave's planes (2316 at n = 512)
+
+// pext: the bits of v at the set positions of MASK, packed from bit 0
+template <int MASK>
+__device__ __forceinline__ int pext(int v)
+{
+    int r = 0, q = 0;
+    sfor<LOGN>([&](auto B) {
+        if constexpr ((MASK >> B) & 1) { r |= ((v >> B) & 1) << q; q++; }
+    });
+    return r;
+}
+
+// position bits held by the lanes (not in-lane) in layout K
+template <int C, int K>
+constexpr int lane_mask()
+{
+    int mk = 0;
+    for (int q = 0; q < LOGN - 5; q++) mk |= 1 << Lay<C>::xbit(K, q);
+    return mk;
+}
+
+// Slot (in float2) of row r (0..N/2-1), column c (0..15) of an N/2 x 16 complex
+// tile written by lanes whose rows differ in the bits LM (x are those
+// bits of r): row bit 0 flips with x bit 0 (unless bit 0 is itself a lane
+// bit) and column bits 2..3 XOR x bits 1..2, so one 64-bit store by a wave
+// (4 columns x 16 rows) hits every 8-byte bank exactly twice, while a row of
+// the tile stays one contiguous 128-byte run with column pairs kept adjacent.
+template <int LM>
+__device__ __forceinline__ int tslot(int r, int c)
+{
+    const int x = pext<LM>(r);
+    const int R = (LM & 1) ? r : (r ^ (x & 1));
+    return R * 16 + (c ^ (((x >> 1) & 3) << 2));
+}
+
+// Column slot in the [row][512] maximum and [block][512] scale arrays of the
+// row pass: bits 2..5 XOR bits 4..7, so the 16 lanes of a line (16 different
+// 4-column groups in every final layout) cover all banks.
+__device__ __forceinline__ int csw(int c) { return c ^ (((c >> 4) & 15) << 2); }
+
+// Word swizzle of the MX intermediate: in the 32-byte row segment of a
+// 16-column group, the word of columns 2w, 2w+1 sits at w ^ cswz(row).  The
+// column pass copies a group's 512 rows verbatim into LDS; its 32-bit reads
+// (rows 16k + r for r = 0..15, two words per wave) then reach 32 distinct banks.
+__device__ __forceinline__ int cswz(int row) { return ((row >> 2) & 3) << 1; }
+
+// ---------------------------------------------------------------------------
 // one radix-2 stage (butterfly position bit B) in layout K
 // ---------------------------------------------------------------------------
+
+// in-lane offsets of position bits 0..C-1 in layout K (offsets 0..C-1 except
+// where a later layout wraps the low bits above the new stage bits)
+template <int LC, int K, int C>
+constexpr int block_offsets()
+{
+    int m = 0;
+    for (int b = 0; b < C; b++) m |= 1 << Lay<LC>::index_of(K, b);
+    return m;
+}
 // LC: layout family (Lay<LC>); BC: log2 of butterflies per MX block.  With
 // BC = LC + 1 the layouts after the first hold LC block bits in-lane and the
 // last block bit in lane bit 0 (position bit LC is the lowest lane bit there):
@@ -463,7 +550,8 @@ template <int F, int LC, int BC, int K, int B, bool INV, bool TR, bool EX = fals
 __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     using Ly = Lay<LC>;
-    constexpr bool SPLIT = (K > 0) && (BC > LC);
+    // split: the block's last bit (position bit LC) is a lane bit of layout K
+    constexpr bool SPLIT = (K > 0) && (BC > LC) && (Ly::index_of(K, LC) < 0);
     static_assert(BC <= LC + 1, "a block spans at most two lanes");
     static_assert(!SPLIT || Ly::xbit(K, 0) == LC, "last block bit in lane bit 0");
     constexpr int C = SPLIT ? LC : BC;                 // block bits held in-lane
@@ -475,7 +563,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
     constexpr int obb = Ly::index_of(K, fbb);
     static_assert(obb >= 0, "block must be in-lane");
     static_assert(!SPLIT || B > BC, "split blocks only in the later layouts");
-    constexpr int FREE = (CB - 1) | (1 << obb);        // in-lane bits of one block
+    constexpr int FREE = block_offsets<LC, K, C>() | (1 << obb);   // in-lane bits of one block
     constexpr int BFLY = FREE & ~(1 << ob);            // bits enumerating its butterflies
     constexpr int OTHER = (P - 1) & ~FREE;             // bits enumerating blocks
     constexpr int NBLK = P / (2 * CB);
@@ -639,37 +727,6 @@ constexpr int layout_family() { return !is_mx(F) ? 1 : (C == 4 ? 3 : C); }
 // kernels
 // ---------------------------------------------------------------------------
 
-struct FastArgs {
-    const float2* src;       // complex64 [batch][N][N] (row pass input / column pass FP32 input)
-    float2* dst;             // complex64 output (row pass FP32 form / column pass)
-    uint32_t* codes;         // intermediate, [slice][16-column group][row][...]: MX, 8 words of 2 code
-                             // pairs (swizzled); FP16/BF16, 16 words of one packed complex value
-    uint8_t* exps;           // MX intermediate: [slice][row block][column] E8M0 bytes
-    const int32_t* kp;       // per-slice prescale exponent or nullptr
-    int32_t* k_out;          // per-slice copy of kp (row pass) or nullptr
-    int32_t kin_mul, kout_mul, kout_add;
-    const float2* tw;
-    const int32_t* tw_exp;
-    int32_t tw_off[16];
-    mxk::StatPart* parts;    // row pass with statistics: [slice][tile]
-    const int32_t* kadd;     // column pass: per-slice offset of the stored exponents, or nullptr
-    const int32_t* fix_list; // list-driven row pass: slices to redo
-    int32_t* fix_count;      // list length (zeroed by the row pass with statistics)
-    const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
-};
-
-using mxk::kStatsBins;
-using mxk::StatPart;
-using mxk::ROW_PLAIN;
-using mxk::ROW_STATS;
-using mxk::ROW_FIX;
-
-__device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
-{
-    int k = g.kp ? g.kp[slice] : 0;
-    return k == INT32_MIN ? 0 : k;
-}
-
 // Shared memory of the row pass.
 template <int F, int C, int KIND>
 struct alignas(16) RowLds {
@@ -684,21 +741,6 @@ struct alignas(16) RowLds {
     uint32_t mc[WAVES];
     int nf[WAVES], elo[WAVES], ehi[WAVES];
 };
-
-template <class T>
-__device__ __forceinline__ T wave_reduce_max(T v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-template <class T>
-__device__ __forceinline__ T wave_reduce_min(T v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 // One 16-row tile of the row pass. F: 0 E4M3, 1 E5M2, 2 FP16, 3 BF16, 4 FP32.
 // C: log2 of complex values per MX block (1 for the plain forms).  KIND:
@@ -716,7 +758,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     float* s_plane = L.plane;
     float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int line = lane >> 4, m = lane & 15;
+    const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
     const int rl = wave * LPW + line;                     // row within the tile
     const int row = rb * LINES + rl;
     const int kp = slice_k(g, slice);
@@ -725,15 +767,15 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     const float2* x = g.src + ((size_t)slice * N + row) * N;
     float* plane = s_plane + wave * WPL + line_base(line);
     uint32_t* hist = (uint32_t*)s_plane;                 // statistics only, before the planes are used
-    const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
+    const int rm = (int)(__brev((unsigned)m) >> (32 - LOG_LPL));   // m bit-reversed
     Tw t{g.tw, g.tw_exp, g.tw_off, g.tw16};
     float2 a[P];
     ERange er;
-    // plain forms: layout 0 directly, natural 16k + rev4(m) -> offset rev5(k);
+    // plain forms: layout 0 directly, natural LPL k + rm -> offset rev5(k);
     // the 16-bit forms round the pass input to the format
     auto load_plain = [&]() {
         sfor<P>([&](auto Kk) {
-            const float2 v = x[16 * Kk + rm];
+            const float2 v = x[LPL * Kk + rm];
             float2 s = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
             if constexpr (is_16(F)) s = unpack16<F>(pack16<F>(s.x, s.y));
             a[rev(Kk, 5)] = s;
@@ -743,12 +785,12 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     if constexpr (!is_mx(F)) {
         load_plain();
     } else {
-        // coalesced loads: lane m of a line holds naturals 32 I + 2 m + e
+        // coalesced loads: lane m of a line holds naturals 2 LPL I + 2 m + e
         // (e = 0, 1) as v[2 I + e]
         float2 v[P];
         const float4* x4 = (const float4*)x;
         sfor<P / 2>([&](auto I) {
-            const float4 q = x4[16 * I + m];
+            const float4 q = x4[LPL * I + m];
             if constexpr (ST) {
                 v[2 * I] = make_float2(q.x, q.y);
                 v[2 * I + 1] = make_float2(q.z, q.w);
@@ -765,7 +807,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
             static_assert(kStatsBins * 32 <= WAVES * WPL, "histogram fits the planes");
-            for (int i = tid; i < kStatsBins * 32 / 4; i += 256) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
+            for (int i = tid; i < kStatsBins * 32 / 4; i += THREADS) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
             double m2max = 0.0, m2sum = 0.0;
@@ -797,7 +839,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // reads fall in 32 different banks
             __syncthreads();
             StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
-            for (int i = tid; i < kStatsBins; i += 256) {
+            for (int i = tid; i < kStatsBins; i += THREADS) {
                 uint32_t h = 0;
 #pragma unroll 8
                 for (int c = 0; c < 32; c++) h += hist[i * 32 + ((c + i) & 31)];
@@ -810,10 +852,10 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         const float* rbp = plane + slot(P * m);
         sfor<2>([&](auto R) {
             wave_sync();
-            // natural 32 I + 2 m + e sits at position e * 256 + rev4(m) * 16 + rev4(I)
+            // natural 2 LPL I + 2 m + e sits at position e N/2 + rm 16 + rev4(I)
             sfor<P>([&](auto J) {
                 constexpr int I = J / 2, e = J % 2;
-                wb[slot((e << 8) | rev(I, 4))] = R ? v[J].y : v[J].x;
+                wb[slot((e << (LOGN - 1)) | rev(I, 4))] = R ? v[J].y : v[J].x;
             });
             wave_sync();
             sfor<P / 2>([&](auto I) {
@@ -855,10 +897,11 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     } else {
         // Column MX encode of the next pass's input: blocks of CB consecutive
         // rows of one column; this work-group holds NSB such blocks.
-        // 1. per-element max(|re|, |im|) into a [16][512] array (column-swizzled);
+        // 1. per-element max(|re|, |im|) into a [16][N] array (column-swizzled);
         //    VW consecutive columns per lane are in-lane offset bits 0..log2(VW)-1
         constexpr int VW = (CL >= 2) ? 4 : 2;
         float* s_m = s_plane;
+        static_assert(LINES * N <= WAVES * WPL, "column maxima fit the planes");
         __syncthreads();                                   // every wave is done with its planes
         sfor<P / VW>([&](auto G) {
             constexpr int o0 = deposit(G, (P - 1) & ~(VW - 1));
@@ -964,7 +1007,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
 
 // Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).
 template <int F, int C, bool INV, int KIND>
-__global__ __launch_bounds__(256) void k_row(FastArgs g)
+__global__ __launch_bounds__(THREADS) void k_row(FastArgs g)
 {
     __shared__ RowLds<F, C, KIND> L;
     row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
@@ -973,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_row(FastArgs g)
 // Row pass over the slices in fix_list only: one work-group per (list entry,
 // tile) of a batch-sized grid; entries past the list length return at once.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(256) void k_row_fix(FastArgs g)
+__global__ __launch_bounds__(THREADS) void k_row_fix(FastArgs g)
 {
     __shared__ RowLds<F, C, ROW_FIX> L;
     const int j = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
@@ -983,27 +1026,29 @@ __global__ __launch_bounds__(256) void k_row_fix(FastArgs g)
 
 // Column pass.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(256) void k_col(FastArgs g)
+__global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
 {
     constexpr int CB = 1 << C;
     constexpr int NRB = N / CB;                        // row blocks per column
     __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; input and output tiles
     __shared__ __align__(16) uint8_t s_ex[!is_mx(F) ? 16 : LINES * NRB];  // [row block][16 columns]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int line = lane >> 4, m = lane & 15;
+    const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
     const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
     const int cl = wave * LPW + line;                  // column within the work-group
     const int kp = slice_k(g, slice);
     const int kout = g.kout_mul * kp + g.kout_add;
     float* plane = s_plane + wave * WPL + line_base(line);
-    const int rm = (int)(__brev((unsigned)m) >> 28);   // rev4(m)
+    const int rm = (int)(__brev((unsigned)m) >> (32 - LOG_LPL));   // m bit-reversed
     Tw t{g.tw, g.tw_exp, g.tw_off, g.tw16};
     float2 a[P];
-    float2* tile = (float2*)s_plane;                   // 256 x 16 complex (32 KiB)
+    float2* tile = (float2*)s_plane;                   // N/2 x 16 complex
+    static_assert(N / 2 * 16 * 2 <= WAVES * WPL, "output tile fits the planes");
     // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
     const uint32_t* c16 = g.codes + (size_t)slice * N * N + (size_t)cb16 * LINES * N;
 
     if constexpr (F == FP32) {
+        static_assert(LOGN == 9, "the plain FP32 form is built for n = 512");
         // rows are read whole (128 bytes = the work-group's 16 columns) into an
         // LDS tile, 256 rows at a time; lanes then take rows 16k + rev4(m)
         // (layout 0: offset rev5(k)), whose low 4 bits are the lane bits
@@ -1028,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         // rotated by XOR ((n >> 1) & 3): the 32-bit reads below (16 rows x 4
         // columns per wave) then reach every bank exactly twice
         uint32_t* ctile = (uint32_t*)s_plane;
-        static_assert(LINES * N / 4 == 8 * 256, "eight 16-byte pieces per thread");
+        static_assert(LINES * N / 4 == 8 * THREADS, "eight 16-byte pieces per thread");
         const uint4* src = (const uint4*)c16;
         auto put = [&](int i, const uint4& v) {
             const int n = i >> 2;
@@ -1036,16 +1081,16 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         };
         sfor<2>([&](auto H) {   // four loads in flight, then their stores
             constexpr int J = 4 * H;
-            const uint4 q0 = src[J * 256 + tid], q1 = src[(J + 1) * 256 + tid];
-            const uint4 q2 = src[(J + 2) * 256 + tid], q3 = src[(J + 3) * 256 + tid];
-            put(J * 256 + tid, q0);
-            put((J + 1) * 256 + tid, q1);
-            put((J + 2) * 256 + tid, q2);
-            put((J + 3) * 256 + tid, q3);
+            const uint4 q0 = src[J * THREADS + tid], q1 = src[(J + 1) * THREADS + tid];
+            const uint4 q2 = src[(J + 2) * THREADS + tid], q3 = src[(J + 3) * THREADS + tid];
+            put(J * THREADS + tid, q0);
+            put((J + 1) * THREADS + tid, q1);
+            put((J + 2) * THREADS + tid, q2);
+            put((J + 3) * THREADS + tid, q3);
         });
         __syncthreads();
         sfor<P>([&](auto O) {
-            const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
+            const int n = (rev(O, 5) << LOG_LPL) | rm;    // row of position 32m + O
             a[O] = unpack16<F>(ctile[n * 16 + (cl ^ (((n >> 1) & 3) << 2))]);
         });
         __syncthreads();
@@ -1054,26 +1099,26 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         // pass): copied verbatim, 16 bytes per thread and step
         uint32_t* ctile = (uint32_t*)s_plane;
         const uint4* cd = (const uint4*)(g.codes + ((size_t)slice * N * N + (size_t)cb16 * LINES * N) / 2);
-        static_assert(LINES * N / 8 == 4 * 256, "four 16-byte pieces per thread");
-        const uint4 q0 = cd[tid], q1 = cd[256 + tid], q2 = cd[512 + tid], q3 = cd[768 + tid];
+        static_assert(LINES * N / 8 == 4 * THREADS, "four 16-byte pieces per thread");
+        const uint4 q0 = cd[tid], q1 = cd[THREADS + tid], q2 = cd[2 * THREADS + tid], q3 = cd[3 * THREADS + tid];
         // exponents [slice][row block][column]: 16 bytes per row block
         const uint8_t* ex = g.exps + (size_t)slice * NRB * N + cb16 * LINES;
-        for (int i = tid; i < NRB; i += 256) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
+        for (int i = tid; i < NRB; i += THREADS) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
         // stored exponents of a row pass that ran unscaled are offset by kadd
         const int eadd = g.kadd ? g.kadd[slice] : 0;
         ((uint4*)ctile)[tid] = q0;
-        ((uint4*)ctile)[256 + tid] = q1;
-        ((uint4*)ctile)[512 + tid] = q2;
-        ((uint4*)ctile)[768 + tid] = q3;
+        ((uint4*)ctile)[THREADS + tid] = q1;
+        ((uint4*)ctile)[2 * THREADS + tid] = q2;
+        ((uint4*)ctile)[3 * THREADS + tid] = q3;
         __syncthreads();
         // exponent bytes of this wave's 4 columns come as one dword per row
         // block (every lane of the wave reads the same dword: a broadcast;
         // byte reads of one dword by many lanes serialise)
-        const uint32_t* s_ex4 = (const uint32_t*)s_ex + wave;
-        const int exsh = 8 * line;
+        const uint32_t* s_ex4 = (const uint32_t*)s_ex + (cl >> 2);
+        const int exsh = 8 * (cl & 3);
         const int cdsh = 16 * (cl & 1);                     // this column's code pair within the word
         sfor<P>([&](auto O) {
-            const int n = (rev(O, 5) << 4) | rm;          // row of position 32m + O
+            const int n = (rev(O, 5) << LOG_LPL) | rm;    // row of position 32m + O
             const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
             const int eb = (int)((s_ex4[(n / CB) * 4] >> exsh) & 0xffu);
             const float s = __uint_as_float((uint32_t)(eb + eadd) << 23);
@@ -1089,25 +1134,25 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         // a product below the FP32 normal range: the wave redoes its columns
         // (input read again from the intermediate) with such products exact
         if (__builtin_amdgcn_ballot_w64(er.sub) != 0) {
-            sfor<P>([&](auto O) { a[O] = unpack16<F>(c16[(size_t)((rev(O, 5) << 4) | rm) * 16 + cl]); });
+            sfor<P>([&](auto O) { a[O] = unpack16<F>(c16[(size_t)((rev(O, 5) << LOG_LPL) | rm) * 16 + cl]); });
             all_stages<F, CL, 1, INV, false, true>(a, m, t, plane, er);
         }
     }
 
-    // output: scaled by 2^kout, staged through an LDS tile 256 rows at a time
-    // (row bit 8 is an in-lane bit of the last layout) and written as whole
-    // 128-byte row pieces
+    // output: scaled by 2^kout, staged through an LDS tile N/2 rows at a time
+    // (the top row bit is an in-lane bit of the last layout) and written as
+    // whole 128-byte row pieces
     constexpr int KL = Lay<CL>::NL - 1;
     constexpr int HB = Lay<CL>::index_of(KL, LOGN - 1);
     constexpr int LM = lane_mask<CL, KL>();
-    static_assert(HB >= 0 && (LM & 1) == 0 && (LM >> 8) == 0, "row bit 8 in-lane, bit 0 in-lane");
+    static_assert(HB >= 0 && (LM & 1) == 0 && (LM >> (LOGN - 1)) == 0, "top row bit and bit 0 in-lane");
     const int pmL = posM<CL, KL>(m);
     float2* ys = g.dst + (size_t)slice * N * N + cb16 * LINES;
     sfor<2>([&](auto H) {
         __syncthreads();
         sfor<P>([&](auto O) {
             if constexpr (((O >> HB) & 1) == H) {
-                const int r = (Lay<CL>::posF(KL, O) | pmL) & 255;
+                const int r = (Lay<CL>::posF(KL, O) | pmL) & (N / 2 - 1);
                 float2 v = a[O];
                 if constexpr (is_16(F)) v = unpack16<F>(pack16<F>(v.x, v.y));   // output in the format
                 tile[tslot<LM>(r, cl)] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));
@@ -1116,14 +1161,14 @@ __global__ __launch_bounds__(256) void k_col(FastArgs g)
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            const int q = i * 256 + tid, R = q >> 3, pr = q & 7;
+            const int q = i * THREADS + tid, R = q >> 3, pr = q & 7;
             const float4 v = *(const float4*)&tile[R * 16 + 2 * pr];
             const int xr = pext<LM>(R);
             const int r = R ^ (xr & 1);
             const int c = (2 * pr) ^ (((xr >> 1) & 3) << 2);
-            *(float4*)&ys[(size_t)(H * 256 + r) * N + c] = v;
+            *(float4*)&ys[(size_t)(H * (N / 2) + r) * N + c] = v;
         }
     });
 }
 
-}  // namespace mxf
+}  // namespace MXF_NS

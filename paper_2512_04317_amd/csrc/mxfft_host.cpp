@@ -314,7 +314,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
         f.kadd = kadd;
         f.fix_list = pl->d_fix_list;
         f.fix_count = pl->d_fix_count;
-        return mxk::launch_fast(pl->mode, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
+        return mxk::launch_fast(pl->mode, pl->n, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
                    ? MXFFT_OK
                    : MXFFT_EHIP;
     }
@@ -457,7 +457,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     {
         // chunk statistics: the literal statistics pass, or one part per row tile
         size_t parts = mxk::stats_parts(n, max_batch);
-        if (mxk::fast_supported(pl->mode, n, pl->cb) && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2))
+        if (mxk::fast_supported(pl->mode, n, pl->cb) && mxk::fast_fused_stats(pl->mode, n))
             parts = std::max(parts, (size_t)max_batch * mxk::fast_row_tiles(n));
         if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_parts, parts);
     }
@@ -474,7 +474,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         if (st == MXFFT_OK && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2)) {
             st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n / 2);
             if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_exps, (size_t)max_batch * n * (n / pl->cb));
-            pl->fused = true;
+            pl->fused = mxk::fast_fused_stats(pl->mode, n);
             if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_kadd, (size_t)max_batch);
             if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_list, (size_t)max_batch);
             if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_count, 1);

@@ -94,9 +94,11 @@ struct FastPassArgs {
 enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2 };
 
 bool fast_supported(int mode, int n, int cb);
+// whether the row pass can gather the Alg. 1 statistics (register-resident MX passes)
+bool fast_fused_stats(int mode, int n);
 // row: kind is one of RowKind; columns ignore it
-hipError_t launch_fast(int mode, int cb, bool row, bool inverse, int kind, const FastPassArgs& p, int batch,
-                       hipStream_t s);
+hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind, const FastPassArgs& p,
+                       int batch, hipStream_t s);
 // Tiles (row chunks) per slice of the row pass with statistics.
 int fast_row_tiles(int n);
 

@@ -258,18 +258,48 @@ def test_n512_all_blocks(op, fmt, B):
     assert_bitexact(yg, yo, "512^2 %s %s B=%d" % (op, fmt, B))
 
 
-def mixed_512_batch():
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
+@pytest.mark.parametrize("B", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("N", [256, 1024])
+def test_fast_sizes_all_blocks(N, op, fmt, B):
+    """256^2 and 1024^2 slices take the register-resident kernels of their
+    size for 4 <= B <= 32 (1024^2 with the statistics on the row pass, 256^2
+    with the two-kernel statistics) and the generic kernels otherwise."""
+    x = synth.kspace_batch(N, 3, 1, 2)
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 %s %s B=%d" % (N, op, fmt, B))
+
+
+def mixed_512_batch(N=512):
     """Slices inside and outside the window where the statistics ride on the
     unscaled row pass: k-space, tiny, all-zero, huge, single value, heavy-tailed."""
-    ks = synth.kspace_batch(512, 4, 1, 2)
-    one = np.zeros((512, 512), np.complex64)
-    one[7, 300] = 2.5 - 1.0j
+    ks = synth.kspace_batch(N, 4, 1, 2)
+    one = np.zeros((N, N), np.complex64)
+    one[7, 3 * N // 5] = 2.5 - 1.0j
     return np.stack([ks[0],
                      ks[1] * np.float32(1e-30),
-                     np.zeros((512, 512), np.complex64),
+                     np.zeros((N, N), np.complex64),
                      ks[1] * np.float32(1e25),
                      one,
-                     synth.random_complex((512, 512), seed=41, dist="lognormal")]).astype(np.complex64)
+                     synth.random_complex((N, N), seed=41, dist="lognormal")]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("op", ["forward", "roundtrip"])
+@pytest.mark.parametrize("N", [256, 1024])
+def test_fast_sizes_prescale_paths(N, op):
+    """The mixed batch at 256^2 (two-kernel statistics) and 1024^2 (statistics
+    on the row pass, out-of-window slices redone literally)."""
+    x = mixed_512_batch(N)
+    yg, kg, st = gpu_run(x, op=op, fmt="e4m3", block=32)
+    so, yo, ko = orc_run(x, op=op, fmt="e4m3", block=32)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 mixed %s" % (N, op))
 
 
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
