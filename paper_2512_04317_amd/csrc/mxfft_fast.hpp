@@ -244,6 +244,31 @@ __device__ __forceinline__ int mx_requant_pair(float2& v0, float2& v1, float& am
     return E;
 }
 
+// As mx_requant_pair for blocks of 4 G consecutive values held four per lane
+// (v0..v3) by G consecutive lanes: lines of 4 lanes with blocks of 16.
+template <int F, int G>
+__device__ __forceinline__ int mx_requant_quad(float2& v0, float2& v1, float2& v2, float2& v3, float& am)
+{
+    uint32_t a;
+    asm("v_max3_f32 %0, |%1|, |%2|, |%3|\n\t"
+        "v_max3_f32 %0, %0, |%4|, |%5|\n\t"
+        "v_max3_f32 %0, %0, |%6|, |%7|\n\t"
+        "v_max_f32_e64 %0, %0, |%8|"
+        : "=&v"(a)
+        : "v"(v0.x), "v"(v0.y), "v"(v1.x), "v"(v1.y), "v"(v2.x), "v"(v2.y), "v"(v3.x), "v"(v3.y));
+    a = group_max_bits<G>(a);
+    am = __uint_as_float(a);
+    const int E = mxd::block_exp<F>(a);
+    const float s = e8(E), lim = lim_of<F>(E);
+    const uint32_t c0 = enc4<F>(clamp2(v0, lim), clamp2(v1, lim), s);
+    const uint32_t c1 = enc4<F>(clamp2(v2, lim), clamp2(v3, lim), s);
+    v0 = dec2<F, false>(c0, s);
+    v1 = dec2<F, true>(c0, s);
+    v2 = dec2<F, false>(c1, s);
+    v3 = dec2<F, true>(c1, s);
+    return E;
+}
+
 struct Tw {
     const float2* tw;      // stage s = b+1, index j at [2^b + j]
     const int32_t* ex;     // twiddle block exponents
@@ -402,7 +427,7 @@ constexpr int LPW = 64 / LPL;       // lines per wave (4 at n = 512)
 constexpr int LINES = 16;           // lines per work-group
 constexpr int WAVES = LINES / LPW;  // waves per work-group (4 at n = 512)
 constexpr int THREADS = 64 * WAVES;
-static_assert(LOGN >= 8 && LOGN <= 10, "register-resident passes for n = 256, 512, 1024");
+static_assert(LOGN >= 7 && LOGN <= 10, "register-resident passes for n = 128 .. 1024");
 
 // Layouts for MX blocks of 2^C butterflies (1 <= C <= 4).
 template <int C>
@@ -476,7 +501,7 @@ __host__ __device__ constexpr int slot(int p)
 
 constexpr int PLINE = slot(N - 1) + 1;    // words spanned by one line's slots (548 at n = 512)
 // line stride: 8 words past a multiple of 32 (584 at n = 512)
-constexpr int LSTRIDE = LOGN == 9 ? 584 : LOGN == 10 ? 1096 : 296;
+constexpr int LSTRIDE = LOGN == 9 ? 584 : LOGN == 10 ? 1096 : LOGN == 8 ? 296 : 136;
 static_assert(LSTRIDE >= PLINE && LSTRIDE % 32 == 8, "line stride");
 // base of line l within its wave's planes
 __host__ __device__ constexpr int line_base(int l) { return LSTRIDE * l + 16 * (l >> 1); }
@@ -825,12 +850,22 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
             if (lane == 0) { L.m2[wave] = m2max; L.nf[wave] = nf; }
         }
-        // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive lanes
-        sfor<P / 2>([&](auto I) {
-            float am;
-            const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);
-            if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
-        });
+        // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive
+        // lanes, or (lines of 4 lanes, blocks of 16) in two loads of every lane
+        if constexpr (CB / 2 <= LPL) {
+            sfor<P / 2>([&](auto I) {
+                float am;
+                const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);
+                if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
+            });
+        } else {
+            static_assert(CB == 4 * LPL, "a block spans two loads of every lane of its line");
+            sfor<P / 4>([&](auto H) {
+                float am;
+                const int E = mx_requant_quad<F, LPL>(v[4 * H], v[4 * H + 1], v[4 * H + 2], v[4 * H + 3], am);
+                if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
+            });
+        }
         if constexpr (ST) {
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;

@@ -261,11 +261,12 @@ def test_n512_all_blocks(op, fmt, B):
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
 @pytest.mark.parametrize("fmt", ["e4m3", "e5m2"])
 @pytest.mark.parametrize("B", [2, 4, 8, 16, 32, 64])
-@pytest.mark.parametrize("N", [256, 1024])
+@pytest.mark.parametrize("N", [128, 256, 1024])
 def test_fast_sizes_all_blocks(N, op, fmt, B):
-    """256^2 and 1024^2 slices take the register-resident kernels of their
-    size for 4 <= B <= 32 (1024^2 with the statistics on the row pass, 256^2
-    with the two-kernel statistics) and the generic kernels otherwise."""
+    """128^2, 256^2 and 1024^2 slices take the register-resident kernels of
+    their size for 4 <= B <= 32 (1024^2 with the statistics on the row pass,
+    the others with the two-kernel statistics) and the generic kernels
+    otherwise."""
     x = synth.kspace_batch(N, 3, 1, 2)
     yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
     so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
@@ -290,10 +291,10 @@ def mixed_512_batch(N=512):
 
 
 @pytest.mark.parametrize("op", ["forward", "roundtrip"])
-@pytest.mark.parametrize("N", [256, 1024])
+@pytest.mark.parametrize("N", [128, 256, 1024])
 def test_fast_sizes_prescale_paths(N, op):
-    """The mixed batch at 256^2 (two-kernel statistics) and 1024^2 (statistics
-    on the row pass, out-of-window slices redone literally)."""
+    """The mixed batch at 128^2, 256^2 (two-kernel statistics) and 1024^2
+    (statistics on the row pass, out-of-window slices redone literally)."""
     x = mixed_512_batch(N)
     yg, kg, st = gpu_run(x, op=op, fmt="e4m3", block=32)
     so, yo, ko = orc_run(x, op=op, fmt="e4m3", block=32)
