@@ -1,0 +1,37 @@
+// fast_16_1024.hip -- instantiations of the register-resident 1024^2 passes for the FP16 and BF16 forms.
+#define MXF_LOGN 10
+#define MXF_NS mxf1024
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+namespace {
+
+template <int F>
+hipError_t launch16(bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s)
+{
+    if (row && kind != ROW_PLAIN) return hipErrorInvalidValue;   // statistics ride on the MX row pass only
+    const dim3 grid((mxf1024::N / mxf1024::LINES) * batch), block(mxf1024::THREADS);
+    if (row) {
+        if (inverse) hipLaunchKernelGGL((mxf1024::k_row<F, 1, true, ROW_PLAIN>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((mxf1024::k_row<F, 1, false, ROW_PLAIN>), grid, block, 0, s, g);
+    } else {
+        if (inverse) hipLaunchKernelGGL((mxf1024::k_col<F, 1, true>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((mxf1024::k_col<F, 1, false>), grid, block, 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fast_fp16_1024(int, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s)
+{
+    return launch16<mxf::FP16>(row, inverse, kind, g, batch, s);
+}
+
+hipError_t launch_fast_bf16_1024(int, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s)
+{
+    return launch16<mxf::BF16>(row, inverse, kind, g, batch, s);
+}
+
+}  // namespace mxk

@@ -121,7 +121,7 @@ def test_batch_create_rejects_bad_groups(groups):
 def test_plan_bytes_host():
     """The device-memory estimate runs on the host (no HIP call) and follows
     the workspace of each path: the MX intermediate (2 + 2/B bytes per value)
-    at n = 128 .. 1024 and the 16-bit one (4 bytes per value) at n = 512,
+    and the 16-bit one (4 bytes per value) at n = 128 .. 1024,
     none for the generic line kernels; invalid arguments fail like mxfft_plan."""
     per = lambda n, **kw: (mxfft.plan_bytes(n, 8, **kw) - mxfft.plan_bytes(n, 4, **kw)) // 4   # noqa: E731
     mx = per(512, fmt="e4m3", block=32)
@@ -133,7 +133,9 @@ def test_plan_bytes_host():
     m1k = per(1024, fmt="e5m2", block=16)
     assert 1024 * 1024 * (2 + 2 / 16) <= m1k < 1024 * 1024 * (2 + 2 / 16) + 64 * 1024
     assert per(64, fmt="e4m3", block=32) < 64 * 1024        # generic line kernels: no intermediate
-    assert per(1024, fmt="fp16") < 64 * 1024
+    h1k = per(1024, fmt="bf16")
+    assert 1024 * 1024 * 4 <= h1k < 1024 * 1024 * 4 + 64 * 1024
+    assert per(64, fmt="fp16") < 64 * 1024
     assert per(512, fmt="fp32") < 64 * 1024
     for bad in (dict(n=63), dict(n=64, max_batch=0), dict(n=64, block=48)):
         n, mb = bad.pop("n"), bad.pop("max_batch", 1)

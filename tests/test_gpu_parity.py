@@ -352,7 +352,7 @@ def test_n512_prescale_limits_and_errors():
 
 
 @pytest.mark.parametrize("fmt", ["fp16", "bf16"])
-@pytest.mark.parametrize("N", [2, 8, 32, 64, 128, 256, 512])
+@pytest.mark.parametrize("N", [2, 8, 32, 64, 128, 256, 512, 1024])
 def test_16bit_forms(fmt, N):
     """The 16-bit forms (Sec. 2.3): rounding of every pass input, v operand,
     product and sum to the format, bit for bit against the oracle; forward
@@ -370,12 +370,12 @@ def test_16bit_forms(fmt, N):
         assert_bitexact(yg, yo, "%s N=%d %s" % (fmt, N, op))
 
 
-@pytest.mark.parametrize("N", [32, 512])
+@pytest.mark.parametrize("N", [32, 128, 512, 1024])
 @pytest.mark.parametrize("fmt", ["fp16", "bf16"])
 def test_16bit_range_edges(fmt, N):
     """Values that overflow the half range and bfloat16 products below the
     FP32 normal range (no prescale, so the data reaches the kernels as is).
-    At N = 512 the bfloat16 waves that meet such products redo their lines
+    At N >= 128 the bfloat16 waves that meet such products redo their lines
     with exact products; the big slices of the same batch do not."""
     rng = np.random.default_rng(3)
     big = (rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))) * 3e4
