@@ -81,6 +81,10 @@ def lib():
         L.orc_fft1_f64.argtypes = [i, lg, i, P]
         L.orc_fmt_info.restype = i
         L.orc_fmt_info.argtypes = [i, P, P, P, P, P]
+        L.orc_rss.restype = i
+        L.orc_rss.argtypes = [P, lg, i, lg, P]
+        L.orc_ssim.restype = i
+        L.orc_ssim.argtypes = [P, P, i, d, P]
         _lib = L
     return _lib
 
@@ -211,3 +215,26 @@ def fft1_f64(x, inverse=False):
     N = a.shape[-1]
     assert lib().orc_fft1_f64(N, a.size // N, int(inverse), _ptr(a)) == OK
     return a
+
+
+def rss(T, coils):
+    """Eq. 1 root-sum-of-squares over coils: T complex64 [recon * coils, n, n]
+    (coil-minor) -> float32 [recon, n, n] (FP32, coils summed in order)."""
+    a = np.ascontiguousarray(T, dtype=np.complex64)
+    n = a.shape[-1]
+    recon = a.size // (coils * n * n)
+    out = np.empty((recon, n, n), np.float32)
+    assert lib().orc_rss(_ptr(a), recon, int(coils), n * n, _ptr(out)) == OK
+    return out
+
+
+def ssim(x, y, L=None):
+    """Mean SSIM of image x against reference y (Wang et al. 2004 form;
+    L defaults to the reference's maximum)."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    b = np.ascontiguousarray(y, dtype=np.float32)
+    L = float(b.max()) if L is None else float(L)
+    out = ctypes.c_double()
+    st = lib().orc_ssim(_ptr(a), _ptr(b), a.shape[-1], L, ctypes.byref(out))
+    assert st == OK, st
+    return out.value

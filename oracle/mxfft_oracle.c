@@ -768,3 +768,76 @@ void orc_mx_butterfly(int f, int cb, const float* u, const float* v, const doubl
                        ev_kr_eo, ev_kr_eo ? ev_kr_eo + 1 : NULL, ev_kr_eo ? ev_kr_eo + 2 : NULL);
     free(scratch);
 }
+
+/* ------------------------------------------------------------------------- */
+/* 10. Root-sum-of-squares coil combine (Eq. 1)                               */
+/* ------------------------------------------------------------------------- */
+
+/* x_RSS = (sum_c |T_c|^2)^(1/2) for every pixel of `recon` images of `coils`
+ * coil slices each (T: [recon][coils][nn] interleaved complex, out:
+ * [recon][nn]).  FP32 throughout: |T|^2 = re*re + im*im with each product and
+ * the sum rounded to FP32 (no fused multiply-add), the coils added in order
+ * c = 0 .. C-1 to a running FP32 sum, then the correctly rounded square root. */
+int orc_rss(const float* T, long recon, int coils, long nn, float* out)
+{
+    if (coils < 1 || recon < 0 || nn < 0) return ORC_EINVAL;
+    for (long r = 0; r < recon; r++)
+        for (long i = 0; i < nn; i++) {
+            float acc = 0.0f;
+            for (int c = 0; c < coils; c++) {
+                const float* t = T + 2 * ((r * coils + c) * nn + i);
+                const float re2 = t[0] * t[0];
+                const float im2 = t[1] * t[1];
+                const float m = re2 + im2;
+                acc = acc + m;
+            }
+            out[r * nn + i] = sqrtf(acc);
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* 11. Structural similarity (SSIM) of two images                             */
+/* ------------------------------------------------------------------------- */
+
+/* Mean SSIM of image x against reference y (both N x N, FP32 values) in the
+ * form of Wang, Bovik, Sheikh and Simoncelli (2004): local statistics under
+ * an 11 x 11 Gaussian window of standard deviation 1.5 normalised to unit
+ * sum, C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L the dynamic range, the index
+ *   ((2 mx my + C1)(2 sxy + C2)) / ((mx^2 + my^2 + C1)(sx^2 + sy^2 + C2))
+ * at every position where the window lies inside the image, averaged.  All
+ * arithmetic in FP64. */
+int orc_ssim(const float* x, const float* y, int N, double L, double* ssim)
+{
+    enum { W = 11, R = 5 };
+    if (N < W || !(L > 0.0)) return ORC_EINVAL;
+    double w[W][W], sum = 0.0;
+    for (int i = 0; i < W; i++)
+        for (int j = 0; j < W; j++) {
+            const double d2 = (double)((i - R) * (i - R) + (j - R) * (j - R));
+            w[i][j] = exp(-d2 / (2.0 * 1.5 * 1.5));
+            sum += w[i][j];
+        }
+    for (int i = 0; i < W; i++)
+        for (int j = 0; j < W; j++) w[i][j] /= sum;
+    const double C1 = (0.01 * L) * (0.01 * L), C2 = (0.03 * L) * (0.03 * L);
+    double total = 0.0;
+    for (int r = R; r < N - R; r++)
+        for (int c = R; c < N - R; c++) {
+            double mx = 0, my = 0, xx = 0, yy = 0, xy = 0;
+            for (int i = 0; i < W; i++)
+                for (int j = 0; j < W; j++) {
+                    const double a = x[(long)(r + i - R) * N + (c + j - R)];
+                    const double b = y[(long)(r + i - R) * N + (c + j - R)];
+                    mx += w[i][j] * a;
+                    my += w[i][j] * b;
+                    xx += w[i][j] * a * a;
+                    yy += w[i][j] * b * b;
+                    xy += w[i][j] * a * b;
+                }
+            const double sx = xx - mx * mx, sy = yy - my * my, sxy = xy - mx * my;
+            total += ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sx + sy + C2));
+        }
+    *ssim = total / ((double)(N - 2 * R) * (N - 2 * R));
+    return ORC_OK;
+}

@@ -41,4 +41,9 @@ int orc_column_encode(int fmt, int B, int N, const float* a, double* mant, int32
 int orc_fft2_f64(int N, long batch, int inverse, double* a);
 int orc_fft1_f64(int N, long lines, int inverse, double* a);
 
+/* Eq. 1 root-sum-of-squares coil combine (FP32, coils in order) and the mean
+ * SSIM (Wang et al. 2004, 11 x 11 Gaussian window, sigma 1.5, FP64). */
+int orc_rss(const float* T, long recon, int coils, long nn, float* out);
+int orc_ssim(const float* x, const float* y, int N, double L, double* ssim);
+
 #endif
