@@ -125,6 +125,25 @@ mxfft_status mxfft_inverse(mxfft_plan_t plan, const void* in, void* out, int32_t
 mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
                              int32_t* k_out, void* stream);
 
+/* Eq. 1 with its root-sum-of-squares coil combine.  `in` holds `recon`
+ * reconstructions of `coils` coil slices each, coil-minor: complex64
+ * [recon][coils][n][n].  op 0: T_c = the forward transform of each coil (as
+ * mxfft_forward, KEEP_SCALE honoured); op 2: T_c = the round trip (as
+ * mxfft_roundtrip).  Output: rss[r][i] = (sum_c |T_{r,c}[i]|^2)^(1/2), FP32
+ * [recon][n][n], with |T|^2 = re re + im im (each product and the sum rounded
+ * to FP32, no fused multiply-add), the coils summed in order and a correctly
+ * rounded square root.  The combine is fused into the last column pass:
+ * the per-coil complex results are never written, only the images (1/(2 C)
+ * of the plain call's output bytes).  work: complex64 [recon * coils][n][n]
+ * scratch for the round trip's forward result and for the FP32 form's
+ * intermediate (may be `in`, which is then overwritten); MXFFT_EINVAL when
+ * it is needed and NULL; unused (may be NULL) otherwise.  k_out: int32[recon * coils] or
+ * NULL.  recon * coils <= max_batch.  Only plans on the register-resident
+ * passes (n = 128..1024 with MX B = 4..32 or FP16/BF16, and FP32 at n = 512)
+ * have the fused epilogue: others return MXFFT_EUNSUPPORTED. */
+mxfft_status mxfft_rss(mxfft_plan_t plan, int32_t op, const void* in, void* work, float* rss, int32_t recon,
+                       int32_t coils, int32_t* k_out, void* stream);
+
 /* Synchronise `stream` and return the device status of the plan's last call
  * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */
 mxfft_status mxfft_plan_last_status(mxfft_plan_t plan, void* stream);

@@ -15,6 +15,9 @@ hipError_t launch16(bool row, bool inverse, int kind, const mxf::FastArgs& g, in
     if (row) {
         if (inverse) hipLaunchKernelGGL((mxf128::k_row<F, 1, true, ROW_PLAIN>), grid, block, 0, s, g);
         else hipLaunchKernelGGL((mxf128::k_row<F, 1, false, ROW_PLAIN>), grid, block, 0, s, g);
+    } else if (kind == COL_RSS) {
+        if (inverse) hipLaunchKernelGGL((mxf128::k_col_rss<F, 1, true>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((mxf128::k_col_rss<F, 1, false>), grid, block, 0, s, g);
     } else {
         if (inverse) hipLaunchKernelGGL((mxf128::k_col<F, 1, true>), grid, block, 0, s, g);
         else hipLaunchKernelGGL((mxf128::k_col<F, 1, false>), grid, block, 0, s, g);

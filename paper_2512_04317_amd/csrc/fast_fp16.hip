@@ -12,6 +12,7 @@ hipError_t launch_fast_fp16(int cb, bool row, bool inverse, int kind, const mxf:
     const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
 #define MXF_CASE(INV)                                                                          \
     if (row) hipLaunchKernelGGL((mxf::k_row<mxf::FP16, 1, INV, ROW_PLAIN>), grid, block, 0, s, g); \
+    else if (kind == COL_RSS) hipLaunchKernelGGL((mxf::k_col_rss<mxf::FP16, 1, INV>), grid, block, 0, s, g); \
     else hipLaunchKernelGGL((mxf::k_col<mxf::FP16, 1, INV>), grid, block, 0, s, g);
     (void)cb;
     if (inverse) { MXF_CASE(true) }

@@ -376,6 +376,8 @@ struct FastArgs {
     const int32_t* fix_list; // list-driven row pass: slices to redo
     int32_t* fix_count;      // list length (zeroed by the row pass with statistics)
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
+    float* rss;              // column pass with the coil combine: [reconstruction][N][N] FP32
+    int32_t coils;           // coil slices per reconstruction (consecutive slices)
 };
 
 using mxk::kStatsBins;
@@ -1059,26 +1061,44 @@ __global__ __launch_bounds__(THREADS) void k_row_fix(FastArgs g)
     row_tile<F, C, INV, ROW_FIX>(g, g.fix_list[j], rb, L);
 }
 
-// Column pass.
+// Shared memory of the column pass: the exchange planes (which also hold the
+// input and output tiles) and the exponent bytes of the MX input.
+template <int F, int C>
+struct alignas(16) ColLds {
+    static constexpr int NRB = N / (1 << C);           // row blocks per column
+    float plane[WAVES * WPL];
+    uint8_t ex[!is_mx(F) ? 16 : LINES * NRB];          // [row block][16 columns]
+};
+
+// Column pass of the 16-column group cb16 of one slice up to its last stage:
+// the input tile, its decode into the first layout, the stages (and, for
+// BF16, the exact redo); a holds the unscaled results in the last layout.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
+__device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16, float2 (&a)[P], ColLds<F, C>& L)
 {
     constexpr int CB = 1 << C;
-    constexpr int NRB = N / CB;                        // row blocks per column
-    __shared__ __align__(16) float s_plane[WAVES * WPL];  // exchange planes; input and output tiles
-    __shared__ __align__(16) uint8_t s_ex[!is_mx(F) ? 16 : LINES * NRB];  // [row block][16 columns]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int NRB = ColLds<F, C>::NRB;
+    float* s_plane = L.plane;
+    uint8_t* s_ex = L.ex;
+    // an opaque copy of the thread index: the lane-dependent addresses are
+    // then recomputed per coil in the combined pass instead of being hoisted
+    // out of its coil loop (which would hold them all in registers)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int wave = tid >> 6, lane = tid & 63;
     const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
-    const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
     const int cl = wave * LPW + line;                  // column within the work-group
-    const int kp = slice_k(g, slice);
-    const int kout = g.kout_mul * kp + g.kout_add;
     float* plane = s_plane + wave * WPL + line_base(line);
     const int rm = (int)(__brev((unsigned)m) >> (32 - LOG_LPL));   // m bit-reversed
-    Tw t{g.tw, g.tw_exp, g.tw_off, g.tw16};
-    float2 a[P];
+    // opaque copies of the table pointers: in the coil loop of the combined
+    // pass the twiddle loads then stay inside the loop (all of them hoisted
+    // out of it would need more registers than a lane has)
+    const float2* twp = g.tw;
+    const int32_t* txp = g.tw_exp;
+    const uint32_t* t16p = g.tw16;
+    asm volatile("" : "+s"(twp), "+s"(txp), "+s"(t16p));
+    Tw t{twp, txp, g.tw_off, t16p};
     float2* tile = (float2*)s_plane;                   // N/2 x 16 complex
-    static_assert(N / 2 * 16 * 2 <= WAVES * WPL, "output tile fits the planes");
     // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
     const uint32_t* c16 = g.codes + (size_t)slice * N * N + (size_t)cb16 * LINES * N;
 
@@ -1173,10 +1193,27 @@ __global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
             all_stages<F, CL, 1, INV, false, true>(a, m, t, plane, er);
         }
     }
+}
+
+// Column pass.
+template <int F, int C, bool INV>
+__global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
+{
+    __shared__ ColLds<F, C> L;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
+    const int slice = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
+    const int cl = wave * LPW + line;                  // column within the work-group
+    float2 a[P];
+    col_lines<F, C, INV>(g, slice, cb16, a, L);
+    const int kout = g.kout_mul * slice_k(g, slice) + g.kout_add;
+    float2* tile = (float2*)L.plane;                   // N/2 x 16 complex
+    static_assert(N / 2 * 16 * 2 <= WAVES * WPL, "output tile fits the planes");
 
     // output: scaled by 2^kout, staged through an LDS tile N/2 rows at a time
     // (the top row bit is an in-lane bit of the last layout) and written as
     // whole 128-byte row pieces
+    constexpr int CL = layout_family<F, C>();
     constexpr int KL = Lay<CL>::NL - 1;
     constexpr int HB = Lay<CL>::index_of(KL, LOGN - 1);
     constexpr int LM = lane_mask<CL, KL>();
@@ -1204,6 +1241,51 @@ __global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
             *(float4*)&ys[(size_t)(H * (N / 2) + r) * N + c] = v;
         }
     });
+}
+
+
+// |v 2^kout|^2 added to a running FP32 sum: each square and their sum rounded
+// to FP32 (no fused multiply-add); the 16-bit forms round v to the format first.
+template <int F>
+__device__ __forceinline__ float rss_add(float acc, float2 v, int kout)
+{
+#pragma clang fp contract(off)
+    if constexpr (is_16(F)) v = unpack16<F>(pack16<F>(v.x, v.y));
+    const float re = ldexpf(v.x, kout), im = ldexpf(v.y, kout);
+    const float re2 = re * re;
+    const float im2 = im * im;
+    const float m2 = re2 + im2;
+    return acc + m2;
+}
+
+// Column pass with the root-sum-of-squares coil combine (Eq. 1) as its
+// epilogue: one work-group per (reconstruction, 16-column group) runs the
+// column pass of every coil slice of the reconstruction in coil order and
+// keeps the running sum of |T_c|^2 per value; only the FP32 image
+// (sum)^(1/2), [reconstruction][n][n], is written.
+template <int F, int C, bool INV>
+__global__ __launch_bounds__(THREADS) void k_col_rss(FastArgs g)
+{
+    __shared__ ColLds<F, C> L;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
+    const int recon = blockIdx.x / (N / LINES), cb16 = blockIdx.x % (N / LINES);
+    const int cl = wave * LPW + line;
+    float acc[P];
+    sfor<P>([&](auto O) { acc[O] = 0.0f; });
+    for (int c = 0; c < g.coils; c++) {
+        if (c > 0) __syncthreads();                    // the planes are free again
+        const int slice = recon * g.coils + c;
+        float2 a[P];
+        col_lines<F, C, INV>(g, slice, cb16, a, L);
+        const int kout = g.kout_mul * slice_k(g, slice) + g.kout_add;
+        sfor<P>([&](auto O) { acc[O] = rss_add<F>(acc[O], a[O], kout); });
+    }
+    constexpr int CL = layout_family<F, C>();
+    constexpr int KL = Lay<CL>::NL - 1;
+    const int pmL = posM<CL, KL>(m);
+    float* y = g.rss + (size_t)recon * N * N + cb16 * LINES + cl;
+    sfor<P>([&](auto O) { y[(size_t)(Lay<CL>::posF(KL, O) | pmL) * N] = sqrtf(acc[O]); });
 }
 
 }  // namespace MXF_NS

@@ -288,7 +288,8 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
 // of the stored exponents (after a ROW_STATS row pass), else nullptr.
 mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* kp, int32_t* k_out,
                   int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s,
-                  int kind = mxk::ROW_PLAIN, const int32_t* kadd = nullptr)
+                  int kind = mxk::ROW_PLAIN, const int32_t* kadd = nullptr, float* rss = nullptr,
+                  int coils = 0)
 {
     const int role = (kind == mxk::ROW_FIX) ? ROLE_FIX
                      : inverse              ? (axis ? ROLE_INV_COL : ROLE_INV_ROW)
@@ -308,6 +309,8 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
         f.kout_add = kout_add;
         f.tw = pl->d_twf;
         f.tw16 = pl->d_tw16;
+        f.rss = rss;
+        f.coils = coils;
         f.tw_exp = pl->d_tw_exp;
         for (int i = 0; i < 16; i++) f.tw_off[i] = i < mxk::kMaxLog2N + 2 ? pl->tw_exp_off[i] : 0;
         f.parts = pl->d_parts;
@@ -619,6 +622,52 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
     }
     MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
     MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
+    pl->last_batch = batch;
+    pl->last_has_stats = pre;
+    return MXFFT_OK;
+}
+
+mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, float* rss, int32_t recon,
+                       int32_t coils, int32_t* k_out, void* stream)
+{
+    if (!pl || !in || !rss || recon < 0 || coils < 1 || (op != 0 && op != 2)) return MXFFT_EINVAL;
+    if ((long)recon * coils > pl->max_batch) return MXFFT_EINVAL;
+    // the FP32 form keeps its intermediate in complex64 (the row pass writes
+    // it where the column pass reads it): `work` is that buffer
+    const bool plain = pl->mode == mxk::MODE_FP32;
+    if ((op == 2 || plain) && !work) return MXFFT_EINVAL;
+    if (!pl->fast) return MXFFT_EUNSUPPORTED;
+    if (recon == 0) return MXFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int batch = recon * coils;
+    const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
+    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    if (op == 0) {
+        const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
+        if (pre && pl->fused) {
+            MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
+            MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, pl->d_kadd,
+                        rss, coils));
+        } else {
+            if (pre) MX_TRY(stats(pl, in, batch, s));
+            MX_TRY(pass(pl, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+            MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, nullptr, rss,
+                        coils));
+        }
+    } else {
+        // round trip: the forward result (kept scaled) goes to `work`
+        if (pre && pl->fused) {
+            MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
+            MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+        } else {
+            if (pre) MX_TRY(stats(pl, in, batch, s));
+            MX_TRY(pass(pl, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+            MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+        }
+        MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
+        MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, recon, s, mxk::COL_RSS, nullptr, rss,
+                    coils));
+    }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     return MXFFT_OK;

@@ -88,10 +88,12 @@ struct FastPassArgs {
     const int32_t* fix_list; // list-driven row pass: slices to redo
     int32_t* fix_count;      // number of list entries (zeroed by the row pass with statistics)
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves at [h + j]
+    float* rss;              // COL_RSS: [reconstruction][n][n] root-sum-of-squares image
+    int32_t coils;           // COL_RSS: coil slices per reconstruction
 };
 
 // Row pass kinds of the register-resident passes.
-enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2 };
+enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2, COL_RSS = 3 };
 
 bool fast_supported(int mode, int n, int cb);
 // whether the row pass can gather the Alg. 1 statistics (register-resident MX passes)

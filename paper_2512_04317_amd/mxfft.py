@@ -26,7 +26,7 @@ EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_fo
            "mxfft_plan_set_tuning", "mxfft_plan_get_tuning", "mxfft_tune", "mxfft_tune_cache_lookup",
            "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
            "mxfft_batch_destroy", "mxfft_plan_bytes", "mxfft_serve_create", "mxfft_serve_submit",
-           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy")
+           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy", "mxfft_rss")
 TUNE_FORCE = 0x1
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 
@@ -130,6 +130,8 @@ def lib():
         L.mxfft_batch_group_tuning.argtypes = [P, i32, TP]
         L.mxfft_batch_destroy.restype = i32
         L.mxfft_batch_destroy.argtypes = [P]
+        L.mxfft_rss.restype = i32
+        L.mxfft_rss.argtypes = [P, i32, P, P, P, i32, i32, P, P]
         L.mxfft_plan_bytes.restype = i32
         L.mxfft_plan_bytes.argtypes = [i32, i32, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint64)]
         L.mxfft_serve_create.restype = i32
@@ -238,6 +240,27 @@ class Plan:
         st = lib().mxfft_roundtrip(self.handle, _ptr(x), _ptr(out), x.shape[0], _ptr(k_out), _stream(stream))
         if st != OK:
             raise MxfftError(st, "mxfft_roundtrip")
+        return out, k_out
+
+    def rss(self, x, coils, op=FORWARD, out=None, work=None, k_out=None, stream=None):
+        """Eq. 1 root-sum-of-squares image of each reconstruction (coil-minor
+        slices of x) after the forward transform or the round trip of every
+        coil, fused into the last column pass; returns (rss, k)."""
+        _check_slices(x, self.n, "x")
+        if x.shape[0] % coils:
+            raise ValueError("the batch must hold whole reconstructions of %d coils" % coils)
+        recon = x.shape[0] // coils
+        if out is None:
+            out = torch.empty((recon, self.n, self.n), dtype=torch.float32, device=x.device)
+        if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.shape == (recon, self.n, self.n)):
+            raise ValueError("out must be a contiguous float32 CUDA tensor [recon, n, n]")
+        if work is None and (op == ROUNDTRIP or self.params.format == FP32):
+            work = torch.empty_like(x)
+        k_out = self._kbuf(x.shape[0], k_out, x.device)
+        st = lib().mxfft_rss(self.handle, int(op), _ptr(x), _ptr(work), _ptr(out), recon, int(coils), _ptr(k_out),
+                             _stream(stream))
+        if st != OK:
+            raise MxfftError(st, "mxfft_rss")
         return out, k_out
 
     def last_status(self, stream=None):

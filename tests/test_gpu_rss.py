@@ -1,0 +1,73 @@
+"""The fused root-sum-of-squares coil combine (Eq. 1) on the GPU, through
+the C ABI: each reconstruction's image equals the oracle's combine of the
+oracle's per-coil transforms bit for bit (FP32 form: to tolerance)."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2512_04317_amd import mxfft, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+MODES = {"fp32": O.MODE_FP32, "fp16": O.MODE_FP16, "bf16": O.MODE_BF16}
+FMTS = {"e4m3": O.E4M3, "e5m2": O.E5M2}
+
+
+def oracle_rss(x, coils, op, fmt, block):
+    mode = MODES.get(fmt, O.MODE_MX)
+    st, y, k = O.transform(x, op=O.FORWARD if op == mxfft.FORWARD else O.ROUNDTRIP, mode=mode,
+                           fmt=FMTS.get(fmt, O.E4M3), B=block, nthreads=NTHREADS)
+    assert st == O.OK
+    return O.rss(y, coils), k
+
+
+@pytest.mark.parametrize("op", [mxfft.FORWARD, mxfft.ROUNDTRIP])
+@pytest.mark.parametrize("N,fmt,block", [(128, "e4m3", 32), (512, "e4m3", 32), (512, "e5m2", 8), (1024, "e4m3", 16),
+                                         (256, "fp16", 0), (512, "bf16", 0), (1024, "fp16", 0)])
+def test_rss_matches_oracle(N, fmt, block, op):
+    coils = 3
+    x = synth.kspace_batch(N, 2, 2, coils)                  # 2 reconstructions x 3 coils
+    print("rss N=%d %s B=%d op=%d" % (N, fmt, block, op), flush=True)
+    kw = dict(fmt=fmt, block=block) if block else dict(fmt=fmt)
+    plan = mxfft.Plan(N, x.shape[0], **kw)
+    xd = torch.from_numpy(x).cuda()
+    rss, k = plan.rss(xd, coils, op=op)
+    assert plan.last_status() == mxfft.OK
+    ro, ko = oracle_rss(x, coils, op, fmt, block or 32)
+    np.testing.assert_array_equal(k.cpu().numpy(), ko)
+    r = rss.cpu().numpy()
+    bad = r.view(np.uint32) != ro.view(np.uint32)
+    assert not bad.any(), "%d of %d differ; first %s: gpu %s oracle %s" % (
+        bad.sum(), bad.size, np.argwhere(bad)[:3].tolist(), r[bad][:3], ro[bad][:3])
+    plan.close()
+
+
+def test_rss_fp32_form_and_arguments():
+    """FP32 form at 512^2 (its FFT may contract multiply-adds: held to the
+    plain form's tolerance); the input stays untouched for the forward;
+    argument errors and sizes without the fused epilogue."""
+    coils = 4
+    x = synth.kspace_batch(512, 2, 1, coils)
+    plan = mxfft.Plan(512, coils, fmt="fp32", flags=mxfft.NO_PRESCALE)
+    xd = torch.from_numpy(x).cuda()
+    rss, _ = plan.rss(xd, coils)
+    ref = np.sqrt((np.abs(np.fft.fft2(x.astype(np.complex128))) ** 2).sum(axis=0))
+    err = np.linalg.norm(rss.cpu().numpy()[0] - ref) / np.linalg.norm(ref)
+    assert err < 2e-6, err
+    assert np.array_equal(xd.cpu().numpy().view(np.uint32), x.view(np.uint32))
+    with pytest.raises(ValueError):
+        plan.rss(xd, 3)                                     # not whole reconstructions
+    # the FP32 form needs the scratch buffer for its intermediate: refused on the host without one
+    out = torch.empty((1, 512, 512), dtype=torch.float32, device="cuda")
+    assert mxfft.lib().mxfft_rss(plan.handle, mxfft.FORWARD, mxfft._ptr(xd), None, mxfft._ptr(out), 1, coils, None,
+                                 mxfft._stream(None)) == mxfft.EINVAL
+    plan.close()
+    small = mxfft.Plan(64, 2)                               # generic kernels: no fused epilogue
+    with pytest.raises(mxfft.MxfftError) as e:
+        small.rss(torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda"), 2)
+    assert e.value.status == mxfft.EUNSUPPORTED
+    small.close()
