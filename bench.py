@@ -8,8 +8,9 @@ the whole resident batch.  Also timed: the plain FP32 form of the same FFT on
 the same batch, the other formats of the precision sweep (the other MX element
 format, FP16, BF16; forward, slices/s and accuracy against FP64 each), and the
 CPU oracle on a bounded sample (host cores), a device copy and rocFFT's FP32
-FFT of the same batch (context), and one graph launch over an uneven work list
-of 128^2..1024^2 slices.
+FFT of the same batch (context), one graph launch over an uneven work list
+of 128^2..1024^2 slices, a served stream of Poisson-arriving requests, and
+Eq. 1's RSS images (SSIM / PSNR / NMSE per format, fused combine timing).
 
 Prints one JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload kspace512_64x16]
@@ -50,6 +51,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the other formats (E5M2/E4M3, FP16, BF16, FP32)")
     ap.add_argument("--no-context", action="store_true", help="skip the device copy and rocFFT context timings")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven work list (sizes 128..1024)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the served request stream")
+    ap.add_argument("--no-rss", action="store_true", help="skip the RSS-image quality and the fused RSS timing")
     ap.add_argument("--cpu-sample", type=int, default=32, help="slices the CPU oracle transforms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of the input (known bytes) to scale HBM counters")
@@ -127,6 +130,115 @@ def uneven_batch(args, torch, mxfft, synth):
            "data": "synthetic: 8 distinct coil slices per size, repeated"}
     b.close()
     return res
+
+
+def serving_workload(count, seed=20251204):
+    """Requests of the serving workload: Poisson arrivals at 2000 per second
+    (seeded exponential gaps), size uniform over 128^2..1024^2, U{1..32}
+    coils, forward or round trip 50/50, format E4M3 / E5M2 / FP16 uniform.
+    Returns [(t_arrival_s, n, coils, op, fmt)]."""
+    rng = np.random.default_rng([seed, 5])
+    t = np.cumsum(rng.exponential(1.0 / 2000.0, size=count))
+    n = rng.choice([128, 256, 512, 1024], size=count)
+    coils = rng.integers(1, 33, size=count)
+    op = rng.choice([0, 2], size=count)
+    fmt = rng.choice(["e4m3", "e5m2", "fp16"], size=count)
+    return [(float(t[i]), int(n[i]), int(coils[i]), int(op[i]), str(fmt[i])) for i in range(count)]
+
+
+def serving(args, torch, mxfft, synth, count=1000, slots=4, budget=64 << 30):
+    """Serve the request stream through mxfft_serve_* and report latency
+    (submission to completion seen by the scheduler) and throughput.  Inputs
+    are pre-staged device pools (8 distinct synthetic coil slices per size,
+    repeated to 32 coils); outputs rotate over 16 device buffers per size.
+    The stream runs twice: the first pass warms the plan pool up."""
+    reqs = serving_workload(count)
+    pools, outs = {}, {}
+    for n in (128, 256, 512, 1024):
+        d = torch.from_numpy(synth.kspace_batch(n, 5, 1, 8)).cuda()
+        pools[n] = d.repeat(4, 1, 1).contiguous()
+        outs[n] = [torch.empty_like(pools[n]) for _ in range(16)]
+    srv = mxfft.Server(budget, slots=slots)
+    passes = []
+    for rep in range(2):
+        tickets = []
+        t0 = time.perf_counter()
+        for i, (ta, n, c, op, fmt) in enumerate(reqs):
+            while time.perf_counter() - t0 < ta:
+                pass
+            kw = dict(fmt=fmt) if fmt == "fp16" else dict(fmt=fmt, block=args.block)
+            tickets.append(srv.submit(pools[n][:c], outs[n][i % 16][:c], op=op, **kw))
+        res = [srv.wait(t) for t in tickets]
+        passes.append(res)
+    st = srv.stats()
+    srv.close()
+    res = passes[-1]
+    assert all(r["status"] == mxfft.OK for r in res)
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
+    span_s = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) / 1e3
+    slices = sum(c for _, _, c, _, _ in reqs)
+    return {"metric": "p50/p99 latency of Poisson-arriving requests (submission to completion)",
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3), "requests": count, "arrival_rate_per_s": 2000,
+            "slices_per_s": round(slices / span_s, 1), "requests_per_s": round(count / span_s, 1),
+            "slots": slots, "budget_GB": budget / 2 ** 30, "admitted": st["admitted"], "rejected": st["rejected"],
+            "peak_plan_MB": round(st["peak_plan_bytes"] / 2 ** 20, 1), "plans_created": st["plans_created"],
+            "data": "pre-staged device pools; host-to-device transfer excluded"}
+
+
+def rss_quality(args, torch, mxfft, x, xd, N, recon=8, coils=16):
+    """Eq. 1 on RSS images, as the paper reports its quality (Sec. 3): the
+    first `recon` reconstructions of the batch (16 coils each), forward and
+    round trip, every format; SSIM (GPU kernel) and PSNR / NMSE against the
+    FP64 reference image (forward: RSS of numpy's complex128 fft2; round trip:
+    RSS of the input itself).  Also the time of the fused forward + RSS over
+    the whole batch against the plain forward."""
+    n_sl = recon * coils
+    xk = x[:n_sl].astype(np.complex128)
+    # forward: the k-space coil slices; round trip: the image-domain coil
+    # images x_c (their inverse transforms), as Eq. 1 takes them
+    xi = np.fft.ifft2(xk).astype(np.complex64)
+    inputs = {mxfft.FORWARD: xd[:n_sl], mxfft.ROUNDTRIP: torch.from_numpy(xi).cuda()}
+    ref_f = np.sqrt((np.abs(np.fft.fft2(xk)) ** 2).reshape(recon, coils, N, N).sum(axis=1))
+    ref_r = np.sqrt((np.abs(xi.astype(np.complex128)) ** 2).reshape(recon, coils, N, N).sum(axis=1))
+    refs = {mxfft.FORWARD: ref_f, mxfft.ROUNDTRIP: ref_r}
+    refs_d = {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in refs.items()}
+    out = {}
+    # the FP16 round trip uses T = 2^-3: its forward result grows by up to N^2
+    # and overflows half precision at T = 2^7
+    kinds = [("e4m3_b%d" % args.block, dict(fmt="e4m3", block=args.block), {}),
+             ("e5m2_b%d" % args.block, dict(fmt="e5m2", block=args.block), {}),
+             ("fp16", dict(fmt="fp16"), {mxfft.ROUNDTRIP: dict(target=2.0 ** -3)}),
+             ("bf16", dict(fmt="bf16"), {}), ("fp32", dict(fmt="fp32", flags=mxfft.NO_PRESCALE), {})]
+    fin = lambda v, nd: round(float(v), nd) if np.isfinite(v) else None   # noqa: E731
+    for name, kw, over in kinds:
+        row = {}
+        for op, opn in ((mxfft.FORWARD, "forward"), (mxfft.ROUNDTRIP, "roundtrip")):
+            pkw = dict(kw, **over.get(op, {}))
+            pl = mxfft.Plan(N, n_sl, **pkw)
+            img, _ = pl.rss(inputs[op], coils, op=op)
+            ss = mxfft.ssim(img, refs_d[op]).cpu().numpy()
+            y = img.cpu().numpy().astype(np.float64)
+            r = refs[op]
+            mse = ((y - r) ** 2).mean(axis=(1, 2))
+            psnr = 20 * np.log10(r.max(axis=(1, 2)) / np.sqrt(mse))
+            nmse = ((y - r) ** 2).sum(axis=(1, 2)) / (r ** 2).sum(axis=(1, 2))
+            row[opn] = {"ssim": fin(ss.mean(), 5), "psnr_db": fin(psnr.mean(), 2), "nmse": fin(nmse.mean(), 6)}
+            if "target" in over.get(op, {}):
+                row[opn]["prescale_target"] = pkw["target"]
+            pl.close()
+        out[name] = row
+    # fused combine over the whole batch (64 reconstructions x 16 coils) against the plain forward
+    plan = mxfft.Plan(N, xd.shape[0], fmt=args.fmt, block=args.block)
+    img = torch.empty((xd.shape[0] // coils, N, N), dtype=torch.float32, device="cuda")
+    k = torch.empty(xd.shape[0], dtype=torch.int32, device="cuda")
+    wall, _ = timed_steps(lambda: plan.rss(xd, coils, out=img, k_out=k), args.steps, args.warmup, torch)
+    plan.close()
+    return {"images": recon, "coils": coils, "reference": "FP64 (numpy complex128 fft2; the input for the round trip)",
+            "metrics": out,
+            "fused_forward_rss": {"ms_per_step": round(1e3 * wall / args.steps, 4),
+                                  "value": round(xd.shape[0] * args.steps / wall, 1), "unit": "coil slices/s",
+                                  "output_bytes_per_slice": N * N * 4 / coils}}
 
 
 def main():
@@ -271,8 +383,14 @@ def main():
                                 "ms_per_step": round(1e3 * wall_r / args.steps, 4),
                                 "what": "torch.fft.fft2 (rocFFT) on the same batch, FP32"}}
 
+    if not args.no_rss:
+        result["rss"] = rss_quality(args, torch, mxfft, x, xd, N)
+
     if not args.no_uneven:
         result["uneven_batch"] = uneven_batch(args, torch, mxfft, synth)
+
+    if not args.no_serving:
+        result["serving"] = serving(args, torch, mxfft, synth)
 
     if not args.no_cpu_baseline:
         import oracle

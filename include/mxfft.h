@@ -144,6 +144,16 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32
 mxfft_status mxfft_rss(mxfft_plan_t plan, int32_t op, const void* in, void* work, float* rss, int32_t recon,
                        int32_t coils, int32_t* k_out, void* stream);
 
+/* Image quality: mean SSIM of each of `count` images x against its reference
+ * ref (device FP32 [count][n][n] each, 11 <= n <= 4096) into ssim (device
+ * double[count]), in the form of Wang, Bovik, Sheikh and Simoncelli (2004),
+ * the metric the paper reports on RSS images (Sec. 3): local statistics under
+ * an 11 x 11 Gaussian window of standard deviation 1.5 normalised to unit
+ * sum, C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = max(ref), the index averaged
+ * over the positions where the window lies inside the image.  FP64; one
+ * work-group per image; no workspace. */
+mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t count, double* ssim, void* stream);
+
 /* Synchronise `stream` and return the device status of the plan's last call
  * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */
 mxfft_status mxfft_plan_last_status(mxfft_plan_t plan, void* stream);

@@ -673,6 +673,14 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     return MXFFT_OK;
 }
 
+mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t count, double* ssim, void* stream)
+{
+    if (!x || !ref || !ssim || n < 11 || n > (1 << mxk::kMaxLog2N) || count < 0 || count > 65535)
+        return MXFFT_EINVAL;
+    if (count == 0) return MXFFT_OK;
+    return mxk::launch_ssim(x, ref, n, count, ssim, (hipStream_t)stream) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
+}
+
 mxfft_status mxfft_plan_last_status(mxfft_plan_t pl, void* stream)
 {
     if (!pl) return MXFFT_EINVAL;

@@ -115,6 +115,9 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
                               int32_t* fix_count, int32_t* k_out, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);
+// Mean SSIM of count images x against references y (n x n FP32 each).
+hipError_t launch_ssim(const float* x, const float* y, int n, int count, double* out, hipStream_t s);
+
 // Synthetic finite data (tuning): count complex values, both parts in [-1, 1).
 hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s);
 

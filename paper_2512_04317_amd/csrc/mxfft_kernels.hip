@@ -470,6 +470,78 @@ hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s)
     return hipGetLastError();
 }
 
+// Mean SSIM of image x against reference y per image (Wang, Bovik, Sheikh
+// and Simoncelli 2004): local means, variances and covariance under an
+// 11 x 11 Gaussian window of standard deviation 1.5 normalised to unit sum,
+// C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = max(y), the index at every
+// position where the window lies inside the image, averaged.  FP64.  One
+// work-group per image; the sums are reduced in a fixed order.
+__global__ __launch_bounds__(1024) void k_ssim(const float* __restrict__ x, const float* __restrict__ y, int n,
+                                               double* __restrict__ out)
+{
+    __shared__ double w[121];
+    __shared__ double red[16];
+    __shared__ float fred[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t nn = (size_t)n * n;
+    const float* X = x + blockIdx.x * nn;
+    const float* Y = y + blockIdx.x * nn;
+    if (tid < 121) {
+        const int i = tid / 11 - 5, j = tid % 11 - 5;
+        w[tid] = exp(-(double)(i * i + j * j) / (2.0 * 1.5 * 1.5));
+    }
+    float m = -INFINITY;
+    for (size_t i = tid; i < nn; i += 1024) m = fmaxf(m, Y[i]);
+    for (int o = 32; o; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0) fred[wv] = m;
+    __syncthreads();
+    if (tid == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < 121; k++) sum += w[k];
+        for (int k = 0; k < 121; k++) w[k] /= sum;
+        float mm = fred[0];
+        for (int k = 1; k < 16; k++) mm = fmaxf(mm, fred[k]);
+        fred[0] = mm;
+    }
+    __syncthreads();
+    const double L = fred[0];
+    const double C1 = (0.01 * L) * (0.01 * L), C2 = (0.03 * L) * (0.03 * L);
+    const int V = n - 10;
+    double acc = 0.0;
+    for (int p = tid; p < V * V; p += 1024) {
+        const int r = p / V, c = p % V;           // window origin (top-left)
+        double mx = 0, my = 0, xx = 0, yy = 0, xy = 0;
+        for (int i = 0; i < 11; i++) {
+            const float* xr = X + (size_t)(r + i) * n + c;
+            const float* yr = Y + (size_t)(r + i) * n + c;
+            for (int j = 0; j < 11; j++) {
+                const double a = xr[j], b = yr[j], wt = w[i * 11 + j];
+                mx += wt * a;
+                my += wt * b;
+                xx += wt * a * a;
+                yy += wt * b * b;
+                xy += wt * a * b;
+            }
+        }
+        const double sx = xx - mx * mx, sy = yy - my * my, sxy = xy - mx * my;
+        acc += ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sx + sy + C2));
+    }
+    for (int o = 32; o; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int k = 0; k < 16; k++) t += red[k];
+        out[blockIdx.x] = t / ((double)V * V);
+    }
+}
+
+hipError_t launch_ssim(const float* x, const float* y, int n, int count, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ssim, dim3(count), dim3(1024), 0, s, x, y, n, out);
+    return hipGetLastError();
+}
+
 int line_lines_per_group(int n)
 {
     int r = 8192 / n;

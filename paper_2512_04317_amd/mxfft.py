@@ -26,7 +26,8 @@ EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_fo
            "mxfft_plan_set_tuning", "mxfft_plan_get_tuning", "mxfft_tune", "mxfft_tune_cache_lookup",
            "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
            "mxfft_batch_destroy", "mxfft_plan_bytes", "mxfft_serve_create", "mxfft_serve_submit",
-           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy", "mxfft_rss")
+           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy", "mxfft_rss",
+           "mxfft_ssim")
 TUNE_FORCE = 0x1
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 
@@ -130,6 +131,8 @@ def lib():
         L.mxfft_batch_group_tuning.argtypes = [P, i32, TP]
         L.mxfft_batch_destroy.restype = i32
         L.mxfft_batch_destroy.argtypes = [P]
+        L.mxfft_ssim.restype = i32
+        L.mxfft_ssim.argtypes = [P, P, i32, i32, P, P]
         L.mxfft_rss.restype = i32
         L.mxfft_rss.argtypes = [P, i32, P, P, P, i32, i32, P, P]
         L.mxfft_plan_bytes.restype = i32
@@ -484,3 +487,18 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def ssim(x, ref, stream=None):
+    """Mean SSIM of each image of x against ref (float32 CUDA [count, n, n]);
+    returns a float64 CUDA tensor [count] (mxfft_ssim)."""
+    for t, what in ((x, "x"), (ref, "ref")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 3):
+            raise ValueError("%s must be a contiguous float32 CUDA tensor [count, n, n]" % what)
+    if x.shape != ref.shape:
+        raise ValueError("x and ref must have the same shape")
+    out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    st = lib().mxfft_ssim(_ptr(x), _ptr(ref), int(x.shape[-1]), int(x.shape[0]), _ptr(out), _stream(stream))
+    if st != OK:
+        raise MxfftError(st, "mxfft_ssim")
+    return out

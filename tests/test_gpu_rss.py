@@ -71,3 +71,23 @@ def test_rss_fp32_form_and_arguments():
         small.rss(torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda"), 2)
     assert e.value.status == mxfft.EUNSUPPORTED
     small.close()
+
+
+def test_ssim_kernel_against_oracle():
+    """Mean SSIM of RSS images: against the oracle's FP64 evaluation of the
+    same definition (different summation order: 1e-9), exactly 1 for an image
+    against itself."""
+    coils = 4
+    x = synth.kspace_batch(256, 2, 2, coils)
+    plan = mxfft.Plan(256, x.shape[0], fmt="e5m2", block=8)
+    rss, _ = plan.rss(torch.from_numpy(x).cuda(), coils)
+    ref = np.sqrt((np.abs(np.fft.fft2(x.astype(np.complex128))) ** 2).reshape(2, coils, 256, 256).sum(axis=1))
+    ref = ref.astype(np.float32)
+    s = mxfft.ssim(rss, torch.from_numpy(ref).cuda()).cpu().numpy()
+    r = rss.cpu().numpy()
+    for i in range(2):
+        assert s[i] == pytest.approx(O.ssim(r[i], ref[i]), abs=1e-9)
+        assert 0.2 < s[i] < 1.0
+    same = mxfft.ssim(rss, rss).cpu().numpy()
+    assert np.all(same == 1.0)
+    plan.close()
