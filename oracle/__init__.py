@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mxfft_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libmxfft_oracle.so")
 
-E4M3, E5M2, FP16, BF16, E6M23 = 0, 1, 2, 3, 4
+E4M3, E5M2, FP16, BF16, E6M23, E2M3, E3M2 = 0, 1, 2, 3, 4, 5, 6
 MODE_MX, MODE_FP32, MODE_FP16, MODE_BF16 = 0, 1, 2, 3
 OK, EINVAL, ENONFINITE, ERANGE = 0, -1, -4, -5
 NO_PRESCALE, KEEP_SCALE, NORMALIZE = 1, 2, 4
@@ -27,7 +27,7 @@ FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 INT32_MIN = -(2 ** 31)
 INT32_MAX = 2 ** 31 - 1
 
-FMT_NAMES = {"e4m3": E4M3, "e5m2": E5M2, "fp16": FP16, "bf16": BF16, "e6m23": E6M23}
+FMT_NAMES = {"e4m3": E4M3, "e5m2": E5M2, "fp16": FP16, "bf16": BF16, "e6m23": E6M23, "e2m3": E2M3, "e3m2": E3M2}
 
 
 def build(force=True):

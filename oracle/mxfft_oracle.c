@@ -52,17 +52,21 @@ typedef struct {
     int emax;        /* exponent of the largest normal (OCP "emax_elem")       */
     double maxval;   /* largest finite magnitude                               */
     int saturate;    /* 1: overflow clamps to maxval; 0: overflow gives Inf    */
-    int nan_all_ones;/* 1: only S.1111.111 is NaN and there is no Inf (E4M3)   */
+    int nan_all_ones;/* 1: only S.1111.111 is NaN and there is no Inf (E4M3);
+                        2: every code is a finite number (OCP FP6)            */
 } fmtdesc;
 
-/* OCP 8-bit formats (E4M3 "fn" and E5M2), IEEE half, bfloat16, and a wide
- * 6-bit-exponent / 23-bit-mantissa element used only to pin the data flow. */
+/* OCP 8-bit formats (E4M3 "fn" and E5M2), IEEE half, bfloat16, a wide
+ * 6-bit-exponent / 23-bit-mantissa element used only to pin the data flow,
+ * and the OCP 6-bit MX elements E2M3 and E3M2 (no infinities, no NaN). */
 static const fmtdesc FMT[ORC_NFMT] = {
     /* E4M3  */ {4, 3, 7, -6, 8, 448.0, 1, 1},
     /* E5M2  */ {5, 2, 15, -14, 15, 57344.0, 1, 0},
     /* FP16  */ {5, 10, 15, -14, 15, 65504.0, 0, 0},
     /* BF16  */ {8, 7, 127, -126, 127, 0x1.fep127, 0, 0},
     /* E6M23 */ {6, 23, 31, -30, 31, 0x1.fffffep31, 1, 0},
+    /* E2M3  */ {2, 3, 1, 0, 2, 7.5, 1, 2},
+    /* E3M2  */ {3, 2, 3, -2, 4, 28.0, 1, 2},
 };
 
 int orc_fmt_info(int f, int* ebits, int* mbits, int* emin, int* emax, double* maxval)
@@ -98,6 +102,7 @@ int orc_encode_code(int f, double q)
     int sign = signbit(q) ? 1 : 0;
     int top = sign << (d->ebits + d->mbits);
     double a = fabs(q);
+    if ((isnan(q) || isinf(q)) && d->nan_all_ones == 2) return ORC_EINVAL;   /* not representable */
     if (isnan(q)) return top | ((1 << (d->ebits + d->mbits)) - 1);
     if (isinf(q)) return top | (((1 << d->ebits) - 1) << d->mbits);
     if (a == 0.0) return top;
@@ -115,9 +120,9 @@ double orc_decode_code(int f, int c)
     int ef = (c >> d->mbits) & ((1 << d->ebits) - 1);
     int mf = c & ((1 << d->mbits) - 1);
     double v;
-    if (d->nan_all_ones) {
+    if (d->nan_all_ones == 1) {
         if (ef == (1 << d->ebits) - 1 && mf == (1 << d->mbits) - 1) return NAN;
-    } else if (ef == (1 << d->ebits) - 1) {
+    } else if (d->nan_all_ones == 0 && ef == (1 << d->ebits) - 1) {
         v = mf ? NAN : INFINITY;
         return sign ? -v : v;
     }
@@ -528,7 +533,7 @@ static int valid_cfg(int mode, int fmt, int B, int N)
 {
     if (N < 2 || (N & (N - 1)) != 0 || N > (1 << 14)) return 0;
     if (mode == ORC_MODE_MX) {
-        if (fmt != ORC_E4M3 && fmt != ORC_E5M2 && fmt != ORC_E6M23) return 0;
+        if (fmt != ORC_E4M3 && fmt != ORC_E5M2 && fmt != ORC_E6M23 && fmt != ORC_E2M3 && fmt != ORC_E3M2) return 0;
         if (B < 2 || (B & (B - 1)) != 0 || B > N) return 0;
         return 1;
     }
