@@ -39,13 +39,18 @@ extern "C" {
  * product are rounded to the format (IEEE round to nearest even, overflow to
  * infinity); u +/- p stays FP32 and the output is rounded to the format.  The
  * block size is ignored for them.  FP32 is the plain single-precision form of
- * the same radix-2 FFT (the comparison baseline, no quantisation). */
+ * the same radix-2 FFT (the comparison baseline, no quantisation).  E2M3 and
+ * E3M2 are the OCP 6-bit elements of MXFP6 (no infinities or NaN), which the
+ * paper evaluates beside MXFP8 (Sec. 3); they run on the generic line
+ * kernels at every size. */
 typedef enum {
     MXFFT_E4M3 = 0,
     MXFFT_E5M2 = 1,
     MXFFT_FP16 = 2,
     MXFFT_BF16 = 3,
-    MXFFT_FP32 = 4
+    MXFFT_FP32 = 4,
+    MXFFT_E2M3 = 5,
+    MXFFT_E3M2 = 6
 } mxfft_format;
 
 typedef enum {

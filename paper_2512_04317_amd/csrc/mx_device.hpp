@@ -15,7 +15,7 @@ namespace mxd {
 // OCP 8-bit elements of MXFP8 (Sec. 2.2; Fig. 1C).
 //   EMAX : exponent of the largest normal (the OCP MX "emax_elem")
 //   MBITS: explicit mantissa bits;  EMIN: exponent of the smallest normal
-//   MAXV : largest finite magnitude (1.75 * 2^EMAX for both formats)
+//   MAXV : largest finite magnitude (1.75 * 2^EMAX for both 8-bit formats)
 template <int F> struct Elem;
 template <> struct Elem<0> {  // E4M3 ("fn": no infinities)
     static constexpr int EMAX = 8, MBITS = 3, EMIN = -6;
@@ -24,6 +24,16 @@ template <> struct Elem<0> {  // E4M3 ("fn": no infinities)
 template <> struct Elem<1> {  // E5M2
     static constexpr int EMAX = 15, MBITS = 2, EMIN = -14;
     static constexpr float MAXV = 57344.0f;
+};
+// OCP 6-bit elements of MXFP6 (no infinities or NaN; MAXV = 1.875 * 2^2 and
+// 1.75 * 2^4)
+template <> struct Elem<5> {  // E2M3
+    static constexpr int EMAX = 2, MBITS = 3, EMIN = 0;
+    static constexpr float MAXV = 7.5f;
+};
+template <> struct Elem<6> {  // E3M2
+    static constexpr int EMAX = 4, MBITS = 2, EMIN = -2;
+    static constexpr float MAXV = 28.0f;
 };
 
 // Round y to the element grid of format F, ties to even, saturating at MAXV,
@@ -59,13 +69,15 @@ __device__ __forceinline__ int block_exp(uint32_t amax_key)
 }
 
 // Alg. 2 renormalisation: the smallest k >= 1 with amax <= MAXV * 2^k when
-// amax > MAXV, else 0.  MAXV = 1.75 * 2^EMAX, so amax = 1.f * 2^e needs
-// k = e - EMAX, plus one when f > 1.75; adding 0x1FFFFF to the bits carries
-// into the exponent field exactly when the fraction field exceeds 0x600000.
+// amax > MAXV, else 0.  MAXV = 1.m * 2^EMAX, so amax = 1.f * 2^e needs
+// k = e - EMAX, plus one when f > m; adding 0x7FFFFF - m to the bits carries
+// into the exponent field exactly when the fraction field exceeds m's (for
+// the 8-bit formats m = 0.75: 0x600000, the addend 0x1FFFFF).
 template <int F>
 __device__ __forceinline__ int renorm_exp(uint32_t amax_key)
 {
-    const int k = int((amax_key + 0x001FFFFFu) >> 23) - 127 - Elem<F>::EMAX;
+    constexpr uint32_t MF = __builtin_bit_cast(uint32_t, Elem<F>::MAXV) & 0x007FFFFFu;
+    const int k = int((amax_key + (0x007FFFFFu - MF)) >> 23) - 127 - Elem<F>::EMAX;
     return max(k, 0);
 }
 

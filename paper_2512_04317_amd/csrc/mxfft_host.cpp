@@ -23,6 +23,8 @@ struct HostElem {
 };
 const HostElem kE4M3 = {3, -6, 8, 448.0};
 const HostElem kE5M2 = {2, -14, 15, 57344.0};
+const HostElem kE2M3 = {3, 0, 2, 7.5};       // OCP FP6 (no infinities or NaN)
+const HostElem kE3M2 = {2, -2, 4, 28.0};
 const HostElem kFP16 = {10, -14, 15, 65504.0};
 const HostElem kBF16 = {7, -126, 127, 3.3895313892515355e38};
 
@@ -181,6 +183,8 @@ mxfft_status check_params(const mxfft_params* p, int n)
     switch (p->format) {
     case MXFFT_E4M3:
     case MXFFT_E5M2:
+    case MXFFT_E2M3:
+    case MXFFT_E3M2:
         if (!is_pow2(p->block) || p->block < 2 || p->block > n) return MXFFT_EINVAL;
         if (p->block > 128) return MXFFT_EUNSUPPORTED;
         break;
@@ -243,7 +247,10 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
     const int n = pl->n;
     tw.assign(n > 1 ? n - 1 : 1, make_float2(0.f, 0.f));
     tw_exp.clear();
-    const HostElem& f = (pl->mode == mxk::MODE_E5M2) ? kE5M2 : kE4M3;
+    const HostElem& f = (pl->mode == mxk::MODE_E5M2)   ? kE5M2
+                        : (pl->mode == mxk::MODE_E2M3) ? kE2M3
+                        : (pl->mode == mxk::MODE_E3M2) ? kE3M2
+                                                       : kE4M3;
     for (int s = 1; s <= pl->logn; s++) {
         const long m = 1L << s, h = m / 2;
         off[s] = (int32_t)tw_exp.size();
@@ -339,7 +346,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     a.lines = pl->lines ? pl->lines : mxk::line_lines_per_group(pl->n);
     a.axis = axis;
     a.inverse = inverse;
-    a.encode = (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2);
+    a.encode = mxk::is_mx_mode(pl->mode);
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -440,10 +447,12 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     pl->p = *p;
     pl->mode = (p->format == MXFFT_E4M3)   ? mxk::MODE_E4M3
                : (p->format == MXFFT_E5M2) ? mxk::MODE_E5M2
+               : (p->format == MXFFT_E2M3) ? mxk::MODE_E2M3
+               : (p->format == MXFFT_E3M2) ? mxk::MODE_E3M2
                : (p->format == MXFFT_FP16) ? mxk::MODE_FP16
                : (p->format == MXFFT_BF16) ? mxk::MODE_BF16
                                            : mxk::MODE_FP32;
-    if (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2) {
+    if (mxk::is_mx_mode(pl->mode)) {
         pl->cb = p->block / 2;
         pl->logcb = ilog2(pl->cb);
     }

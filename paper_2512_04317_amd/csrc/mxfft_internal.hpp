@@ -69,7 +69,9 @@ struct LineArgs {
 };
 
 // MX formats, the 16-bit positive controls (per-operation rounding) and plain FP32
-enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP16 = 2, MODE_BF16 = 3, MODE_FP32 = 4 };
+enum Mode { MODE_E4M3 = 0, MODE_E5M2 = 1, MODE_FP16 = 2, MODE_BF16 = 3, MODE_FP32 = 4, MODE_E2M3 = 5, MODE_E3M2 = 6 };
+// MX element formats: MXFP8 (E4M3, E5M2) and MXFP6 (E2M3, E3M2)
+inline bool is_mx_mode(int m) { return m == MODE_E4M3 || m == MODE_E5M2 || m == MODE_E2M3 || m == MODE_E3M2; }
 
 // Register-resident passes for n = 512 (see mxfft_fast.hip).
 struct FastPassArgs {

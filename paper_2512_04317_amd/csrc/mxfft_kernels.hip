@@ -560,6 +560,8 @@ hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s)
     case MODE_FP16: hipLaunchKernelGGL(k_lines<MODE_FP16>, grid, block, lds, s, a); break;
     case MODE_BF16: hipLaunchKernelGGL(k_lines<MODE_BF16>, grid, block, lds, s, a); break;
     case MODE_FP32: hipLaunchKernelGGL(k_lines<MODE_FP32>, grid, block, lds, s, a); break;
+    case MODE_E2M3: hipLaunchKernelGGL(k_lines<MODE_E2M3>, grid, block, lds, s, a); break;
+    case MODE_E3M2: hipLaunchKernelGGL(k_lines<MODE_E3M2>, grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -53,6 +53,8 @@ def plan_status(n, max_batch, **kw):
     (512, 1, dict(block=256), mxfft.EUNSUPPORTED),   # B > 128 not built
     (64, 1, dict(fmt="fp16", tau=-1.0), mxfft.EINVAL),
     (64, 1, dict(fmt=9), mxfft.EINVAL),
+    (64, 1, dict(fmt="e2m3", block=48), mxfft.EINVAL),   # MXFP6 blocks follow the MX rules
+    (64, 1, dict(fmt="e3m2", block=256), mxfft.EINVAL),
     (64, 1, dict(tau=101.0), mxfft.EINVAL),
     (64, 1, dict(target=0.0), mxfft.EINVAL),
     (64, 1, dict(target=float("nan")), mxfft.EINVAL),

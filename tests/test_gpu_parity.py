@@ -17,7 +17,7 @@ from paper_2512_04317_amd import mxfft, synth
 pytestmark = pytest.mark.gpu
 
 NTHREADS = min(16, os.cpu_count() or 1)
-FMTS = {"e4m3": O.E4M3, "e5m2": O.E5M2}
+FMTS = {"e4m3": O.E4M3, "e5m2": O.E5M2, "e2m3": O.E2M3, "e3m2": O.E3M2}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -268,6 +268,20 @@ def test_fast_sizes_all_blocks(N, op, fmt, B):
     the others with the two-kernel statistics) and the generic kernels
     otherwise."""
     x = synth.kspace_batch(N, 3, 1, 2)
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 %s %s B=%d" % (N, op, fmt, B))
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("fmt", ["e2m3", "e3m2"])
+@pytest.mark.parametrize("N,B", [(16, 8), (64, 32), (256, 16), (512, 32)])
+def test_fp6_forms(N, B, fmt, op):
+    """MXFP6 elements (E2M3, E3M2) on the generic line kernels: bit for bit."""
+    x = synth.kspace_batch(N, 3, 1, 2) if N >= 64 else synth.random_complex((3, N, N), seed=N, dist="lognormal")
     yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
     so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
     assert st == mxfft.OK and so == O.OK
