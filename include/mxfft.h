@@ -140,12 +140,15 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32
  * rounded square root.  The combine is fused into the last column pass:
  * the per-coil complex results are never written, only the images (1/(2 C)
  * of the plain call's output bytes).  work: complex64 [recon * coils][n][n]
- * scratch for the round trip's forward result and for the FP32 form's
- * intermediate (may be `in`, which is then overwritten); MXFFT_EINVAL when
- * it is needed and NULL; unused (may be NULL) otherwise.  k_out: int32[recon * coils] or
- * NULL.  recon * coils <= max_batch.  Only plans on the register-resident
+ * scratch for the round trip's forward result, for the FP32 form's
+ * intermediate, and for the per-coil results of plans without the fused
+ * epilogue (may be `in`, which is then overwritten); MXFFT_EINVAL when it is
+ * needed and NULL; unused (may be NULL) otherwise.  k_out: int32[recon *
+ * coils] or NULL.  recon * coils <= max_batch.  Plans on the register-resident
  * passes (n = 128..1024 with MX B = 4..32 or FP16/BF16, and FP32 at n = 512)
- * have the fused epilogue: others return MXFFT_EUNSUPPORTED. */
+ * fuse the combine; the others (generic line kernels) write the per-coil
+ * results to work and combine them in a separate kernel with the same
+ * arithmetic. */
 mxfft_status mxfft_rss(mxfft_plan_t plan, int32_t op, const void* in, void* work, float* rss, int32_t recon,
                        int32_t coils, int32_t* k_out, void* stream);
 

@@ -644,11 +644,19 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     // the FP32 form keeps its intermediate in complex64 (the row pass writes
     // it where the column pass reads it): `work` is that buffer
     const bool plain = pl->mode == mxk::MODE_FP32;
-    if ((op == 2 || plain) && !work) return MXFFT_EINVAL;
-    if (!pl->fast) return MXFFT_EUNSUPPORTED;
+    if ((op == 2 || plain || !pl->fast) && !work) return MXFFT_EINVAL;
     if (recon == 0) return MXFFT_OK;
     hipStream_t s = (hipStream_t)stream;
     const int batch = recon * coils;
+    if (!pl->fast) {
+        // no fused epilogue on the generic line kernels: the per-coil results
+        // go to `work`, then the combine
+        MX_TRY(op == 0 ? mxfft_forward(pl, in, work, batch, k_out, stream)
+                       : mxfft_roundtrip(pl, in, work, batch, k_out, stream));
+        return mxk::launch_rss((const float2*)work, coils, (size_t)pl->n * pl->n, recon, rss, s) == hipSuccess
+                   ? MXFFT_OK
+                   : MXFFT_EHIP;
+    }
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
     const int32_t* kp = pre ? pl->d_kp : nullptr;
     if (op == 0) {

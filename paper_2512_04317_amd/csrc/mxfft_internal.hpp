@@ -117,6 +117,9 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
                               int32_t* fix_count, int32_t* k_out, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);
+// Root-sum-of-squares coil combine of finished transforms (recon x coils slices).
+hipError_t launch_rss(const float2* T, int coils, size_t nn, long recon, float* rss, hipStream_t s);
+
 // Mean SSIM of count images x against references y (n x n FP32 each).
 hipError_t launch_ssim(const float* x, const float* y, int n, int count, double* out, hipStream_t s);
 

@@ -470,6 +470,37 @@ hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s)
     return hipGetLastError();
 }
 
+// Root-sum-of-squares coil combine of finished transforms (Eq. 1): T holds
+// [recon][coils][nn] complex values; rss[r][i] = (sum_c |T|^2)^(1/2) in FP32,
+// each square and their sum rounded, the coils in order, correctly rounded
+// square root (the arithmetic of the fused column-pass epilogue).
+__global__ void k_rss(const float2* __restrict__ T, int coils, size_t nn, size_t total, float* __restrict__ rss)
+{
+#pragma clang fp contract(off)
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = q / nn, i = q % nn;
+        const float2* t = T + r * coils * nn + i;
+        float acc = 0.0f;
+        for (int c = 0; c < coils; c++) {
+            const float2 v = t[(size_t)c * nn];
+            const float re2 = v.x * v.x;
+            const float im2 = v.y * v.y;
+            const float m2 = re2 + im2;
+            acc = acc + m2;
+        }
+        rss[q] = sqrtf(acc);
+    }
+}
+
+hipError_t launch_rss(const float2* T, int coils, size_t nn, long recon, float* rss, hipStream_t s)
+{
+    const size_t total = nn * (size_t)recon;
+    const size_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_rss, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, T, coils, nn, total,
+                       rss);
+    return hipGetLastError();
+}
+
 // Mean SSIM of image x against reference y per image (Wang, Bovik, Sheikh
 // and Simoncelli 2004): local means, variances and covariance under an
 // 11 x 11 Gaussian window of standard deviation 1.5 normalised to unit sum,

@@ -66,11 +66,34 @@ def test_rss_fp32_form_and_arguments():
     assert mxfft.lib().mxfft_rss(plan.handle, mxfft.FORWARD, mxfft._ptr(xd), None, mxfft._ptr(out), 1, coils, None,
                                  mxfft._stream(None)) == mxfft.EINVAL
     plan.close()
-    small = mxfft.Plan(64, 2)                               # generic kernels: no fused epilogue
-    with pytest.raises(mxfft.MxfftError) as e:
-        small.rss(torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda"), 2)
-    assert e.value.status == mxfft.EUNSUPPORTED
-    small.close()
+
+
+@pytest.mark.parametrize("op", [mxfft.FORWARD, mxfft.ROUNDTRIP])
+@pytest.mark.parametrize("N,fmt,block", [(64, "e4m3", 32), (512, "e2m3", 32), (256, "e3m2", 8)])
+def test_rss_generic_kernels(N, fmt, block, op):
+    """Plans without the fused epilogue (generic line kernels: small sizes,
+    MXFP6) transform into the scratch buffer and combine separately, with the
+    same arithmetic: bit for bit against the oracle."""
+    coils = 2
+    x = synth.kspace_batch(N, 4, 2, coils)
+    plan = mxfft.Plan(N, x.shape[0], fmt=fmt, block=block)
+    assert not plan.tuning()["fast"]
+    rss, k = plan.rss(torch.from_numpy(x).cuda(), coils, op=op)
+    assert plan.last_status() == mxfft.OK
+    fo = {"e4m3": O.E4M3, "e2m3": O.E2M3, "e3m2": O.E3M2}[fmt]
+    st, y, ko = O.transform(x, op=O.FORWARD if op == mxfft.FORWARD else O.ROUNDTRIP, fmt=fo, B=block,
+                            nthreads=NTHREADS)
+    assert st == O.OK
+    np.testing.assert_array_equal(k.cpu().numpy(), ko)
+    np.testing.assert_array_equal(rss.cpu().numpy().view(np.uint32), O.rss(y, coils).view(np.uint32))
+    with pytest.raises(mxfft.MxfftError) as e:              # the scratch buffer is required here
+        out = torch.empty((2, N, N), dtype=torch.float32, device="cuda")
+        st = mxfft.lib().mxfft_rss(plan.handle, int(op), mxfft._ptr(torch.from_numpy(x).cuda()), None,
+                                   mxfft._ptr(out), 2, coils, None, mxfft._stream(None))
+        if st != mxfft.OK:
+            raise mxfft.MxfftError(st, "mxfft_rss")
+    assert e.value.status == mxfft.EINVAL
+    plan.close()
 
 
 def test_ssim_kernel_against_oracle():
