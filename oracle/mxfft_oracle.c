@@ -286,6 +286,7 @@ typedef struct {
     int mode, fmt, B;
     double* scratch;    /* sized by line_scratch_doubles() */
     int* trace;         /* optional: per stage, per block (Ev, kr, Eout) for the first line */
+    int raw_input;      /* MX: the line enters the stages without the input encode */
 } passcfg;
 
 static long line_scratch_doubles(int N) { return 16L * N + 64; }
@@ -305,7 +306,7 @@ static void mx_line(const passcfg* c, int N, int inverse, float* a, int* trace)
     float* y1 = u + 6 * cb;
 
     /* input encode: blocks of cb consecutive complex in natural order */
-    for (int b = 0; b < N / cb; b++) {
+    for (int b = 0; b < N / cb && !c->raw_input; b++) {
         for (int k = 0; k < 2 * cb; k++) vals[k] = a[2 * b * cb + k];
         int E = orc_mx_encode(f, vals, 2 * cb, mant);
         for (int k = 0; k < 2 * cb; k++) a[2 * b * cb + k] = (float)ldexp(mant[k], E);
@@ -503,14 +504,16 @@ int orc_prescale(const float* x, long n, double target, double tau, double tau_m
 /* x <- fl32(in * 2^k_in); every row then every column gets a 1D pass;
  * FP16/BF16 round the result to the format; out <- fl32(y * 2^k_out). */
 static void transform2d(const passcfg* c, int N, int inverse, int k_in, int k_out,
-                        const float* in, float* out, float* line, int* trace)
+                        const float* in, float* out, float* line, int* trace, int raw_rows)
 {
     const long NN = (long)N * N;
     float* a = out;
+    passcfg rc = *c;            /* the row passes' configuration */
+    rc.raw_input = raw_rows;
     for (long i = 0; i < 2 * NN; i++) a[i] = (float)ldexp((double)in[i], k_in);
     for (int r = 0; r < N; r++) {
         memcpy(line, a + 2L * r * N, sizeof(float) * 2 * N);
-        run_line(c, N, inverse, line, r == 0 ? trace : NULL);
+        run_line(&rc, N, inverse, line, r == 0 ? trace : NULL);
         memcpy(a + 2L * r * N, line, sizeof(float) * 2 * N);
     }
     for (int col = 0; col < N; col++) {
@@ -577,7 +580,7 @@ static int run_slice(job* jb, long s, double* scratch, float* line)
     if (jb->op == 1 && jb->kp_given) {
         k = jb->kp[s];
         int ko = -k - ((jb->flags & ORC_NORMALIZE) ? 2 * L : 0);
-        transform2d(&c, N, 1, 0, ko, in, out, line, NULL);
+        transform2d(&c, N, 1, 0, ko, in, out, line, NULL, 0);
         return ORC_OK;
     }
     if (!(jb->flags & ORC_NO_PRESCALE))
@@ -586,16 +589,18 @@ static int run_slice(job* jb, long s, double* scratch, float* line)
     if (st != ORC_OK) { memset(out, 0, sizeof(float) * 2 * NN); return st; }
 
     if (jb->op == 0) {
-        transform2d(&c, N, 0, k, (jb->flags & ORC_KEEP_SCALE) ? 0 : -k, in, out, line, NULL);
+        transform2d(&c, N, 0, k, (jb->flags & ORC_KEEP_SCALE) ? 0 : -k, in, out, line, NULL, 0);
     } else if (jb->op == 1) {
         int ko = -k - ((jb->flags & ORC_NORMALIZE) ? 2 * L : 0);
-        transform2d(&c, N, 1, k, ko, in, out, line, NULL);
+        transform2d(&c, N, 1, k, ko, in, out, line, NULL, 0);
     } else {
         /* round trip (Eq. 1): forward keeping the scale, then the inverse with
-         * the same k, then 2^(-k - 2 log2 N) */
+         * the same k, then 2^(-k - 2 log2 N).  Fused (the encode -> F -> F^-1
+         * -> decode of the discussion, Sec. 4): the forward result enters the
+         * inverse's row stages without being MX-encoded again. */
         float* mid = (float*)malloc(sizeof(float) * 2 * NN);
-        transform2d(&c, N, 0, k, 0, in, mid, line, NULL);
-        transform2d(&c, N, 1, 0, -k - 2 * L, mid, out, line, NULL);
+        transform2d(&c, N, 0, k, 0, in, mid, line, NULL, 0);
+        transform2d(&c, N, 1, 0, -k - 2 * L, mid, out, line, NULL, (jb->flags & ORC_FUSED_RT) ? 1 : 0);
         free(mid);
     }
     return ORC_OK;
