@@ -69,6 +69,11 @@ typedef enum {
 #define MXFFT_NO_PRESCALE 0x1u  /* skip Alg. 1: k = 0 for every slice */
 #define MXFFT_KEEP_SCALE  0x2u  /* forward: return 2^k * F{x} (do not de-scale) */
 #define MXFFT_NORMALIZE   0x4u  /* inverse: multiply by 1/N^2 (Eq. 1 round trip) */
+/* round trip, MX formats: the forward result enters the inverse transform's
+ * row stages without being MX-encoded again (the encode -> F -> F^-1 -> decode
+ * fusion the paper proposes in its discussion, Sec. 4; less round-trip loss).
+ * No effect on the other operations and formats. */
+#define MXFFT_FUSED_ROUNDTRIP 0x8u
 
 typedef struct {
     uint32_t struct_size;  /* sizeof(mxfft_params); checked for ABI versioning */

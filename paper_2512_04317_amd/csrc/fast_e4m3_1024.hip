@@ -12,6 +12,7 @@ hipError_t launch_fast_e4m3_1024(int cb, bool row, bool inverse, int kind, const
 #define MXF_CASE(CC, INV)                                                                                  \
     if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf1024::k_col_rss<0, CC, INV>), grid, block, 0, s, g); \
     else if (!row) hipLaunchKernelGGL((mxf1024::k_col<0, CC, INV>), grid, block, 0, s, g);                  \
+    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf1024::k_row<0, CC, INV, ROW_RAW>), grid, block, 0, s, g); \
     else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf1024::k_row<0, CC, INV, ROW_STATS>), grid, block, 0, s, g);   \
     else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf1024::k_row_fix<0, CC, INV>), grid, block, 0, s, g);           \
     else hipLaunchKernelGGL((mxf1024::k_row<0, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);

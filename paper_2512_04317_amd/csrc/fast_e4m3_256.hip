@@ -12,6 +12,7 @@ hipError_t launch_fast_e4m3_256(int cb, bool row, bool inverse, int kind, const 
 #define MXF_CASE(CC, INV)                                                                                  \
     if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf256::k_col_rss<0, CC, INV>), grid, block, 0, s, g); \
     else if (!row) hipLaunchKernelGGL((mxf256::k_col<0, CC, INV>), grid, block, 0, s, g);                  \
+    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf256::k_row<0, CC, INV, ROW_RAW>), grid, block, 0, s, g); \
     else if (kind != ROW_PLAIN) return hipErrorInvalidValue;                                          \
     else hipLaunchKernelGGL((mxf256::k_row<0, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
     switch (cb * 2 + (inverse ? 1 : 0)) {

@@ -385,6 +385,7 @@ using mxk::StatPart;
 using mxk::ROW_PLAIN;
 using mxk::ROW_STATS;
 using mxk::ROW_FIX;
+using mxk::ROW_RAW;
 
 __device__ __forceinline__ int slice_k(const FastArgs& g, int slice)
 {
@@ -775,6 +776,7 @@ struct alignas(16) RowLds {
 //   ROW_STATS  input unscaled; also the Alg. 1 statistics of the tile (with the
 //              range of the block exponents used) into parts[slice][tile]
 //   ROW_FIX    input scaled by 2^kp: the literal pass for a listed slice
+//   ROW_RAW    as ROW_PLAIN without the input MX encode (fused round trip)
 template <int F, int C, bool INV, int KIND>
 __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, RowLds<F, C, KIND>& L)
 {
@@ -782,6 +784,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr int NSB = RowLds<F, C, KIND>::NSB;
     constexpr bool ST = (KIND == ROW_STATS);
     static_assert(!ST || is_mx(F), "statistics ride on the MX row pass only");
+    static_assert(KIND != ROW_RAW || is_mx(F), "the raw row pass is an MX variant");
     float* s_plane = L.plane;
     float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -853,8 +856,10 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             if (lane == 0) { L.m2[wave] = m2max; L.nf[wave] = nf; }
         }
         // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive
-        // lanes, or (lines of 4 lanes, blocks of 16) in two loads of every lane
-        if constexpr (CB / 2 <= LPL) {
+        // lanes, or (lines of 4 lanes, blocks of 16) in two loads of every lane;
+        // ROW_RAW leaves the input as it is
+        if constexpr (KIND == ROW_RAW) {
+        } else if constexpr (CB / 2 <= LPL) {
             sfor<P / 2>([&](auto I) {
                 float am;
                 const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);

@@ -13,7 +13,7 @@
 
 namespace {
 
-constexpr uint32_t kKnownFlags = MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE;
+constexpr uint32_t kKnownFlags = MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE | MXFFT_FUSED_ROUNDTRIP;
 
 // Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2) and the
 // 16-bit forms (IEEE half, bfloat16; twiddles never reach their overflow).
@@ -346,7 +346,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     a.lines = pl->lines ? pl->lines : mxk::line_lines_per_group(pl->n);
     a.axis = axis;
     a.inverse = inverse;
-    a.encode = mxk::is_mx_mode(pl->mode);
+    a.encode = mxk::is_mx_mode(pl->mode) && kind != mxk::ROW_RAW;
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -395,6 +395,13 @@ mxfft_status row_with_stats(mxfft_plan_s* pl, const void* in, int32_t* k_out, in
             return MXFFT_EHIP;
     }
     return pass(pl, in, nullptr, pl->d_kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
+}
+
+// Row pass kind of the round trip's inverse half: without the input encode
+// when the fused round trip is asked for (MX formats).
+int inverse_row_kind(const mxfft_plan_s* pl)
+{
+    return (pl->p.flags & MXFFT_FUSED_ROUNDTRIP) && mxk::is_mx_mode(pl->mode) ? mxk::ROW_RAW : mxk::ROW_PLAIN;
 }
 
 mxfft_status check_call(const mxfft_plan_s* pl, const void* in, const void* out, int32_t batch)
@@ -629,7 +636,7 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
         MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
         MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
     }
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
+    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
     MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     pl->last_batch = batch;
     pl->last_has_stats = pre;
@@ -681,7 +688,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
             MX_TRY(pass(pl, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
             MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
         }
-        MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 0, 1, batch, s));
+        MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
         MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, recon, s, mxk::COL_RSS, nullptr, rss,
                     coils));
     }

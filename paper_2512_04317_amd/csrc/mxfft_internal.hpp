@@ -95,7 +95,9 @@ struct FastPassArgs {
 };
 
 // Row pass kinds of the register-resident passes.
-enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2, COL_RSS = 3 };
+// ROW_RAW: an MX row pass whose input enters the stages without the input
+// encode (the inverse half of the fused round trip).
+enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2, COL_RSS = 3, ROW_RAW = 4 };
 
 bool fast_supported(int mode, int n, int cb);
 // whether the row pass can gather the Alg. 1 statistics (register-resident MX passes)

@@ -290,6 +290,20 @@ def test_fp6_forms(N, B, fmt, op):
     assert_bitexact(yg, yo, "%d^2 %s %s B=%d" % (N, op, fmt, B))
 
 
+@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e5m2", 8), ("e2m3", 32)])
+@pytest.mark.parametrize("N", [64, 128, 512, 1024])
+def test_fused_roundtrip(N, fmt, B):
+    """The fused round trip (no re-encode between the transforms) on every
+    kind of pass: bit for bit against the oracle's fused round trip."""
+    x = synth.kspace_batch(N, 2, 1, 2)
+    img = np.fft.ifft2(x.astype(np.complex128)).astype(np.complex64)
+    yg, kg, st = gpu_run(img, op="roundtrip", fmt=fmt, block=B, flags=mxfft.FUSED_ROUNDTRIP)
+    so, yo, ko = orc_run(img, op="roundtrip", fmt=fmt, block=B, flags=O.FUSED_RT)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "fused round trip %d^2 %s B=%d" % (N, fmt, B))
+
+
 def mixed_512_batch(N=512):
     """Slices inside and outside the window where the statistics ride on the
     unscaled row pass: k-space, tiny, all-zero, huge, single value, heavy-tailed."""
