@@ -231,6 +231,18 @@ def rss_quality(args, torch, mxfft, x, xd, N, recon=8, coils=16):
             if over.get(op):
                 row[opn]["prescale"] = {"target": pkw["target"], "tau_min": pkw["tau_min"]}
             pl.close()
+        if name[:2] == "e4" or name[:2] == "e5" or name[:2] == "e2" or name[:2] == "e3":
+            # the fused round trip of the paper's discussion (no re-encode between F and F^-1)
+            pl = mxfft.Plan(N, n_sl, flags=mxfft.FUSED_ROUNDTRIP, **kw)
+            img, _ = pl.rss(inputs[mxfft.ROUNDTRIP], coils, op=mxfft.ROUNDTRIP)
+            ss = mxfft.ssim(img, refs_d[mxfft.ROUNDTRIP]).cpu().numpy()
+            y = img.cpu().numpy().astype(np.float64)
+            r = refs[mxfft.ROUNDTRIP]
+            mse = ((y - r) ** 2).mean(axis=(1, 2))
+            row["roundtrip_fused"] = {"ssim": fin(ss.mean(), 5),
+                                      "psnr_db": fin((20 * np.log10(r.max(axis=(1, 2)) / np.sqrt(mse))).mean(), 2),
+                                      "nmse": fin((((y - r) ** 2).sum(axis=(1, 2)) / (r ** 2).sum(axis=(1, 2))).mean(), 6)}
+            pl.close()
         out[name] = row
     # fused combine over the whole batch (64 reconstructions x 16 coils) against the plain forward
     plan = mxfft.Plan(N, xd.shape[0], fmt=args.fmt, block=args.block)
