@@ -1,0 +1,30 @@
+// fast_e2m3.hip -- instantiations of the register-resident 512^2 passes for MXFP6-E2M3 (blocks of 16 and 32).
+#define MXF_LOGN 9
+#define MXF_NS mxf
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+hipError_t launch_fast_e2m3(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch,
+                          hipStream_t s)
+{
+    const dim3 grid((mxf::N / mxf::LINES) * batch), block(256);
+#define MXF_CASE(CC, INV)                                                                                \
+    if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf::k_col_rss<5, CC, INV>), grid, block, 0, s, g); \
+    else if (!row) hipLaunchKernelGGL((mxf::k_col<5, CC, INV>), grid, block, 0, s, g);                  \
+    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf::k_row<5, CC, INV, ROW_RAW>), grid, block, 0, s, g); \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf::k_row<5, CC, INV, ROW_STATS>), grid, block, 0, s, g); \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf::k_row_fix<5, CC, INV>), grid, block, 0, s, g);       \
+    else hipLaunchKernelGGL((mxf::k_row<5, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
+    switch (cb * 2 + (inverse ? 1 : 0)) {
+    case 16: MXF_CASE(3, false) break;
+    case 17: MXF_CASE(3, true) break;
+    case 32: MXF_CASE(4, false) break;
+    case 33: MXF_CASE(4, true) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MXF_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mxk

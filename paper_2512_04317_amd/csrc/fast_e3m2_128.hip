@@ -1,0 +1,29 @@
+// fast_e3m2_128.hip -- instantiations of the register-resident 128^2 passes for MXFP6-E3M2 (blocks of 16 and 32).
+#define MXF_LOGN 7
+#define MXF_NS mxf128
+#include "mxfft_fast.hpp"
+
+namespace mxk {
+
+hipError_t launch_fast_e3m2_128(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch,
+                               hipStream_t s)
+{
+    const dim3 grid((mxf128::N / mxf128::LINES) * batch), block(mxf128::THREADS);
+#define MXF_CASE(CC, INV)                                                                                  \
+    if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf128::k_col_rss<6, CC, INV>), grid, block, 0, s, g); \
+    else if (!row) hipLaunchKernelGGL((mxf128::k_col<6, CC, INV>), grid, block, 0, s, g);                  \
+    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf128::k_row<6, CC, INV, ROW_RAW>), grid, block, 0, s, g); \
+    else if (kind != ROW_PLAIN) return hipErrorInvalidValue;                                          \
+    else hipLaunchKernelGGL((mxf128::k_row<6, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
+    switch (cb * 2 + (inverse ? 1 : 0)) {
+    case 16: MXF_CASE(3, false) break;
+    case 17: MXF_CASE(3, true) break;
+    case 32: MXF_CASE(4, false) break;
+    case 33: MXF_CASE(4, true) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MXF_CASE
+    return hipGetLastError();
+}
+
+}  // namespace mxk

@@ -10,6 +10,14 @@ hipError_t launch_fast_e5m2(int cb, bool row, bool inverse, int kind, const mxf:
 hipError_t launch_fast_fp32(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_fp16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_bf16(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e2m3(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e2m3_128(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e2m3_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e2m3_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e3m2(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e3m2_128(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e3m2_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_e3m2_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_fp16_128(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_bf16_128(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_fp16_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
@@ -25,7 +33,9 @@ hipError_t launch_fast_e5m2_1024(int cb, bool row, bool inverse, int kind, const
 
 bool fast_supported(int mode, int n, int cb)
 {
-    const bool mx = (mode == MODE_E4M3 || mode == MODE_E5M2) && cb >= 2 && cb <= 16;
+    // MXFP6 is instantiated for blocks of 16 and 32 only
+    const bool mx = ((mode == MODE_E4M3 || mode == MODE_E5M2) && cb >= 2 && cb <= 16) ||
+                    ((mode == MODE_E2M3 || mode == MODE_E3M2) && (cb == 8 || cb == 16));
     if (n == 512) return mx || mode == MODE_FP32 || mode == MODE_FP16 || mode == MODE_BF16;
     return (n == 128 || n == 256 || n == 1024) && (mx || mode == MODE_FP16 || mode == MODE_BF16);
 }
@@ -33,7 +43,7 @@ bool fast_supported(int mode, int n, int cb)
 bool fast_fused_stats(int mode, int n)
 {
     // the statistics histogram lives in the exchange planes of the row pass
-    return (mode == MODE_E4M3 || mode == MODE_E5M2) && (n == 512 || n == 1024);
+    return is_mx_mode(mode) && (n == 512 || n == 1024);
 }
 
 int fast_row_tiles(int n)
@@ -76,6 +86,14 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
     case MODE_BF16 * 4096 + 256: return launch_fast_bf16_256(cb, row, inverse, kind, g, batch, s);
     case MODE_FP16 * 4096 + 1024: return launch_fast_fp16_1024(cb, row, inverse, kind, g, batch, s);
     case MODE_BF16 * 4096 + 1024: return launch_fast_bf16_1024(cb, row, inverse, kind, g, batch, s);
+    case MODE_E2M3 * 4096 + 128: return launch_fast_e2m3_128(cb, row, inverse, kind, g, batch, s);
+    case MODE_E2M3 * 4096 + 256: return launch_fast_e2m3_256(cb, row, inverse, kind, g, batch, s);
+    case MODE_E2M3 * 4096 + 512: return launch_fast_e2m3(cb, row, inverse, kind, g, batch, s);
+    case MODE_E2M3 * 4096 + 1024: return launch_fast_e2m3_1024(cb, row, inverse, kind, g, batch, s);
+    case MODE_E3M2 * 4096 + 128: return launch_fast_e3m2_128(cb, row, inverse, kind, g, batch, s);
+    case MODE_E3M2 * 4096 + 256: return launch_fast_e3m2_256(cb, row, inverse, kind, g, batch, s);
+    case MODE_E3M2 * 4096 + 512: return launch_fast_e3m2(cb, row, inverse, kind, g, batch, s);
+    case MODE_E3M2 * 4096 + 1024: return launch_fast_e3m2_1024(cb, row, inverse, kind, g, batch, s);
     case MODE_E4M3 * 4096 + 128: return launch_fast_e4m3_128(cb, row, inverse, kind, g, batch, s);
     case MODE_E5M2 * 4096 + 128: return launch_fast_e5m2_128(cb, row, inverse, kind, g, batch, s);
     case MODE_E4M3 * 4096 + 256: return launch_fast_e4m3_256(cb, row, inverse, kind, g, batch, s);

@@ -52,8 +52,10 @@ typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
 
 constexpr int FP16 = 2;          // format ids of the plain forms (mxk::MODE_FP16,
 constexpr int BF16 = 3;          // mxk::MODE_BF16, mxk::MODE_FP32); 0 and 1 are
-constexpr int FP32 = 4;          // the MX element formats E4M3 and E5M2
-constexpr bool is_mx(int F) { return F < FP16; }
+constexpr int FP32 = 4;          // the MXFP8 element formats E4M3 and E5M2, 5 and 6
+constexpr int E2M3 = 5;          // the MXFP6 ones E2M3 and E3M2
+constexpr int E3M2 = 6;
+constexpr bool is_mx(int F) { return F < FP16 || F == E2M3 || F == E3M2; }
 constexpr bool is_16(int F) { return F == FP16 || F == BF16; }
 
 // ---------------------------------------------------------------------------
@@ -104,12 +106,62 @@ __device__ __forceinline__ void wave_sync()
 // 2^E as the E8M0-style scale operand, -127 <= E <= 127.
 __device__ __forceinline__ float e8(int E) { return __uint_as_float((uint32_t)(E + 127) << 23); }
 
-// MAXV * 2^E (MAXV = 1.75 * 2^EMAX), the saturation bound at block scale 2^E.
+// Conversion hardware of element format F.  MXFP6 travels in the FP8
+// conversions: an E2M3 value times 2^-6 is an E4M3 value and an E3M2 value
+// times 2^-12 an E5M2 value (same mantissa width, subnormal spacing and
+// smallest normal), so encoding x / 2^E to FP6 is encoding x / 2^(E + OFF)
+// to FP8 and decoding multiplies by 2^(E + OFF).
+template <int F> struct Hw { static constexpr int FMT = F, OFF = 0; };
+template <> struct Hw<5> { static constexpr int FMT = 0, OFF = 6; };    // E2M3 via E4M3
+template <> struct Hw<6> { static constexpr int FMT = 1, OFF = 12; };   // E3M2 via E5M2
+
+// Mantissa field of MAXV (0x600000 for 1.75, 0x700000 for 1.875).
+template <int F>
+constexpr uint32_t maxv_frac() { return __builtin_bit_cast(uint32_t, mxd::Elem<F>::MAXV) & 0x007FFFFFu; }
+
+// MAXV * 2^E, the saturation bound at block scale 2^E.
 template <int F>
 __device__ __forceinline__ float lim_of(int E)
 {
-    return __uint_as_float(((uint32_t)(E + mxd::Elem<F>::EMAX + 127) << 23) | 0x00600000u);
+    constexpr uint32_t MF = maxv_frac<F>();
+    return __uint_as_float(((uint32_t)(E + mxd::Elem<F>::EMAX + 127) << 23) | MF);
 }
+
+// Block scale at exponent E for the conversions: the scale operand s, a
+// factor pre applied to the values before encoding (and to the saturation
+// bound) and post applied after decoding.  FP8: s = 2^E.  FP6: s = 2^(E+OFF),
+// unless E + OFF is above the scale range; then s = 2^E with pre = 2^-OFF and
+// post = 2^OFF (exact: such blocks hold values near 2^(127 - OFF)).
+struct Blk {
+    float s, pre, post;
+};
+template <int F>
+__device__ __forceinline__ Blk blk(int E)
+{
+    constexpr int OFF = Hw<F>::OFF;
+    if constexpr (OFF == 0) {
+        return Blk{e8(E), 1.0f, 1.0f};
+    } else {
+        const bool hi = E > 127 - OFF;
+        return Blk{e8(hi ? E : E + OFF), hi ? e8(-OFF) : 1.0f, hi ? e8(OFF) : 1.0f};
+    }
+}
+// v * f, only for the formats with a scale offset
+template <int F>
+__device__ __forceinline__ float2 mulp(float2 v, float f)
+{
+    if constexpr (Hw<F>::OFF == 0) return v;
+    else return make_float2(v.x * f, v.y * f);
+}
+template <int F>
+__device__ __forceinline__ float mulp1(float v, float f)
+{
+    if constexpr (Hw<F>::OFF == 0) return v;
+    else return v * f;
+}
+// scale operand that decodes codes to element values (2^OFF)
+template <int F>
+__device__ __forceinline__ float unit_scale() { return e8(Hw<F>::OFF); }
 
 // codes of (a, b) / 2^E in the low (W = 0) or high (W = 1) half of `old`
 template <int F, bool W>
@@ -118,7 +170,7 @@ __device__ __forceinline__ uint32_t enc2(uint32_t old, float a, float b, float s
     short2v o;
     __builtin_memcpy(&o, &old, 4);
     short2v r;
-    if constexpr (F == 0) r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(o, a, b, scale, W);
+    if constexpr (Hw<F>::FMT == 0) r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(o, a, b, scale, W);
     else r = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(o, a, b, scale, W);
     uint32_t u;
     __builtin_memcpy(&u, &r, 4);
@@ -130,7 +182,7 @@ template <int F, bool W>
 __device__ __forceinline__ float2 dec2(uint32_t codes, float scale)
 {
     float2v d;
-    if constexpr (F == 0) d = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, scale, W);
+    if constexpr (Hw<F>::FMT == 0) d = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, scale, W);
     else d = __builtin_amdgcn_cvt_scalef32_pk_f32_bf8(codes, scale, W);
     return make_float2(d.x, d.y);
 }
@@ -189,12 +241,15 @@ __device__ __forceinline__ int mx_requant(float2* v, float& am)
 {
     am = amax_of<CNT>(v);
     const int E = mxd::block_exp<F>(__float_as_uint(am));
-    const float s = e8(E), lim = lim_of<F>(E);
+    const Blk b = blk<F>(E);
+    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
     uint32_t c[CNT / 2];
-    sfor<CNT / 2>([&](auto H) { c[H] = enc4<F>(clamp2(v[2 * H], lim), clamp2(v[2 * H + 1], lim), s); });
     sfor<CNT / 2>([&](auto H) {
-        v[2 * H] = dec2<F, false>(c[H], s);
-        v[2 * H + 1] = dec2<F, true>(c[H], s);
+        c[H] = enc4<F>(clamp2(mulp<F>(v[2 * H], b.pre), lim), clamp2(mulp<F>(v[2 * H + 1], b.pre), lim), s);
+    });
+    sfor<CNT / 2>([&](auto H) {
+        v[2 * H] = mulp<F>(dec2<F, false>(c[H], s), b.post);
+        v[2 * H + 1] = mulp<F>(dec2<F, true>(c[H], s), b.post);
     });
     return E;
 }
@@ -237,10 +292,11 @@ __device__ __forceinline__ int mx_requant_pair(float2& v0, float2& v1, float& am
     a = group_max_bits<CB / 2>(a);
     am = __uint_as_float(a);
     const int E = mxd::block_exp<F>(a);
-    const float s = e8(E), lim = lim_of<F>(E);
-    const uint32_t c = enc4<F>(clamp2(v0, lim), clamp2(v1, lim), s);
-    v0 = dec2<F, false>(c, s);
-    v1 = dec2<F, true>(c, s);
+    const Blk b = blk<F>(E);
+    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
+    const uint32_t c = enc4<F>(clamp2(mulp<F>(v0, b.pre), lim), clamp2(mulp<F>(v1, b.pre), lim), s);
+    v0 = mulp<F>(dec2<F, false>(c, s), b.post);
+    v1 = mulp<F>(dec2<F, true>(c, s), b.post);
     return E;
 }
 
@@ -259,13 +315,14 @@ __device__ __forceinline__ int mx_requant_quad(float2& v0, float2& v1, float2& v
     a = group_max_bits<G>(a);
     am = __uint_as_float(a);
     const int E = mxd::block_exp<F>(a);
-    const float s = e8(E), lim = lim_of<F>(E);
-    const uint32_t c0 = enc4<F>(clamp2(v0, lim), clamp2(v1, lim), s);
-    const uint32_t c1 = enc4<F>(clamp2(v2, lim), clamp2(v3, lim), s);
-    v0 = dec2<F, false>(c0, s);
-    v1 = dec2<F, true>(c0, s);
-    v2 = dec2<F, false>(c1, s);
-    v3 = dec2<F, true>(c1, s);
+    const Blk b = blk<F>(E);
+    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
+    const uint32_t c0 = enc4<F>(clamp2(mulp<F>(v0, b.pre), lim), clamp2(mulp<F>(v1, b.pre), lim), s);
+    const uint32_t c1 = enc4<F>(clamp2(mulp<F>(v2, b.pre), lim), clamp2(mulp<F>(v3, b.pre), lim), s);
+    v0 = mulp<F>(dec2<F, false>(c0, s), b.post);
+    v1 = mulp<F>(dec2<F, true>(c0, s), b.post);
+    v2 = mulp<F>(dec2<F, false>(c1, s), b.post);
+    v3 = mulp<F>(dec2<F, true>(c1, s), b.post);
     return E;
 }
 
@@ -641,13 +698,16 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
             const float am = amax_of<CB>(V);
             const int Ev = mxd::block_exp<F>(__float_as_uint(am));
             if constexpr (TR) er.add(Ev);
-            const float s = e8(Ev), lim = lim_of<F>(Ev);
+            const Blk bv = blk<F>(Ev);
+            const float s = bv.s, lim = mulp1<F>(lim_of<F>(Ev), bv.pre);
             uint32_t c[CB / 2];
-            sfor<CB / 2>([&](auto H) { c[H] = enc4<F>(clamp2(V[2 * H], lim), clamp2(V[2 * H + 1], lim), s); });
+            sfor<CB / 2>([&](auto H) {
+                c[H] = enc4<F>(clamp2(mulp<F>(V[2 * H], bv.pre), lim), clamp2(mulp<F>(V[2 * H + 1], bv.pre), lim), s);
+            });
             sfor<CB>([&](auto T) {
                 constexpr int ou = base | deposit(T, BFLY);
                 constexpr int jc = Ly::posF(K, ou) & (h - 1);
-                float2 w = dec2<F, (T & 1) == 1>(c[T / 2], s);
+                float2 w = mulp<F>(dec2<F, (T & 1) == 1>(c[T / 2], s), bv.post);
                 if constexpr (jc == 1) w = INV ? make_float2(-w.y, w.x) : make_float2(w.y, -w.x);
                 a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
                 a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
@@ -658,25 +718,31 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
             // operand v: EncodeBlockMX, element values as FP32 mantissas
             const int Ev = mxd::block_exp<F>(bmax(amax_of<CB>(V)));
             if constexpr (TR) er.add(Ev);
-            const float s = e8(Ev), lim = lim_of<F>(Ev);
+            const Blk bv = blk<F>(Ev);
+            const float s = bv.s, lim = mulp1<F>(lim_of<F>(Ev), bv.pre);
             float2 Pp[CB];
             uint32_t cv[CB / 2];
-            sfor<CB / 2>([&](auto H) { cv[H] = enc4<F>(clamp2(V[2 * H], lim), clamp2(V[2 * H + 1], lim), s); });
+            sfor<CB / 2>([&](auto H) {
+                cv[H] = enc4<F>(clamp2(mulp<F>(V[2 * H], bv.pre), lim), clamp2(mulp<F>(V[2 * H + 1], bv.pre), lim), s);
+            });
             sfor<CB>([&](auto T) {
                 constexpr int ou = base | deposit(T, BFLY);
                 constexpr int jc = Ly::posF(K, ou) & (h - 1);
                 const float2 x = t.tw[h + (jm | jc)];
-                const float2 y = dec2<F, (T & 1) == 1>(cv[T / 2], 1.0f);
+                const float2 y = dec2<F, (T & 1) == 1>(cv[T / 2], unit_scale<F>());
                 const float xi = INV ? -x.y : x.y;
-                // products of 8-bit elements are exact: one rounding per component
+                // products of 8-bit (and 6-bit) elements are exact: one rounding per component
                 Pp[T].x = x.x * y.x - xi * y.y;
                 Pp[T].y = x.x * y.y + xi * y.x;
             });
             const int kr = mxd::renorm_exp<F>(bmax(amax_of<CB>(Pp)));
-            const float sp = e8(kr);
+            constexpr int OFF = Hw<F>::OFF;
+            const float sp = e8(kr + OFF);
             const int Eo = Ew + Ev + kr;
-            if (__builtin_expect(Eo >= -127, 1)) {
-                const float so = e8(Eo);
+            // the product block's scale operand 2^(Eo + OFF) must be in range
+            const bool in_range = (OFF == 0) ? (Eo >= -127) : (Eo + OFF >= -127 && Eo + OFF <= 127);
+            if (__builtin_expect(in_range, 1)) {
+                const float so = e8(Eo + OFF);
                 uint32_t cp[CB / 2];
                 sfor<CB / 2>([&](auto H) { cp[H] = enc4<F>(Pp[2 * H], Pp[2 * H + 1], sp); });
                 sfor<CB>([&](auto T) {
@@ -686,12 +752,12 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
                     a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
                 });
             } else {
-                // product scale below the E8M0 range: decode the elements and
+                // product scale outside the E8M0 range: decode the elements and
                 // apply 2^Eo with ldexp (correctly rounded, subnormals kept)
                 sfor<CB>([&](auto T) {
                     constexpr int ou = base | deposit(T, BFLY);
                     const uint32_t c = enc2<F, false>(__float_as_uint(Pp[T].x), Pp[T].x, Pp[T].y, sp);
-                    const float2 q = dec2<F, false>(c, 1.0f);
+                    const float2 q = dec2<F, false>(c, unit_scale<F>());
                     const float2 w = make_float2(ldexpf(q.x, Eo), ldexpf(q.y, Eo));
                     a[ou] = make_float2(U[T].x + w.x, U[T].y + w.y);
                     a[ou | (1 << ob)] = make_float2(U[T].x - w.x, U[T].y - w.y);
@@ -975,7 +1041,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         }
         __syncthreads();
         // 3. encode: clamp to MAXV * 2^E (bits of 2^E plus those of MAXV), scaled conversion
-        constexpr uint32_t LIMADD = ((uint32_t)mxd::Elem<F>::EMAX << 23) | 0x00600000u;
+        constexpr uint32_t LIMADD = ((uint32_t)mxd::Elem<F>::EMAX << 23) | maxv_frac<F>();
         const float* my_sc = s_sc + (rl / CB) * N;
         uint32_t* cd = g.codes + ((size_t)slice * N * N) / 2;
         // in-lane column groups: CG consecutive columns (in-lane offset bits 0..CL-1)
@@ -998,13 +1064,35 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             sfor<CG / 2>([&](auto H) {
                 constexpr int oa = o0 + 2 * H, obx = oa + 1;
                 const float sa = sc[2 * H], sb = sc[2 * H + 1];
-                const float la = __uint_as_float(__float_as_uint(sa) + LIMADD);
-                const float lb = __uint_as_float(__float_as_uint(sb) + LIMADD);
-                const float ra = __builtin_amdgcn_fmed3f(a[oa].x, -la, la);
-                uint32_t r = enc2<F, false>(__float_as_uint(ra), ra, __builtin_amdgcn_fmed3f(a[oa].y, -la, la), sa);
-                r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x, -lb, lb),
-                                  __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), sb);
-                w[H] = r;
+                if constexpr (Hw<F>::OFF == 0) {
+                    const float la = __uint_as_float(__float_as_uint(sa) + LIMADD);
+                    const float lb = __uint_as_float(__float_as_uint(sb) + LIMADD);
+                    const float ra = __builtin_amdgcn_fmed3f(a[oa].x, -la, la);
+                    uint32_t r = enc2<F, false>(__float_as_uint(ra), ra, __builtin_amdgcn_fmed3f(a[oa].y, -la, la), sa);
+                    r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x, -lb, lb),
+                                      __builtin_amdgcn_fmed3f(a[obx].y, -lb, lb), sb);
+                    w[H] = r;
+                } else {
+                    // MXFP6: scale operand 2^(E + OFF), or 2^E with the values
+                    // times 2^-OFF when E + OFF is above the scale range
+                    constexpr int OFF = Hw<F>::OFF;
+                    auto prep = [&](float sc2, float& op, float& pre, float& lim) {
+                        const uint32_t b = __float_as_uint(sc2);
+                        const bool hi = b > ((uint32_t)(254 - OFF) << 23);
+                        op = __uint_as_float(hi ? b : b + ((uint32_t)OFF << 23));
+                        pre = hi ? e8(-OFF) : 1.0f;
+                        lim = __uint_as_float(b + LIMADD) * pre;
+                    };
+                    float opa, pa, la, opb, pb, lb;
+                    prep(sa, opa, pa, la);
+                    prep(sb, opb, pb, lb);
+                    const float ra = __builtin_amdgcn_fmed3f(a[oa].x * pa, -la, la);
+                    uint32_t r = enc2<F, false>(__float_as_uint(ra), ra,
+                                                __builtin_amdgcn_fmed3f(a[oa].y * pa, -la, la), opa);
+                    r = enc2<F, true>(r, __builtin_amdgcn_fmed3f(a[obx].x * pb, -lb, lb),
+                                      __builtin_amdgcn_fmed3f(a[obx].y * pb, -lb, lb), opb);
+                    w[H] = r;
+                }
             });
             // [16-column group][row][8 words], word of columns 2w, 2w+1 of the
             // group at position w ^ cswz(row)
@@ -1181,8 +1269,18 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
             const int n = (rev(O, 5) << LOG_LPL) | rm;    // row of position 32m + O
             const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
             const int eb = (int)((s_ex4[(n / CB) * 4] >> exsh) & 0xffu);
-            const float s = __uint_as_float((uint32_t)(eb + eadd) << 23);
-            a[O] = dec2<F, false>(wd >> cdsh, s);
+            if constexpr (Hw<F>::OFF == 0) {
+                const float s = __uint_as_float((uint32_t)(eb + eadd) << 23);
+                a[O] = dec2<F, false>(wd >> cdsh, s);
+            } else {
+                // MXFP6: scale operand 2^(E + OFF), or 2^E and a factor 2^OFF
+                // after decoding when E + OFF is above the scale range
+                constexpr int OFF = Hw<F>::OFF;
+                const int ebits = eb + eadd;
+                const bool hi = ebits > 254 - OFF;
+                const float s = __uint_as_float((uint32_t)(hi ? ebits : ebits + OFF) << 23);
+                a[O] = mulp<F>(dec2<F, false>(wd >> cdsh, s), hi ? e8(OFF) : 1.0f);
+            }
         });
         __syncthreads();
     }

@@ -304,6 +304,7 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     LaunchTimer timer(pl, role, s);
     if (pl->fast) {
         // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
+        if (mxk::is_mx_mode(pl->mode) && (!pl->d_codes || !pl->d_exps)) return MXFFT_EHIP;
         mxk::FastPassArgs f{};
         f.src = (const float2*)src;
         f.dst = (float2*)dst;
@@ -490,7 +491,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         for (long h = 1; h < n; h <<= 1)
             for (long j = 0; j < h; j++) twf[h + j] = tw[h - 1 + j];
         st = dev_alloc(pl, &pl->d_twf, twf.size());
-        if (st == MXFFT_OK && (pl->mode == mxk::MODE_E4M3 || pl->mode == mxk::MODE_E5M2)) {
+        if (st == MXFFT_OK && mxk::is_mx_mode(pl->mode)) {   // MX intermediate: codes and block exponents
             st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n / 2);
             if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_exps, (size_t)max_batch * n * (n / pl->cb));
             pl->fused = mxk::fast_fused_stats(pl->mode, n);

@@ -29,8 +29,9 @@ struct alignas(16) StatPart {
 // bit-identical to the row pass of the input scaled by 2^k (checked for the
 // exponents both before and after adding k): no E8M0 clamp at +-127, and
 // every FP32 value of the pass stays zero or normal and finite (element
-// grids are at least 2^(E - 32) for either FP8 format, values below
-// 2^(E + 17)).
+// grids are at least 2^(E - 32) for every MX element format, values below
+// 2^(E + 17); the 6-bit formats' scale operand 2^(E + 12) at most stays in
+// range there too).
 constexpr int kEquivLo = -90, kEquivHi = 90;
 
 // Chunks per slice for a batch: enough work-groups to fill the chip, at

@@ -139,6 +139,13 @@ def test_plan_bytes_host():
     assert 1024 * 1024 * 4 <= h1k < 1024 * 1024 * 4 + 64 * 1024
     assert per(64, fmt="fp16") < 64 * 1024
     assert per(512, fmt="fp32") < 64 * 1024
+    # the 6-bit formats ride in 8-bit containers: the same buffers as MXFP8
+    # wherever they take the register-resident path (blocks of 16 and 32)
+    for n in (128, 256, 512, 1024):
+        for f6, f8 in (("e2m3", "e4m3"), ("e3m2", "e5m2")):
+            for blk in (16, 32):
+                assert mxfft.plan_bytes(n, 3, fmt=f6, block=blk) == mxfft.plan_bytes(n, 3, fmt=f8, block=blk), (n, f6, blk)
+    assert per(512, fmt="e2m3", block=8) < 64 * 1024        # blocks of 8: line kernels
     for bad in (dict(n=63), dict(n=64, max_batch=0), dict(n=64, block=48)):
         n, mb = bad.pop("n"), bad.pop("max_batch", 1)
         with pytest.raises(mxfft.MxfftError):

@@ -278,9 +278,15 @@ def test_fast_sizes_all_blocks(N, op, fmt, B):
 
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
 @pytest.mark.parametrize("fmt", ["e2m3", "e3m2"])
-@pytest.mark.parametrize("N,B", [(16, 8), (64, 32), (256, 16), (512, 32)])
-def test_fp6_forms(N, B, fmt, op):
-    """MXFP6 elements (E2M3, E3M2) on the generic line kernels: bit for bit."""
+@pytest.mark.parametrize("N,B,fast", [(16, 8, False), (64, 32, False), (128, 32, True), (256, 16, True),
+                                      (512, 32, True), (512, 8, False), (1024, 16, True)])
+def test_fp6_forms(N, B, fast, fmt, op):
+    """MXFP6 elements (E2M3, E3M2) bit for bit, on the generic line kernels and
+    on the register-resident passes (blocks of 16 and 32 at 128^2 .. 1024^2,
+    which carry the 6-bit codes in the 8-bit conversions)."""
+    pl = mxfft.Plan(N, 1, fmt=fmt, block=B)
+    assert pl.tuning()["fast"] == fast
+    pl.close()
     x = synth.kspace_batch(N, 3, 1, 2) if N >= 64 else synth.random_complex((3, N, N), seed=N, dist="lognormal")
     yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
     so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
@@ -329,6 +335,53 @@ def test_fast_sizes_prescale_paths(N, op):
     assert st == mxfft.OK and so == O.OK
     np.testing.assert_array_equal(kg, ko)
     assert_bitexact(yg, yo, "%d^2 mixed %s" % (N, op))
+
+
+@pytest.mark.parametrize("op", ["forward", "roundtrip"])
+@pytest.mark.parametrize("fmt,B", [("e2m3", 32), ("e3m2", 16)])
+@pytest.mark.parametrize("N", [512, 1024])
+def test_fp6_prescale_paths(N, fmt, B, op):
+    """MXFP6 on the passes that gather the prescale statistics on the row
+    pass: the mixed batch, slices inside and outside the window."""
+    x = mixed_512_batch(N)
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 mixed %s %s B=%d" % (N, op, fmt, B))
+
+
+def fp6_range_batch(N):
+    """Unprescaled slices whose block exponents reach past 127 - OFF (2^OFF
+    the factor between the 6-bit element and its 8-bit carrier): impulses near
+    2^125 (a plane wave of the same magnitude after each pass, no growth), two
+    impulses in one slice, a tiny impulse and tiny noise."""
+    x = np.zeros((6, N, N), np.complex64)
+    x[0, 3, 5] = np.float32(2.0 ** 125 * 1.3) - 1j * np.float32(2.0 ** 124)
+    x[1, N // 2, 7] = np.float32(-(2.0 ** 121) * 1.9)
+    x[2, 1, 1] = np.float32(2.0 ** 123)
+    x[2, N - 3, N // 3] = 1j * np.float32(2.0 ** 122 * 1.7)
+    x[3, 5, N - 2] = np.float32(2.0 ** 118) + 1j * np.float32(2.0 ** 117)
+    x[4, 9, 9] = np.float32(2.0 ** -120) - 1j * np.float32(2.0 ** -121)
+    rng = np.random.default_rng(N)
+    x[5] = ((rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * 1e-38).astype(np.complex64)
+    return x
+
+
+@pytest.mark.parametrize("fmt,B", [("e2m3", 32), ("e3m2", 16), ("e2m3", 8)])
+@pytest.mark.parametrize("N", [128, 512])
+def test_fp6_scale_range_edges(N, fmt, B):
+    """Blocks whose scale 2^(E + OFF) would leave the E8M0 range: encoded
+    with 2^E and the values times 2^-OFF, decoded times 2^OFF, on the
+    register-resident passes (B = 16, 32) and the line kernels (B = 8).  No
+    round trip: its unnormalised inverse of the forward overflows FP32 here."""
+    x = fp6_range_batch(N)
+    for op in ("forward", "inverse"):
+        yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B, flags=mxfft.NO_PRESCALE)
+        so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B, flags=O.NO_PRESCALE)
+        assert st == mxfft.OK and so == O.OK
+        assert np.isfinite(yo).all() and np.abs(yo).max() > 2.0 ** 124
+        assert_bitexact(yg, yo, "%d^2 %s %s B=%d range edges" % (N, op, fmt, B))
 
 
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
