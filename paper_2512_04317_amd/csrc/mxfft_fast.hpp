@@ -1135,9 +1135,13 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     }
 }
 
-// Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).
+// Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).  At 1024^2
+// the statistics form of blocks of 16 and 32 is held to 128 VGPRs, so that
+// four waves share a SIMD (the LDS allows as many) instead of two; a few
+// values live across the stages go to scratch.
 template <int F, int C, bool INV, int KIND>
-__global__ __launch_bounds__(THREADS) void k_row(FastArgs g)
+__global__ __launch_bounds__(THREADS)
+__attribute__((amdgpu_waves_per_eu((KIND == ROW_STATS && C >= 3 && LOGN == 10) ? 4 : 1, 8))) void k_row(FastArgs g)
 {
     __shared__ RowLds<F, C, KIND> L;
     row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
@@ -1365,9 +1369,13 @@ __device__ __forceinline__ float rss_add(float acc, float2 v, int kout)
 // epilogue: one work-group per (reconstruction, 16-column group) runs the
 // column pass of every coil slice of the reconstruction in coil order and
 // keeps the running sum of |T_c|^2 per value; only the FP32 image
-// (sum)^(1/2), [reconstruction][n][n], is written.
+// (sum)^(1/2), [reconstruction][n][n], is written.  At 1024^2 it is held to
+// 128 VGPRs: four waves per SIMD (as many as the LDS allows) instead of two,
+// at the cost of a few values in scratch; at the smaller sizes that trade
+// (three waves to four) does not pay.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(THREADS) void k_col_rss(FastArgs g)
+__global__ __launch_bounds__(THREADS)
+__attribute__((amdgpu_waves_per_eu(LOGN == 10 ? 4 : 1, 8))) void k_col_rss(FastArgs g)
 {
     __shared__ ColLds<F, C> L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
