@@ -487,6 +487,13 @@ constexpr int LPW = 64 / LPL;       // lines per wave (4 at n = 512)
 constexpr int LINES = 16;           // lines per work-group
 constexpr int WAVES = LINES / LPW;  // waves per work-group (4 at n = 512)
 constexpr int THREADS = 64 * WAVES;
+// Waves per SIMD the register allocation of a kernel aims at (1: the
+// compiler's own choice).  At 1024^2 the LDS of a 512-thread work-group lets
+// two groups share a CU, four waves per SIMD; the kernels that take more
+// than 128 VGPRs there would run two, and holding them to 128 (a few values
+// go to scratch) measured 7 to 22 % faster.  At the smaller sizes the same
+// limit takes three waves to four and measured slower.
+constexpr int waves_target(bool over_128_vgprs) { return (LOGN == 10 && over_128_vgprs) ? 4 : 1; }
 static_assert(LOGN >= 7 && LOGN <= 10, "register-resident passes for n = 128 .. 1024");
 
 // Layouts for MX blocks of 2^C butterflies (1 <= C <= 4).
@@ -1135,13 +1142,11 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     }
 }
 
-// Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).  At 1024^2
-// the statistics form of blocks of 16 and 32 is held to 128 VGPRs, so that
-// four waves share a SIMD (the LDS allows as many) instead of two; a few
-// values live across the stages go to scratch.
+// Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).  Above 128
+// VGPRs at 1024^2: the statistics form of blocks of 16 and 32, and BF16.
 template <int F, int C, bool INV, int KIND>
 __global__ __launch_bounds__(THREADS)
-__attribute__((amdgpu_waves_per_eu((KIND == ROW_STATS && C >= 3 && LOGN == 10) ? 4 : 1, 8))) void k_row(FastArgs g)
+__attribute__((amdgpu_waves_per_eu(waves_target((KIND == ROW_STATS && C >= 3) || F == BF16), 8))) void k_row(FastArgs g)
 {
     __shared__ RowLds<F, C, KIND> L;
     row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
@@ -1304,7 +1309,8 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
 
 // Column pass.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(THREADS) void k_col(FastArgs g)
+__global__ __launch_bounds__(THREADS)
+__attribute__((amdgpu_waves_per_eu(waves_target(F == BF16), 8))) void k_col(FastArgs g)
 {
     __shared__ ColLds<F, C> L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1369,13 +1375,11 @@ __device__ __forceinline__ float rss_add(float acc, float2 v, int kout)
 // epilogue: one work-group per (reconstruction, 16-column group) runs the
 // column pass of every coil slice of the reconstruction in coil order and
 // keeps the running sum of |T_c|^2 per value; only the FP32 image
-// (sum)^(1/2), [reconstruction][n][n], is written.  At 1024^2 it is held to
-// 128 VGPRs: four waves per SIMD (as many as the LDS allows) instead of two,
-// at the cost of a few values in scratch; at the smaller sizes that trade
-// (three waves to four) does not pay.
+// (sum)^(1/2), [reconstruction][n][n], is written.  Above 128 VGPRs in
+// every form.
 template <int F, int C, bool INV>
 __global__ __launch_bounds__(THREADS)
-__attribute__((amdgpu_waves_per_eu(LOGN == 10 ? 4 : 1, 8))) void k_col_rss(FastArgs g)
+__attribute__((amdgpu_waves_per_eu(waves_target(true), 8))) void k_col_rss(FastArgs g)
 {
     __shared__ ColLds<F, C> L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
