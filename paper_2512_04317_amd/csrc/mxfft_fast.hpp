@@ -902,7 +902,19 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                 v[2 * I + 1] = make_float2(ldexpf(q.z, kin), ldexpf(q.w, kin));
             }
         });
-        uint32_t mcb = 0;   // bits of the largest |part| (statistics)
+        // statistics: bits of the largest block maximum (= largest |part|), of
+        // the smallest nonzero one (minus one, so that zero wraps to the top),
+        // and whether a block was all zero.  block_exp is monotone in the
+        // maximum of a nonzero block and 0 for a zero block, so these give the
+        // exponent range of the input blocks (tracking each E instead holds
+        // about 20 more VGPRs over the stages)
+        uint32_t mcb = 0, mnz1 = 0xFFFFFFFFu;
+        bool zblk = false;
+        auto track = [&](uint32_t ab) {
+            mcb = max(mcb, ab);
+            mnz1 = min(mnz1, ab - 1u);
+            zblk |= ab == 0u;
+        };
         if constexpr (ST) {
             // Alg. 1 statistics of the unscaled input: |x|^2 in FP64 (both squares
             // exact, one rounding), its maximum, a non-finite check (the sum of
@@ -936,17 +948,22 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             sfor<P / 2>([&](auto I) {
                 float am;
                 const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);
-                if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
+                if constexpr (ST) { (void)E; track(__float_as_uint(am)); }
             });
         } else {
             static_assert(CB == 4 * LPL, "a block spans two loads of every lane of its line");
             sfor<P / 4>([&](auto H) {
                 float am;
                 const int E = mx_requant_quad<F, LPL>(v[4 * H], v[4 * H + 1], v[4 * H + 2], v[4 * H + 3], am);
-                if constexpr (ST) { er.add(E); mcb = max(mcb, __float_as_uint(am)); }
+                if constexpr (ST) { (void)E; track(__float_as_uint(am)); }
             });
         }
         if constexpr (ST) {
+            if (mnz1 != 0xFFFFFFFFu) {
+                er.add(mxd::block_exp<F>(mnz1 + 1u));
+                er.add(mxd::block_exp<F>(mcb));
+            }
+            if (zblk) er.add(0);
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
             // the tile's histogram to its part (the planes are needed next):
