@@ -1192,30 +1192,34 @@ struct alignas(16) ColLds {
 // Column pass of the 16-column group cb16 of one slice up to its last stage:
 // the input tile, its decode into the first layout, the stages (and, for
 // BF16, the exact redo); a holds the unscaled results in the last layout.
-template <int F, int C, bool INV>
+// LOOP: called once per coil inside the combined pass's coil loop.
+template <int F, int C, bool INV, bool LOOP = false>
 __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16, float2 (&a)[P], ColLds<F, C>& L)
 {
     constexpr int CB = 1 << C;
     constexpr int NRB = ColLds<F, C>::NRB;
     float* s_plane = L.plane;
     uint8_t* s_ex = L.ex;
-    // an opaque copy of the thread index: the lane-dependent addresses are
-    // then recomputed per coil in the combined pass instead of being hoisted
-    // out of its coil loop (which would hold them all in registers)
+    // in the coil loop, an opaque copy of the thread index: the lane-dependent
+    // addresses are then recomputed per coil instead of being hoisted out of
+    // the loop (which would hold them all in registers)
     int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
+    if constexpr (LOOP) asm volatile("" : "+v"(tid));
     const int wave = tid >> 6, lane = tid & 63;
     const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
     const int cl = wave * LPW + line;                  // column within the work-group
     float* plane = s_plane + wave * WPL + line_base(line);
     const int rm = (int)(__brev((unsigned)m) >> (32 - LOG_LPL));   // m bit-reversed
-    // opaque copies of the table pointers: in the coil loop of the combined
-    // pass the twiddle loads then stay inside the loop (all of them hoisted
-    // out of it would need more registers than a lane has)
-    const float2* twp = g.tw;
-    const int32_t* txp = g.tw_exp;
-    const uint32_t* t16p = g.tw16;
-    asm volatile("" : "+s"(twp), "+s"(txp), "+s"(t16p));
+    // in the coil loop, the table pointers plus an opaque zero: the twiddle
+    // loads then stay inside the loop (all of them hoisted out of it would
+    // need more registers than a lane has).  An offset rather than an opaque
+    // pointer keeps the pointers' global address space known (global, not
+    // flat, loads)
+    size_t zo = 0;
+    if constexpr (LOOP) asm volatile("" : "+s"(zo));
+    const float2* twp = g.tw + zo;
+    const int32_t* txp = g.tw_exp + zo;
+    const uint32_t* t16p = g.tw16 + zo;
     Tw t{twp, txp, g.tw_off, t16p};
     float2* tile = (float2*)s_plane;                   // N/2 x 16 complex
     // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
@@ -1409,7 +1413,7 @@ __attribute__((amdgpu_waves_per_eu(waves_target(true), 8))) void k_col_rss(FastA
         if (c > 0) __syncthreads();                    // the planes are free again
         const int slice = recon * g.coils + c;
         float2 a[P];
-        col_lines<F, C, INV>(g, slice, cb16, a, L);
+        col_lines<F, C, INV, true>(g, slice, cb16, a, L);
         const int kout = g.kout_mul * slice_k(g, slice) + g.kout_add;
         sfor<P>([&](auto O) { acc[O] = rss_add<F>(acc[O], a[O], kout); });
     }
