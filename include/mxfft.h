@@ -41,8 +41,9 @@ extern "C" {
  * block size is ignored for them.  FP32 is the plain single-precision form of
  * the same radix-2 FFT (the comparison baseline, no quantisation).  E2M3 and
  * E3M2 are the OCP 6-bit elements of MXFP6 (no infinities or NaN), which the
- * paper evaluates beside MXFP8 (Sec. 3); they run on the generic line
- * kernels at every size. */
+ * paper evaluates beside MXFP8 (Sec. 3); blocks of 16 and 32 at n = 128..1024
+ * run on the register-resident passes (the 6-bit codes held in 8-bit ones),
+ * other blocks and sizes on the generic line kernels. */
 typedef enum {
     MXFFT_E4M3 = 0,
     MXFFT_E5M2 = 1,
@@ -150,7 +151,8 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32
  * epilogue (may be `in`, which is then overwritten); MXFFT_EINVAL when it is
  * needed and NULL; unused (may be NULL) otherwise.  k_out: int32[recon *
  * coils] or NULL.  recon * coils <= max_batch.  Plans on the register-resident
- * passes (n = 128..1024 with MX B = 4..32 or FP16/BF16, and FP32 at n = 512)
+ * passes (n = 128..1024 with MXFP8 B = 4..32, MXFP6 B = 16 or 32, or FP16/BF16,
+ * and FP32 at n = 512)
  * fuse the combine; the others (generic line kernels) write the per-coil
  * results to work and combine them in a separate kernel with the same
  * arithmetic. */
@@ -197,8 +199,9 @@ mxfft_status mxfft_plan_kernel_times(mxfft_plan_t plan, mxfft_kernel_time* out, 
 uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
 
 /* ---- Launch tuning ------------------------------------------------------
- * Sizes and formats without register-resident passes (every n other than 512,
- * and B in {2, 64, 128} at 512) run the generic line kernels: one work-group
+ * Sizes and formats without register-resident passes (n below 128 or above
+ * 1024, MX blocks of 2, 64 and 128, MXFP6 blocks other than 16 and 32, FP32 at
+ * every n but 512) run the generic line kernels: one work-group
  * holds `lines` whole lines of a pass in LDS, one thread per butterfly.  The
  * best `lines` depends on n, the format and the GPU, so it is measured. */
 typedef struct {
