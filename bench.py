@@ -260,7 +260,7 @@ def rss_quality(args, torch, mxfft, x, xd, N, recon=8, coils=16):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1). Slices are independent, so a "
+        print("bench.py: the transform runs on one GPU only (--gpus 1). Slices are independent, so a "
               "batch would shard across GPUs with no communication; no multi-GPU path is built.",
               file=sys.stderr)
         sys.exit(2)
