@@ -199,9 +199,15 @@ def test_nonfinite_and_range_errors():
     assert O.prescale(x[0], k_min=121) == (O.ERANGE, O.INT32_MIN)
 
 
-def test_in_place_batch_independence_determinism():
-    x = synth.kspace_batch(128, 2, 2, 3)
-    plan = mxfft.Plan(128, 8, fmt="e4m3", block=32)
+@pytest.mark.parametrize("N,kw", [(128, dict(fmt="e4m3", block=32)), (512, dict(fmt="e2m3", block=32)),
+                                  (1024, dict(fmt="e3m2", block=16)), (512, dict(fmt="bf16")),
+                                  (512, dict(fmt="fp32", flags=mxfft.NO_PRESCALE))])
+def test_in_place_batch_independence_determinism(N, kw):
+    """Repeated calls give the same bits; in place (out = in) equals out of
+    place; a slice transformed alone equals the same slice in a batch."""
+    x = synth.kspace_batch(N, 2, 2, 3)
+    print("in-place / batch case N=%d %s" % (N, kw), flush=True)
+    plan = mxfft.Plan(N, 8, **kw)
     xd = torch.from_numpy(x).cuda()
     y1, k1 = plan.forward(xd)
     y2, k2 = plan.forward(xd)
