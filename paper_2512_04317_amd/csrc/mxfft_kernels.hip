@@ -143,9 +143,10 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
     const float2* xs = x + (size_t)slice * nn;
     const StatPart* pt = parts + (size_t)slice * chunks;
 
+    __shared__ uint32_t s_wave[4];
     if (tid == 0) {
         s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0;
-        s_emin = 0; s_emax = 0;
+        s_emin = 0; s_emax = 0; s_bin_lo = -1; s_bin_hi = -1;
     }
     for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
     __syncthreads();
@@ -177,19 +178,40 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
     long long ri = (long long)floor(pos);
     if (n && ri > (long long)n - 1) ri = (long long)n - 1;
     const double fr = pos - (double)ri;
-    if (tid == 0 && n && !s_nonfin) {
-        // binades holding the order statistics ri and ri + 1 (S[n] := S[n-1])
+    if (n && !s_nonfin) {
+        // binades holding the order statistics ri and ri + 1 (S[n] := S[n-1]):
+        // the bin b with (count below b) <= r < (count up to b).  Each thread
+        // owns BPT consecutive bins; their counts are prefix-summed over the
+        // work-group (wave scans, then the four wave totals)
+        static_assert(kStatsBins <= 2 * 256, "two bins per thread");
+        constexpr int BPT = 2;
         const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
-        long long cum = 0;
-        int blo = -1, bhi = -1;
-        for (int b = 0; b < kStatsBins; b++) {
-            cum += hist[b];
-            if (blo < 0 && cum > ri) blo = b;
-            if (bhi < 0 && cum > r1) { bhi = b; break; }
+        const int b0 = tid * BPT;
+        uint32_t h[BPT], mine = 0;
+        for (int j = 0; j < BPT; j++) {
+            h[j] = (b0 + j < kStatsBins) ? hist[b0 + j] : 0u;
+            mine += h[j];
         }
-        s_bin_lo = blo;
-        s_bin_hi = bhi;
-        s_refine = (blo != bhi) && (fr != 0.0);
+        uint32_t incl = mine;                        // inclusive scan within the wave
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t below = incl - mine;                // counts of all lower bins
+        for (int w = 0; w < wave; w++) below += s_wave[w];
+        long long cum = below;
+        for (int j = 0; j < BPT; j++) {
+            if (cum <= ri && ri < cum + (long long)h[j]) s_bin_lo = b0 + j;
+            if (cum <= r1 && r1 < cum + (long long)h[j]) s_bin_hi = b0 + j;
+            cum += h[j];
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && n && !s_nonfin) {
+        s_refine = (s_bin_lo != s_bin_hi) && (fr != 0.0);
         s_lo_max = 0;
         s_hi_min = ~0ull;
     }
