@@ -74,6 +74,8 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
     g.tw16 = p.tw16;
     g.rss = p.rss;
     g.coils = p.coils;
+    // the redo pass strides over its list: tiles of at most 64 slices in the grid
+    if (row && kind == ROW_FIX && batch > 64) batch = 64;
     switch (mode * 4096 + n) {
     case MODE_E4M3 * 4096 + 512: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
     case MODE_E5M2 * 4096 + 512: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);

@@ -1169,15 +1169,19 @@ __attribute__((amdgpu_waves_per_eu(waves_target((KIND == ROW_STATS && C >= 3) ||
     row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
 }
 
-// Row pass over the slices in fix_list only: one work-group per (list entry,
-// tile) of a batch-sized grid; entries past the list length return at once.
+// Row pass over the slices in fix_list only: the work-groups stride over the
+// (list entry, tile) pairs, so a grid of a few slices' tiles serves any list
+// length and an empty list costs one read per work-group.
 template <int F, int C, bool INV>
 __global__ __launch_bounds__(THREADS) void k_row_fix(FastArgs g)
 {
     __shared__ RowLds<F, C, ROW_FIX> L;
-    const int j = blockIdx.x / (N / LINES), rb = blockIdx.x % (N / LINES);
-    if (j >= *g.fix_count) return;
-    row_tile<F, C, INV, ROW_FIX>(g, g.fix_list[j], rb, L);
+    constexpr int TILES = N / LINES;
+    const int total = *g.fix_count * TILES;            // the same for every thread
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        if (e != (int)blockIdx.x) __syncthreads();     // the previous tile is done with the LDS
+        row_tile<F, C, INV, ROW_FIX>(g, g.fix_list[e / TILES], e % TILES, L);
+    }
 }
 
 // Shared memory of the column pass: the exchange planes (which also hold the

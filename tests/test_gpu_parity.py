@@ -438,6 +438,20 @@ def test_n512_prescale_limits_and_errors():
     assert st == mxfft.ERANGE and O.prescale(ks[0], k_min=kmax_ok + 1)[0] == O.ERANGE
 
 
+def test_n512_redo_list_longer_than_grid():
+    """80 slices pushed outside the equivariance window (k_min = 100: the
+    largest block exponents, about 2^9 above the scale of the data, plus k
+    pass 90): the redo pass's work-groups (64 slices' tiles) stride over the
+    longer list."""
+    x = synth.kspace_batch(512, 3, 5, 16)
+    yg, kg, st = gpu_run(x, fmt="e4m3", block=32, k_min=100)
+    so, yo, ko = orc_run(x, fmt="e4m3", block=32, k_min=100)
+    assert st == mxfft.OK and so == O.OK and x.shape[0] == 80 and (kg == 100).all()
+    assert np.isfinite(yo).all()
+    np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "512^2 redo list of 80 slices")
+
+
 @pytest.mark.parametrize("fmt", ["fp16", "bf16"])
 @pytest.mark.parametrize("N", [2, 8, 32, 64, 128, 256, 512, 1024])
 def test_16bit_forms(fmt, N):
