@@ -312,6 +312,13 @@ class Plan:
             lib().mxfft_plan_destroy(self.handle)
             self.handle = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()
@@ -404,6 +411,13 @@ class Batch:
             lib().mxfft_batch_destroy(self.handle)
             self.handle = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()
@@ -481,6 +495,13 @@ class Server:
         if getattr(self, "handle", None):
             lib().mxfft_serve_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -222,6 +222,16 @@ def test_in_place_batch_independence_determinism(N, kw):
     plan.close()
 
 
+def test_plan_as_context_manager():
+    """A plan used in a with-block works inside it and is released at its end."""
+    x = torch.from_numpy(synth.kspace_batch(64, 1, 1, 2)).cuda()
+    with mxfft.Plan(64, 2, fmt="e4m3", block=32) as plan:
+        y, k = plan.forward(x)
+        torch.cuda.synchronize()
+        assert plan.last_status() == mxfft.OK and plan.handle
+    assert plan.handle is None
+
+
 @pytest.fixture(scope="module")
 def full_workload():
     w = synth.WORKLOADS["kspace512_64x16"]
