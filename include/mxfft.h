@@ -283,7 +283,9 @@ mxfft_status mxfft_batch_destroy(mxfft_batch_t b);
  * the device memory of the plans it holds stays within the budget: plans
  * (tables and workspace) are pooled by (n, parameters, batch capacity: the
  * coil count rounded up to a power of two) and reused; idle plans are evicted,
- * least recently used first, when a new one would exceed the budget.  Up to
+ * least recently used first, when a new one would exceed the budget.  A
+ * planner thread creates and frees the plans, so admission of later requests
+ * and completion of running ones never wait on an allocation or a free.  Up to
  * `slots` requests run at once, each on its own stream, so transfers of
  * results and the kernels of different requests overlap.  A request's input
  * and output stay caller-owned (pre-staged device buffers); each request is
@@ -300,6 +302,13 @@ typedef struct {
     int32_t coils;        /* slices in the request, 1..65535 */
     int32_t op;           /* 0 forward, 1 inverse (own prescale), 2 round trip */
     mxfft_params params;  /* format, block, prescale parameters, flags */
+    void* ready;          /* hipEvent_t or NULL.  The request's stream waits on
+                             it before its first kernel: record it on the
+                             stream that produces `in` (and last used `out`),
+                             after that work.  NULL: the caller guarantees the
+                             input is complete on the device at submission.
+                             The event must stay valid until the ticket is
+                             answered. */
 } mxfft_request;
 
 typedef struct {
@@ -325,7 +334,11 @@ mxfft_status mxfft_serve_create(mxfft_server_t* out, uint64_t hbm_budget_bytes, 
 
 /* Queue a request (non-blocking; any thread).  *ticket identifies it.
  * MXFFT_EINVAL for bad arguments and MXFFT_EBUDGET when its plan alone would
- * exceed the budget (counted as rejected; nothing is queued). */
+ * exceed the budget (counted as rejected; nothing is queued).  The request
+ * runs on a stream of the server, not on the caller's: its input must be
+ * complete when its `ready` event fires (or at submission without one), and
+ * in, out and k_out must stay allocated and untouched by other work until the
+ * ticket is answered by mxfft_serve_wait or mxfft_serve_poll. */
 mxfft_status mxfft_serve_submit(mxfft_server_t srv, const mxfft_request* req, uint64_t* ticket);
 
 /* Block until the request is done and fill *res; a ticket is answered once

@@ -545,6 +545,8 @@ namespace mxk {
 
 const int32_t* plan_status_words(mxfft_plan_t pl) { return pl->d_status; }
 
+void plan_release_idle(mxfft_plan_t pl) { release(pl); }
+
 bool plan_has_status(mxfft_plan_t pl) { return !(pl->p.flags & MXFFT_NO_PRESCALE); }
 
 }  // namespace mxk

@@ -129,6 +129,10 @@ hipError_t launch_ssim(const float* x, const float* y, int n, int count, double*
 // Synthetic finite data (tuning): count complex values, both parts in [-1, 1).
 hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s);
 
+// Release a plan whose work has completed (the caller has seen its last
+// event), without the device-wide synchronisation of mxfft_plan_destroy.
+void plan_release_idle(mxfft_plan_s* pl);
+
 // Device status words of a plan (one int32 per slice of its last call, written
 // by the prescale statistics), and whether its calls write them.
 const int32_t* plan_status_words(mxfft_plan_s* pl);

@@ -23,7 +23,11 @@ struct Entry {
     double ms = 0.0;
 };
 
-bool is_mx(int format) { return format == MXFFT_E4M3 || format == MXFFT_E5M2; }
+// every MX element format (MXFP8 and MXFP6) keys its cache entries by block size
+bool is_mx(int format)
+{
+    return format == MXFFT_E4M3 || format == MXFFT_E5M2 || format == MXFFT_E2M3 || format == MXFFT_E3M2;
+}
 
 // Value of "key": in one line; false when absent or malformed.
 bool find_num(const std::string& line, const char* key, double* v)

@@ -6,6 +6,7 @@ HIP kernels.  Tensors are torch complex64 CUDA tensors of shape [batch, n, n]
 """
 import ctypes
 import os
+import threading
 
 import torch
 
@@ -52,7 +53,8 @@ class Group(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("k_out", ctypes.c_void_p),
-                ("n", ctypes.c_int32), ("coils", ctypes.c_int32), ("op", ctypes.c_int32), ("params", Params)]
+                ("n", ctypes.c_int32), ("coils", ctypes.c_int32), ("op", ctypes.c_int32), ("params", Params),
+                ("ready", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -436,7 +438,14 @@ def plan_bytes(n, max_batch, **params):
 
 
 class Server:
-    """A request server (mxfft_serve_*): submit() from any thread, wait()."""
+    """A request server (mxfft_serve_*): submit() from any thread, wait().
+
+    A request runs on one of the server's streams.  submit() records an event
+    on the submitting stream (the current torch stream unless one is given)
+    that the request waits on, so work queued there before the call, such as
+    writing x, is complete first; the tensors are kept referenced until the
+    ticket is answered, so the caching allocator cannot hand their memory to
+    other work while the request may still use it."""
 
     def __init__(self, budget_bytes, slots=4):
         h = ctypes.c_void_p()
@@ -444,8 +453,10 @@ class Server:
         if st != OK:
             raise MxfftError(st, "mxfft_serve_create")
         self.handle = h
+        self._held = {}
+        self._held_lock = threading.Lock()
 
-    def submit(self, x, out, k_out=None, op=FORWARD, **params):
+    def submit(self, x, out, k_out=None, op=FORWARD, stream=None, **params):
         """Queue one request over x = [coils, n, n]; returns its ticket.  Raises
         MxfftError (status EBUDGET when its plan alone exceeds the budget)."""
         if not (x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous() and x.dim() == 3):
@@ -454,13 +465,22 @@ class Server:
             raise ValueError("out must be a contiguous complex64 CUDA tensor shaped like x")
         if k_out is not None and not (k_out.is_cuda and k_out.dtype == torch.int32 and k_out.numel() >= x.shape[0]):
             raise ValueError("k_out must be an int32 CUDA tensor with >= coils entries")
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream() if stream is None else stream)
         r = Request(x.data_ptr(), out.data_ptr(), None if k_out is None else k_out.data_ptr(),
-                    int(x.shape[1]), int(x.shape[0]), int(op), make_params(**params))
+                    int(x.shape[1]), int(x.shape[0]), int(op), make_params(**params), ready.cuda_event)
         t = ctypes.c_uint64()
-        st = lib().mxfft_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        with self._held_lock:
+            st = lib().mxfft_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+            if st == OK:
+                self._held[t.value] = (x, out, k_out, ready)
         if st != OK:
             raise MxfftError(st, "mxfft_serve_submit")
         return t.value
+
+    def _release(self, ticket):
+        with self._held_lock:
+            self._held.pop(int(ticket), None)
 
     @staticmethod
     def _res(r):
@@ -472,6 +492,7 @@ class Server:
         st = lib().mxfft_serve_wait(self.handle, int(ticket), ctypes.byref(r))
         if st != OK:
             raise MxfftError(st, "mxfft_serve_wait")
+        self._release(ticket)
         return self._res(r)
 
     def poll(self, ticket):
@@ -482,6 +503,7 @@ class Server:
             return None
         if st != OK:
             raise MxfftError(st, "mxfft_serve_poll")
+        self._release(ticket)
         return self._res(r)
 
     def stats(self):
@@ -493,8 +515,9 @@ class Server:
 
     def close(self):
         if getattr(self, "handle", None):
-            lib().mxfft_serve_destroy(self.handle)
+            lib().mxfft_serve_destroy(self.handle)   # finishes every request first
             self.handle = None
+            self._held.clear()
 
     def __enter__(self):
         return self

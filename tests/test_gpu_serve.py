@@ -1,6 +1,9 @@
-"""Serving on the GPU, through the C ABI: results bit-identical alone and in a
-mixed stream of requests, admission under a device-memory budget, and a
-request with non-finite input failing alone (its neighbours unaffected)."""
+"""Serving on the GPU, through the C ABI: results bit-identical to the oracle
+and to a single plan, alone and in a mixed stream of requests; plans never
+shared across block sizes (MXFP8 and MXFP6); admission under a device-memory
+budget; a request with non-finite input failing alone (its neighbours
+unaffected)."""
+import os
 import threading
 
 import numpy as np
@@ -8,10 +11,23 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+import oracle as O  # noqa: E402
 from paper_2512_04317_amd import mxfft, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 GiB = 1 << 30
+NTHREADS = min(16, os.cpu_count() or 1)
+ORC_FMT = {"e4m3": (O.MODE_MX, O.E4M3), "e5m2": (O.MODE_MX, O.E5M2), "e2m3": (O.MODE_MX, O.E2M3),
+           "e3m2": (O.MODE_MX, O.E3M2), "fp16": (O.MODE_FP16, O.E4M3), "bf16": (O.MODE_BF16, O.E4M3)}
+
+
+def oracle_of(x, op, fmt="e4m3", block=32):
+    """The oracle's result for a request (default prescale parameters)."""
+    mode, f = ORC_FMT[fmt]
+    opcode = {mxfft.FORWARD: O.FORWARD, mxfft.INVERSE: O.INVERSE, mxfft.ROUNDTRIP: O.ROUNDTRIP}[op]
+    st, y, k = O.transform(x.cpu().numpy(), op=opcode, mode=mode, fmt=f, B=block, nthreads=NTHREADS)
+    assert st == O.OK
+    return y, (None if op == mxfft.INVERSE else k)
 
 
 def bits(a):
@@ -75,10 +91,14 @@ def test_serve_mixed_requests_match_alone():
     for i, ((x, op, params), r) in enumerate(zip(reqs, results)):
         assert r["status"] == mxfft.OK, (i, r)
         assert r["t_submit_ms"] <= r["t_start_ms"] <= r["t_done_ms"]
+        got = bits(outs[i].cpu().numpy())
         y, k = alone(x, op, **params)
-        assert np.array_equal(bits(outs[i].cpu().numpy()), bits(y)), "request %d (%s)" % (i, params)
+        assert np.array_equal(got, bits(y)), "request %d (%s)" % (i, params)
+        yo, ko = oracle_of(x, op, **params)
+        assert np.array_equal(got, bits(yo)), "request %d (%s) vs oracle" % (i, params)
         if k is not None:
             assert np.array_equal(ks[i].cpu().numpy(), k)
+            assert np.array_equal(ks[i].cpu().numpy(), ko)
     with pytest.raises(mxfft.MxfftError):
         srv.wait(tickets[0])                   # answered once
     srv.close()
@@ -127,4 +147,47 @@ def test_serve_nonfinite_request_fails_alone():
     for i in (0, 2):
         y, _ = alone(xs[i], mxfft.FORWARD, fmt="e4m3", block=32)
         assert np.array_equal(bits(outs[i].cpu().numpy()), bits(y))
+    srv.close()
+
+
+@pytest.mark.parametrize("fmt,blocks", [("e2m3", (16, 32)), ("e3m2", (8, 32)), ("e4m3", (16, 32))])
+def test_serve_plans_keep_their_block_size(fmt, blocks):
+    """Requests of one MX element format that differ only in the block size
+    (same n, coil count and prescale parameters) each get a plan of their
+    own block size: the second arrives when the first request's plan is idle
+    in the pool, and must not be handed it.  Both results against the oracle,
+    bit for bit (MXFP6 blocks of 8 run on the generic kernels, 16 and 32 on
+    the register-resident passes)."""
+    srv = mxfft.Server(4 * GiB, slots=2)
+    for b in blocks + blocks[:1]:
+        x = torch.from_numpy(synth.random_complex((2, 128, 128), seed=40 + b, dist="lognormal")).cuda()
+        out = torch.empty_like(x)
+        k = torch.empty(2, dtype=torch.int32, device="cuda")
+        print("serve case: %s B=%d" % (fmt, b), flush=True)
+        r = srv.wait(srv.submit(x, out, k, op=mxfft.FORWARD, fmt=fmt, block=b))
+        assert r["status"] == mxfft.OK
+        yo, ko = oracle_of(x, mxfft.FORWARD, fmt=fmt, block=b)
+        assert np.array_equal(bits(out.cpu().numpy()), bits(yo)), "%s B=%d" % (fmt, b)
+        assert np.array_equal(k.cpu().numpy(), ko)
+    st = srv.stats()
+    # one plan per block size; the repeat of the first block reuses its plan
+    assert st["plans_created"] == len(blocks) and st["completed"] == len(blocks) + 1
+    srv.close()
+
+
+def test_serve_waits_for_input_written_on_the_submitting_stream():
+    """The input is produced by a kernel still queued on the submitting torch
+    stream when the request is submitted; the request runs after it (its
+    stream waits on the event submit() records) and matches the oracle."""
+    x0 = torch.from_numpy(synth.random_complex((4, 256, 256), seed=5, dist="lognormal")).cuda()
+    x = torch.empty_like(x0)
+    out = torch.empty_like(x0)
+    srv = mxfft.Server(4 * GiB, slots=2)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(20_000_000)      # keeps the stream busy for a while before the copy
+    x.copy_(x0)
+    r = srv.wait(srv.submit(x, out, op=mxfft.FORWARD, fmt="e4m3", block=32))
+    assert r["status"] == mxfft.OK
+    yo, _ = oracle_of(x0, mxfft.FORWARD)
+    assert np.array_equal(bits(out.cpu().numpy()), bits(yo))
     srv.close()
