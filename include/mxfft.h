@@ -61,7 +61,7 @@ typedef enum {
     MXFFT_EHIP = -3,          /* a HIP runtime call failed */
     MXFFT_ENONFINITE = -4,    /* a slice holds Inf or NaN (found on the device) */
     MXFFT_ERANGE = -5,        /* the prescale would overflow FP32 (found on the device) */
-    MXFFT_EBUDGET = -6,       /* reserved */
+    MXFFT_EBUDGET = -6,       /* over a memory budget (a server's, or the static workspace) */
     MXFFT_EBUSY = -7,         /* reserved */
     MXFFT_EUNSUPPORTED = -8   /* valid for the method but not built in this library */
 } mxfft_status;
@@ -120,6 +120,31 @@ mxfft_status mxfft_plan_destroy(mxfft_plan_t plan);
  * 1 <= batch <= max_batch. */
 mxfft_status mxfft_forward(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
                            int32_t* k_out, void* stream);
+
+/* Forward transform without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and status words as
+ * mxfft_forward, bit for bit, but every buffer the kernels write besides `out`
+ * and `k_out` (the MX or 16-bit intermediate of the register-resident passes,
+ * the prescale statistics and exponents, the status words, the redo list) is
+ * taken from one static device array of MXFFT_STATIC_SCRATCH_BYTES per GPU,
+ * which the library holds from its first use on a device until the process
+ * ends.  The plan supplies only its twiddle tables, so batch may exceed the
+ * plan's max_batch (1 <= batch <= 65535) as long as that workspace fits:
+ * MXFFT_EBUDGET otherwise (nothing is enqueued).  It is about 0.55 MiB per
+ * slice at n = 512 and 2.2 MiB at n = 1024 for MXFP8 B = 32 (113 and 28 slices),
+ * 1 MiB per slice at n = 512 for FP16/BF16, and under 5 MiB in all for plans on
+ * the generic line kernels.  The plan must belong to the current device
+ * (MXFFT_EINVAL otherwise).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other plans, other host
+ * threads) race and give undefined results, so order them on one stream or
+ * with events.  The array keeps the last call's contents; the kernels rewrite
+ * every entry they read, and mxfft_plan_last_status() reads the status words
+ * from it, so query it before the next call of this kind on the device.  The
+ * first call on a device looks the array's address up (no allocation). */
+#define MXFFT_STATIC_SCRATCH_BYTES (64u << 20)
+mxfft_status mxfft_forward_static(mxfft_plan_t plan, const void* in, void* out, int32_t batch,
+                                  int32_t* k_out, void* stream);
 
 /* Inverse transform F^-1 (conjugate twiddles, same pipeline; Eq. 1).
  * k_in == NULL: the input is prescaled by its own Alg. 1 exponent k and the

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mxfft.h"
@@ -88,25 +89,22 @@ struct mxfft_plan_s {
     float2* d_tw = nullptr;
     int32_t* d_tw_exp = nullptr;
     int32_t tw_exp_off[mxk::kMaxLog2N + 2] = {};
-    mxk::StatPart* d_parts = nullptr;
-    int32_t* d_kp = nullptr;
-    int32_t* d_status = nullptr;
+    // per-call workspace for batches up to max_batch (the MX or 16-bit
+    // intermediate of the register-resident passes, statistics, exponents)
+    mxk::Workspace ws;
+    // status words written by the last call (the plan's own, or those of the
+    // shared static workspace after mxfft_forward_static)
+    const int32_t* last_status = nullptr;
     // generic line kernels: lines per work-group (0 = line_lines_per_group)
     int lines = 0;
     // sizing only: nothing is allocated or uploaded
     bool dry = false;
-    // register-resident path (n = 512): twiddles at [h + j], MX intermediate
+    // register-resident passes: twiddles at [h + j]
     bool fast = false;
     float2* d_twf = nullptr;
     uint32_t* d_tw16 = nullptr;      // FP16 form: the same twiddles as packed halves
-    uint32_t* d_codes = nullptr;
-    uint8_t* d_exps = nullptr;
-    // statistics gathered by the row pass (MX, n = 512): exponent offsets and
-    // the list of slices whose row pass is redone literally
+    // statistics gathered by the row pass (MX at 512^2 and 1024^2)
     bool fused = false;
-    int32_t* d_kadd = nullptr;
-    int32_t* d_fix_list = nullptr;
-    int32_t* d_fix_count = nullptr;
     uint64_t bytes = 0;
     int last_batch = 0;
     bool last_has_stats = false;
@@ -225,16 +223,16 @@ void release(mxfft_plan_s* pl)
     for (hipEvent_t e : pl->spare) (void)hipEventDestroy(e);
     (void)hipFree(pl->d_tw);
     (void)hipFree(pl->d_tw_exp);
-    (void)hipFree(pl->d_parts);
-    (void)hipFree(pl->d_kp);
-    (void)hipFree(pl->d_status);
     (void)hipFree(pl->d_twf);
     (void)hipFree(pl->d_tw16);
-    (void)hipFree(pl->d_codes);
-    (void)hipFree(pl->d_exps);
-    (void)hipFree(pl->d_kadd);
-    (void)hipFree(pl->d_fix_list);
-    (void)hipFree(pl->d_fix_count);
+    (void)hipFree(pl->ws.parts);
+    (void)hipFree(pl->ws.kp);
+    (void)hipFree(pl->ws.status);
+    (void)hipFree(pl->ws.codes);
+    (void)hipFree(pl->ws.exps);
+    (void)hipFree(pl->ws.kadd);
+    (void)hipFree(pl->ws.fix_list);
+    (void)hipFree(pl->ws.fix_count);
     delete pl;
 }
 
@@ -283,6 +281,34 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
     if (tw_exp.empty()) tw_exp.push_back(0);
 }
 
+// Element counts of the per-call workspace for batches of up to `batch`
+// slices (after pl->fast and pl->fused are set).
+struct WsCounts {
+    size_t parts, kp, status, codes, exps, kadd, fix_list, fix_count;
+};
+
+WsCounts ws_counts(const mxfft_plan_s* pl, int batch)
+{
+    const size_t n = (size_t)pl->n, b = (size_t)batch;
+    WsCounts c{};
+    // chunk statistics: the literal statistics pass, or one part per row tile
+    c.parts = mxk::stats_parts(pl->n, batch);
+    if (pl->fused) c.parts = std::max(c.parts, b * mxk::fast_row_tiles(pl->n));
+    c.kp = b;
+    c.status = b;
+    if (pl->fast && mxk::is_mx_mode(pl->mode)) {
+        // MX intermediate: codes (2 bytes per complex value) and block exponents
+        c.codes = b * n * n / 2;
+        c.exps = b * n * (n / (size_t)pl->cb);
+        c.kadd = b;
+        c.fix_list = b;
+        c.fix_count = 1;
+    }
+    if (pl->fast && (pl->mode == mxk::MODE_FP16 || pl->mode == mxk::MODE_BF16))
+        c.codes = b * n * n;   // one packed 16-bit pair per value
+    return c;
+}
+
 #define MX_TRY(expr)                          \
     do {                                      \
         mxfft_status st_ = (expr);            \
@@ -293,7 +319,8 @@ void build_twiddles(const mxfft_plan_s* pl, std::vector<float2>& tw, std::vector
 // register-resident path): ROW_PLAIN, ROW_STATS (unscaled, with the Alg. 1
 // statistics) or ROW_FIX (the listed slices only).  kadd: column pass offsets
 // of the stored exponents (after a ROW_STATS row pass), else nullptr.
-mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* kp, int32_t* k_out,
+mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, void* dst, const int32_t* kp,
+                  int32_t* k_out,
                   int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s,
                   int kind = mxk::ROW_PLAIN, const int32_t* kadd = nullptr, float* rss = nullptr,
                   int coils = 0)
@@ -304,12 +331,12 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
     LaunchTimer timer(pl, role, s);
     if (pl->fast) {
         // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
-        if (mxk::is_mx_mode(pl->mode) && (!pl->d_codes || !pl->d_exps)) return MXFFT_EHIP;
+        if (mxk::is_mx_mode(pl->mode) && (!w.codes || !w.exps)) return MXFFT_EHIP;
         mxk::FastPassArgs f{};
         f.src = (const float2*)src;
         f.dst = (float2*)dst;
-        f.codes = pl->d_codes;
-        f.exps = pl->d_exps;
+        f.codes = w.codes;
+        f.exps = w.exps;
         f.kp = kp;
         f.k_out = k_out;
         f.kin_mul = kin_mul;
@@ -321,10 +348,10 @@ mxfft_status pass(mxfft_plan_s* pl, const void* src, void* dst, const int32_t* k
         f.coils = coils;
         f.tw_exp = pl->d_tw_exp;
         for (int i = 0; i < 16; i++) f.tw_off[i] = i < mxk::kMaxLog2N + 2 ? pl->tw_exp_off[i] : 0;
-        f.parts = pl->d_parts;
+        f.parts = w.parts;
         f.kadd = kadd;
-        f.fix_list = pl->d_fix_list;
-        f.fix_count = pl->d_fix_count;
+        f.fix_list = w.fix_list;
+        f.fix_count = w.fix_count;
         return mxk::launch_fast(pl->mode, pl->n, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
                    ? MXFFT_OK
                    : MXFFT_EHIP;
@@ -365,11 +392,11 @@ mxk::PrescaleArgs prescale_args(const mxfft_plan_s* pl)
 }
 
 // Literal Alg. 1: a statistics pass over the input, then kp per slice.
-mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
+mxfft_status stats(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, int batch, hipStream_t s)
 {
     const mxk::PrescaleArgs pa = prescale_args(pl);
     LaunchTimer timer(pl, ROLE_STATS, s);
-    if (mxk::launch_stats((const float2*)in, pl->n, batch, pl->d_parts, pl->d_kp, pl->d_status, pa, s) != hipSuccess)
+    if (mxk::launch_stats((const float2*)in, pl->n, batch, w.parts, w.kp, w.status, pa, s) != hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
 }
@@ -383,19 +410,18 @@ mxfft_status stats(mxfft_plan_s* pl, const void* in, int batch, hipStream_t s)
 // [kEquivLo, kEquivHi], the stored intermediate is the scaled row pass with
 // its exponents offset by -kp, which the column pass adds back (kadd = kp);
 // any other slice gets the literal row pass of x * 2^kp (kadd = 0).
-mxfft_status row_with_stats(mxfft_plan_s* pl, const void* in, int32_t* k_out, int inverse, int batch,
-                            hipStream_t s)
+mxfft_status row_with_stats(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, int32_t* k_out, int inverse,
+                            int batch, hipStream_t s)
 {
-    MX_TRY(pass(pl, in, nullptr, nullptr, nullptr, 0, 0, 0, 0, inverse, batch, s, mxk::ROW_STATS));
+    MX_TRY(pass(pl, w, in, nullptr, nullptr, nullptr, 0, 0, 0, 0, inverse, batch, s, mxk::ROW_STATS));
     {
         const mxk::PrescaleArgs pa = prescale_args(pl);
         LaunchTimer timer(pl, ROLE_STATS, s);
-        if (mxk::launch_stats_final((const float2*)in, pl->n, batch, mxk::fast_row_tiles(pl->n), pl->d_parts,
-                                    pl->d_kp, pl->d_status, pa, pl->d_kadd, pl->d_fix_list, pl->d_fix_count,
-                                    k_out, s) != hipSuccess)
+        if (mxk::launch_stats_final((const float2*)in, pl->n, batch, mxk::fast_row_tiles(pl->n), w.parts, w.kp,
+                                    w.status, pa, w.kadd, w.fix_list, w.fix_count, k_out, s) != hipSuccess)
             return MXFFT_EHIP;
     }
-    return pass(pl, in, nullptr, pl->d_kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
+    return pass(pl, w, in, nullptr, w.kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
 }
 
 // Row pass kind of the round trip's inverse half: without the input encode
@@ -471,19 +497,22 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     std::vector<int32_t> tw_exp;
     build_twiddles(pl, tw, tw_exp, pl->tw_exp_off);
 
+    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
+    pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw_exp, tw_exp.size());
     {
-        // chunk statistics: the literal statistics pass, or one part per row tile
-        size_t parts = mxk::stats_parts(n, max_batch);
-        if (mxk::fast_supported(pl->mode, n, pl->cb) && mxk::fast_fused_stats(pl->mode, n))
-            parts = std::max(parts, (size_t)max_batch * mxk::fast_row_tiles(n));
-        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_parts, parts);
+        const WsCounts c = ws_counts(pl, max_batch);
+        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->ws.parts, c.parts);
+        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->ws.kp, c.kp);
+        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->ws.status, c.status);
+        if (st == MXFFT_OK && c.codes) st = dev_alloc(pl, &pl->ws.codes, c.codes);
+        if (st == MXFFT_OK && c.exps) st = dev_alloc(pl, &pl->ws.exps, c.exps);
+        if (st == MXFFT_OK && c.kadd) st = dev_alloc(pl, &pl->ws.kadd, c.kadd);
+        if (st == MXFFT_OK && c.fix_list) st = dev_alloc(pl, &pl->ws.fix_list, c.fix_list);
+        if (st == MXFFT_OK && c.fix_count) st = dev_alloc(pl, &pl->ws.fix_count, c.fix_count);
     }
-    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_kp, (size_t)max_batch);
-    if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_status, (size_t)max_batch);
-    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     std::vector<float2> twf;
     std::vector<uint32_t> tw16;
     if (st == MXFFT_OK && pl->fast) {
@@ -491,16 +520,6 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         for (long h = 1; h < n; h <<= 1)
             for (long j = 0; j < h; j++) twf[h + j] = tw[h - 1 + j];
         st = dev_alloc(pl, &pl->d_twf, twf.size());
-        if (st == MXFFT_OK && mxk::is_mx_mode(pl->mode)) {   // MX intermediate: codes and block exponents
-            st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n / 2);
-            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_exps, (size_t)max_batch * n * (n / pl->cb));
-            pl->fused = mxk::fast_fused_stats(pl->mode, n);
-            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_kadd, (size_t)max_batch);
-            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_list, (size_t)max_batch);
-            if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_fix_count, 1);
-        }
-        if (st == MXFFT_OK && (pl->mode == mxk::MODE_FP16 || pl->mode == mxk::MODE_BF16))
-            st = dev_alloc(pl, &pl->d_codes, (size_t)max_batch * n * n);   // one packed pair per value
         if (st == MXFFT_OK && pl->mode == mxk::MODE_FP16) {
             // the twiddles are halves already: packed exactly
             tw16.assign((size_t)n, 0u);
@@ -529,7 +548,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         ok = ok && hipMemcpyAsync(pl->d_twf, twf.data(), twf.size() * sizeof(float2), hipMemcpyHostToDevice, s) == hipSuccess;
     if (pl->d_tw16)
         ok = ok && hipMemcpyAsync(pl->d_tw16, tw16.data(), tw16.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemsetAsync(pl->d_status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
+    ok = ok && hipMemsetAsync(pl->ws.status, 0, sizeof(int32_t) * (size_t)max_batch, s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         release(pl);
@@ -543,11 +562,35 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
 
 namespace mxk {
 
-const int32_t* plan_status_words(mxfft_plan_t pl) { return pl->d_status; }
+const int32_t* plan_status_words(mxfft_plan_t pl) { return pl->ws.status; }
 
 void plan_release_idle(mxfft_plan_t pl) { release(pl); }
 
 bool plan_has_status(mxfft_plan_t pl) { return !(pl->p.flags & MXFFT_NO_PRESCALE); }
+
+int plan_device(const mxfft_plan_s* pl) { return pl->device; }
+
+void plan_workspace_layout(const mxfft_plan_s* pl, int batch, char* base, Workspace* w, size_t* bytes)
+{
+    const WsCounts c = ws_counts(pl, batch);
+    size_t off = 0;
+    auto take = [&](auto** ptr, size_t count) {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*ptr)>>;
+        if (base) *ptr = count ? (T*)(base + off) : nullptr;
+        off += (count * sizeof(T) + 255) & ~(size_t)255;
+    };
+    Workspace tmp;
+    Workspace* o = w ? w : &tmp;
+    take(&o->parts, c.parts);
+    take(&o->kp, c.kp);
+    take(&o->status, c.status);
+    take(&o->codes, c.codes);
+    take(&o->exps, c.exps);
+    take(&o->kadd, c.kadd);
+    take(&o->fix_list, c.fix_list);
+    take(&o->fix_count, c.fix_count);
+    *bytes = off;
+}
 
 }  // namespace mxk
 
@@ -578,28 +621,44 @@ mxfft_status mxfft_forward(mxfft_plan_t pl, const void* in, void* out, int32_t b
 {
     MX_TRY(check_call(pl, in, out, batch));
     if (batch == 0) return MXFFT_OK;
+    return mxk::plan_forward_ws(pl, pl->ws, in, out, batch, k_out, stream);
+}
+
+}  // extern "C"
+
+namespace mxk {
+
+mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                             int32_t* k_out, void* stream)
+{
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
-    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    const int32_t* kp = pre ? w.kp : nullptr;
     const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
     if (pre && pl->fused) {
-        MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+        MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
-        if (pre) MX_TRY(stats(pl, in, batch, s));
-        MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
+        if (pre) MX_TRY(stats(pl, w, in, batch, s));
+        MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
     }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
+    pl->last_status = w.status;
     return MXFFT_OK;
 }
+
+}  // namespace mxk
+
+extern "C" {
 
 mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t batch, const int32_t* k_in,
                            void* stream)
 {
     MX_TRY(check_call(pl, in, out, batch));
     if (batch == 0) return MXFFT_OK;
+    const mxk::Workspace& w = pl->ws;
     hipStream_t s = (hipStream_t)stream;
     const int kout_add = (pl->p.flags & MXFFT_NORMALIZE) ? -2 * pl->logn : 0;
     bool pre = false;
@@ -607,19 +666,20 @@ mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t b
     int kin_mul = 0;
     if (!k_in && !(pl->p.flags & MXFFT_NO_PRESCALE)) {
         pre = true;
-        kp = pl->d_kp;
+        kp = w.kp;
         kin_mul = 1;
     }
     if (pre && pl->fused) {
-        MX_TRY(row_with_stats(pl, in, nullptr, 1, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+        MX_TRY(row_with_stats(pl, w, in, nullptr, 1, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
-        if (pre) MX_TRY(stats(pl, in, batch, s));
-        MX_TRY(pass(pl, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
+        if (pre) MX_TRY(stats(pl, w, in, batch, s));
+        MX_TRY(pass(pl, w, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
     }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
+    pl->last_status = w.status;
     return MXFFT_OK;
 }
 
@@ -628,21 +688,23 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
 {
     MX_TRY(check_call(pl, in, out, batch));
     if (batch == 0) return MXFFT_OK;
+    const mxk::Workspace& w = pl->ws;
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
-    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    const int32_t* kp = pre ? w.kp : nullptr;
     if (pre && pl->fused) {
-        MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+        MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
-        if (pre) MX_TRY(stats(pl, in, batch, s));
-        MX_TRY(pass(pl, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-        MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+        if (pre) MX_TRY(stats(pl, w, in, batch, s));
+        MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
     }
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
-    MX_TRY(pass(pl, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
+    MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
+    MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     pl->last_batch = batch;
     pl->last_has_stats = pre;
+    pl->last_status = w.status;
     return MXFFT_OK;
 }
 
@@ -656,6 +718,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     const bool plain = pl->mode == mxk::MODE_FP32;
     if ((op == 2 || plain || !pl->fast) && !work) return MXFFT_EINVAL;
     if (recon == 0) return MXFFT_OK;
+    const mxk::Workspace& w = pl->ws;
     hipStream_t s = (hipStream_t)stream;
     const int batch = recon * coils;
     if (!pl->fast) {
@@ -668,35 +731,36 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
                    : MXFFT_EHIP;
     }
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
-    const int32_t* kp = pre ? pl->d_kp : nullptr;
+    const int32_t* kp = pre ? w.kp : nullptr;
     if (op == 0) {
         const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
         if (pre && pl->fused) {
-            MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
-            MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, pl->d_kadd,
+            MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
+            MX_TRY(pass(pl, w, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, w.kadd,
                         rss, coils));
         } else {
-            if (pre) MX_TRY(stats(pl, in, batch, s));
-            MX_TRY(pass(pl, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-            MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, nullptr, rss,
+            if (pre) MX_TRY(stats(pl, w, in, batch, s));
+            MX_TRY(pass(pl, w, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+            MX_TRY(pass(pl, w, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, nullptr, rss,
                         coils));
         }
     } else {
         // round trip: the forward result (kept scaled) goes to `work`
         if (pre && pl->fused) {
-            MX_TRY(row_with_stats(pl, in, k_out, 0, batch, s));
-            MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, pl->d_kadd));
+            MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
+            MX_TRY(pass(pl, w, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
         } else {
-            if (pre) MX_TRY(stats(pl, in, batch, s));
-            MX_TRY(pass(pl, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-            MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+            if (pre) MX_TRY(stats(pl, w, in, batch, s));
+            MX_TRY(pass(pl, w, in, work, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+            MX_TRY(pass(pl, w, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
         }
-        MX_TRY(pass(pl, work, work, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
-        MX_TRY(pass(pl, work, nullptr, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, recon, s, mxk::COL_RSS, nullptr, rss,
+        MX_TRY(pass(pl, w, work, work, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
+        MX_TRY(pass(pl, w, work, nullptr, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, recon, s, mxk::COL_RSS, nullptr, rss,
                     coils));
     }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
+    pl->last_status = w.status;
     return MXFFT_OK;
 }
 
@@ -714,7 +778,8 @@ mxfft_status mxfft_plan_last_status(mxfft_plan_t pl, void* stream)
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MXFFT_EHIP;
     if (!pl->last_has_stats || pl->last_batch == 0) return MXFFT_OK;
     std::vector<int32_t> st(pl->last_batch);
-    if (hipMemcpy(st.data(), pl->d_status, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    if (!pl->last_status ||
+        hipMemcpy(st.data(), pl->last_status, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return MXFFT_EHIP;
     for (int32_t v : st)
         if (v != 0) return (mxfft_status)v;

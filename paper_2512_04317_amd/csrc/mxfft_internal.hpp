@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "mxfft.h"
 
 struct mxfft_plan_s;
 
@@ -33,6 +36,21 @@ struct alignas(16) StatPart {
 // 2^(E + 17); the 6-bit formats' scale operand 2^(E + 12) at most stays in
 // range there too).
 constexpr int kEquivLo = -90, kEquivHi = 90;
+
+// Device workspace of one call: everything the kernels of a transform write
+// besides its output (and read back later in the same call).  A plan owns one
+// sized for its largest batch; the no-allocation forward carves one out of a
+// static device array instead.
+struct Workspace {
+    StatPart* parts = nullptr;    // prescale statistics per chunk or row tile
+    int32_t* kp = nullptr;        // prescale exponent per slice
+    int32_t* status = nullptr;    // device status word per slice
+    uint32_t* codes = nullptr;    // register-resident intermediate: MX codes or packed 16-bit values
+    uint8_t* exps = nullptr;      // MX intermediate block exponents (E8M0)
+    int32_t* kadd = nullptr;      // fused statistics: exponent offset per slice
+    int32_t* fix_list = nullptr;  // fused statistics: slices whose row pass is redone
+    int32_t* fix_count = nullptr; // length of fix_list (cleared by the row pass)
+};
 
 // Chunks per slice for a batch: enough work-groups to fill the chip, at
 // least 8192 elements each.
@@ -132,6 +150,20 @@ hipError_t launch_fill(float2* x, size_t count, uint32_t seed, hipStream_t s);
 // Release a plan whose work has completed (the caller has seen its last
 // event), without the device-wide synchronisation of mxfft_plan_destroy.
 void plan_release_idle(mxfft_plan_s* pl);
+
+// Forward transform of a checked call (1 <= batch) with the workspace w,
+// which must be sized for batch slices (the plan's own, or a carve-out of the
+// static array of mxfft_forward_static).
+mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                             int32_t* k_out, void* stream);
+
+// Workspace of a plan's forward call over `batch` slices laid out from
+// `base` (each buffer 256-byte aligned): *bytes gets the extent; with base
+// non-null, *w gets the buffer addresses.
+void plan_workspace_layout(const mxfft_plan_s* pl, int batch, char* base, Workspace* w, size_t* bytes);
+
+// Device the plan was created on.
+int plan_device(const mxfft_plan_s* pl);
 
 // Device status words of a plan (one int32 per slice of its last call, written
 // by the prescale statistics), and whether its calls write them.

@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ERANGE, EBUDGET, EBUSY, EUNSUPPORTED = 0, 
 INT32_MIN, INT32_MAX = -(2 ** 31), 2 ** 31 - 1
 
 # Every entry point declared in include/mxfft.h.
-EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_forward",
+EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_forward", "mxfft_forward_static",
            "mxfft_inverse", "mxfft_roundtrip", "mxfft_plan_last_status", "mxfft_plan_profile",
            "mxfft_plan_profile_roles",
            "mxfft_plan_kernel_times", "mxfft_plan_device_bytes", "mxfft_status_string", "mxfft_version",
@@ -95,7 +95,7 @@ def lib():
         L.mxfft_plan.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(Params), P]
         L.mxfft_plan_destroy.restype = i32
         L.mxfft_plan_destroy.argtypes = [P]
-        for name in ("mxfft_forward", "mxfft_roundtrip"):
+        for name in ("mxfft_forward", "mxfft_forward_static", "mxfft_roundtrip"):
             getattr(L, name).restype = i32
             getattr(L, name).argtypes = [P, P, P, i32, P, P]
         L.mxfft_inverse.restype = i32
@@ -224,6 +224,20 @@ class Plan:
         st = lib().mxfft_forward(self.handle, _ptr(x), _ptr(out), x.shape[0], _ptr(k_out), _stream(stream))
         if st != OK:
             raise MxfftError(st, "mxfft_forward")
+        return out, k_out
+
+    def forward_static(self, x, out=None, k_out=None, stream=None):
+        """As forward, through mxfft_forward_static: no device allocation in
+        the library; its workspace is the static array shared by every such
+        call on the device (batch may exceed max_batch while it fits)."""
+        _check_slices(x, self.n, "x")
+        if out is None or k_out is None:
+            raise ValueError("forward_static needs caller-allocated out and k_out")
+        _check_slices(out, self.n, "out")
+        k_out = self._kbuf(x.shape[0], k_out, x.device)
+        st = lib().mxfft_forward_static(self.handle, _ptr(x), _ptr(out), x.shape[0], _ptr(k_out), _stream(stream))
+        if st != OK:
+            raise MxfftError(st, "mxfft_forward_static")
         return out, k_out
 
     def inverse(self, x, out=None, k_in=None, stream=None):
