@@ -132,7 +132,7 @@ mxfft_status mxfft_forward(mxfft_plan_t plan, const void* in, void* out, int32_t
  * ends.  The plan supplies only its twiddle tables, so batch may exceed the
  * plan's max_batch (1 <= batch <= 65535) as long as that workspace fits:
  * MXFFT_EBUDGET otherwise (nothing is enqueued).  It is about 0.55 MiB per
- * slice at n = 512 and 2.2 MiB at n = 1024 for MXFP8 B = 32 (113 and 28 slices),
+ * slice at n = 512 and 2.2 MiB at n = 1024 for MXFP8 B = 32 (114 and 28 slices),
  * 1 MiB per slice at n = 512 for FP16/BF16, and under 5 MiB in all for plans on
  * the generic line kernels.  The plan must belong to the current device
  * (MXFFT_EINVAL otherwise).  Every call on a GPU shares that GPU's array:
