@@ -241,7 +241,8 @@ def full_workload():
 
 def test_full_size_sampled(full_workload):
     """The benchmark's launch: 1024 slices of 512^2, MXFP8-E4M3, B = 32.
-    Every slice's k against the oracle's Alg. 1; three whole slices bit for bit."""
+    Every 16th slice's k against the oracle's Alg. 1; three whole slices bit
+    for bit."""
     x = full_workload
     plan = mxfft.Plan(512, x.shape[0], fmt="e4m3", block=32)
     xd = torch.from_numpy(x).cuda()
