@@ -75,6 +75,13 @@ typedef enum {
  * fusion the paper proposes in its discussion, Sec. 4; less round-trip loss).
  * No effect on the other operations and formats. */
 #define MXFFT_FUSED_ROUNDTRIP 0x8u
+/* MX formats: every forward call also records the column pass's MX input
+ * (the row pass's result in blocks of B/2 rows of one column: Alg. 2's
+ * EncodeBlockMX, element values and shared exponents), which
+ * mxfft_plan_capture() returns.  The plan holds 8 + 8/B bytes more per
+ * complex value of max_batch slices, and each forward call of up to
+ * max_batch slices writes them. */
+#define MXFFT_DEBUG_CAPTURE 0x10u
 
 typedef struct {
     uint32_t struct_size;  /* sizeof(mxfft_params); checked for ABI versioning */
@@ -87,8 +94,10 @@ typedef struct {
     uint32_t flags;        /* MXFFT_* flags above */
     double target;         /* Alg. 1 peak target T > 0 (e.g. 2^7) */
     double tau_pct;        /* Alg. 1 tail percentile tau, in percent, 0..100 */
-    double tau_min;        /* Alg. 1 tail floor tau_min > 0; this library needs a
-                              power of two (else MXFFT_EUNSUPPORTED) */
+    double tau_min;        /* Alg. 1 tail floor tau_min > 0 (any value; when it is
+                              not a power of two the statistics read each
+                              slice once more to place the percentile against
+                              it exactly) */
 } mxfft_params;
 
 typedef struct mxfft_plan_s* mxfft_plan_t;
@@ -193,6 +202,18 @@ mxfft_status mxfft_rss(mxfft_plan_t plan, int32_t op, const void* in, void* work
  * over the positions where the window lies inside the image.  FP64; one
  * work-group per image; no workspace. */
 mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t count, double* ssim, void* stream);
+
+/* MXFFT_DEBUG_CAPTURE plans: copy (on `stream`, asynchronously) what the
+ * last forward call recorded for its `batch` slices, the MX encode of the
+ * column pass's input (Alg. 2, EncodeBlockMX over blocks of B/2 consecutive
+ * rows of one column, after the row pass and the Alg. 1 prescale):
+ *   mant: complex64 [batch][n][n] element values (the decoded codes without
+ *         the block scale: E4M3/E5M2/E2M3/E3M2 values, signed zeros kept);
+ *   exps: int32 [batch][n][n / (B/2)] shared exponent E of column c and row
+ *         block r at [slice][c][r] (value = mant * 2^E).
+ * 1 <= batch <= the batch of that call; MXFFT_EINVAL otherwise (also for a
+ * plan without the flag or before any forward call). */
+mxfft_status mxfft_plan_capture(mxfft_plan_t plan, void* mant, int32_t* exps, int32_t batch, void* stream);
 
 /* Synchronise `stream` and return the device status of the plan's last call
  * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */

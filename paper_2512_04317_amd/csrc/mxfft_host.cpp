@@ -14,7 +14,8 @@
 
 namespace {
 
-constexpr uint32_t kKnownFlags = MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE | MXFFT_FUSED_ROUNDTRIP;
+constexpr uint32_t kKnownFlags =
+    MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE | MXFFT_FUSED_ROUNDTRIP | MXFFT_DEBUG_CAPTURE;
 
 // Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2) and the
 // 16-bit forms (IEEE half, bfloat16; twiddles never reach their overflow).
@@ -105,6 +106,10 @@ struct mxfft_plan_s {
     uint32_t* d_tw16 = nullptr;      // FP16 form: the same twiddles as packed halves
     // statistics gathered by the row pass (MX at 512^2 and 1024^2)
     bool fused = false;
+    // MXFFT_DEBUG_CAPTURE: the column pass input of the last forward call
+    float2* d_cap_mant = nullptr;
+    int32_t* d_cap_exp = nullptr;
+    int cap_batch = 0;
     uint64_t bytes = 0;
     int last_batch = 0;
     bool last_has_stats = false;
@@ -188,15 +193,15 @@ mxfft_status check_params(const mxfft_params* p, int n)
         break;
     case MXFFT_FP32:
     case MXFFT_FP16:
-    case MXFFT_BF16: break;
+    case MXFFT_BF16:
+        if (p->flags & MXFFT_DEBUG_CAPTURE) return MXFFT_EINVAL;   // MX formats only
+        break;
     default: return MXFFT_EINVAL;
     }
     if (!(p->flags & MXFFT_NO_PRESCALE)) {
         if (!std::isfinite(p->target) || !(p->target > 0.0)) return MXFFT_EINVAL;
         if (!(p->tau_pct >= 0.0 && p->tau_pct <= 100.0)) return MXFFT_EINVAL;
         if (!std::isfinite(p->tau_min) || !(p->tau_min > 0.0)) return MXFFT_EINVAL;
-        int e;
-        if (std::frexp(p->tau_min, &e) != 0.5) return MXFFT_EUNSUPPORTED;
         if (p->k_min > p->k_max) return MXFFT_EINVAL;
     }
     return MXFFT_OK;
@@ -225,6 +230,8 @@ void release(mxfft_plan_s* pl)
     (void)hipFree(pl->d_tw_exp);
     (void)hipFree(pl->d_twf);
     (void)hipFree(pl->d_tw16);
+    (void)hipFree(pl->d_cap_mant);
+    (void)hipFree(pl->d_cap_exp);
     (void)hipFree(pl->ws.parts);
     (void)hipFree(pl->ws.kp);
     (void)hipFree(pl->ws.status);
@@ -323,7 +330,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
                   int32_t* k_out,
                   int kin_mul, int kout_mul, int kout_add, int axis, int inverse, int batch, hipStream_t s,
                   int kind = mxk::ROW_PLAIN, const int32_t* kadd = nullptr, float* rss = nullptr,
-                  int coils = 0)
+                  int coils = 0, bool capture = false)
 {
     const int role = (kind == mxk::ROW_FIX) ? ROLE_FIX
                      : inverse              ? (axis ? ROLE_INV_COL : ROLE_INV_ROW)
@@ -375,6 +382,8 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     a.axis = axis;
     a.inverse = inverse;
     a.encode = mxk::is_mx_mode(pl->mode) && kind != mxk::ROW_RAW;
+    a.cap_mant = capture ? pl->d_cap_mant : nullptr;
+    a.cap_exp = capture ? pl->d_cap_exp : nullptr;
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -383,9 +392,7 @@ mxk::PrescaleArgs prescale_args(const mxfft_plan_s* pl)
     mxk::PrescaleArgs pa{};
     pa.target = pl->p.target;
     pa.tau = pl->p.tau_pct;
-    int e;
-    std::frexp(pl->p.tau_min, &e);
-    pa.log2_tau_min = e - 1;
+    pa.tau_min = pl->p.tau_min;
     pa.k_min = pl->p.k_min;
     pa.k_max = pl->p.k_max;
     return pa;
@@ -513,6 +520,10 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         if (st == MXFFT_OK && c.fix_list) st = dev_alloc(pl, &pl->ws.fix_list, c.fix_list);
         if (st == MXFFT_OK && c.fix_count) st = dev_alloc(pl, &pl->ws.fix_count, c.fix_count);
     }
+    if (st == MXFFT_OK && (p->flags & MXFFT_DEBUG_CAPTURE)) {
+        st = dev_alloc(pl, &pl->d_cap_mant, (size_t)max_batch * n * n);
+        if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_cap_exp, (size_t)max_batch * n * (n / pl->cb));
+    }
     std::vector<float2> twf;
     std::vector<uint32_t> tw16;
     if (st == MXFFT_OK && pl->fast) {
@@ -635,14 +646,23 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
     const int32_t* kp = pre ? w.kp : nullptr;
     const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
+    const bool cap = pl->d_cap_mant != nullptr && batch <= pl->max_batch;   // capture buffers hold max_batch
     if (pre && pl->fused) {
         MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
         if (pre) MX_TRY(stats(pl, w, in, batch, s));
         MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr,
+                    0, cap));
     }
+    if (cap && pl->fast) {
+        // the register-resident intermediate holds the column pass input
+        if (mxk::launch_capture_mx(pl->mode, pl->n, pl->cb, w.codes, w.exps, (pre && pl->fused) ? w.kadd : nullptr,
+                                   batch, pl->d_cap_mant, pl->d_cap_exp, s) != hipSuccess)
+            return MXFFT_EHIP;
+    }
+    if (cap) pl->cap_batch = batch;
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     pl->last_status = w.status;
@@ -770,6 +790,18 @@ mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t cou
         return MXFFT_EINVAL;
     if (count == 0) return MXFFT_OK;
     return mxk::launch_ssim(x, ref, n, count, ssim, (hipStream_t)stream) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
+}
+
+mxfft_status mxfft_plan_capture(mxfft_plan_t pl, void* mant, int32_t* exps, int32_t batch, void* stream)
+{
+    if (!pl || !mant || !exps || !pl->d_cap_mant || batch < 1 || batch > pl->cap_batch) return MXFFT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nn = (size_t)pl->n * pl->n, b = (size_t)batch;
+    if (hipMemcpyAsync(mant, pl->d_cap_mant, b * nn * sizeof(float2), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(exps, pl->d_cap_exp, b * pl->n * (pl->n / pl->cb) * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+        return MXFFT_EHIP;
+    return MXFFT_OK;
 }
 
 mxfft_status mxfft_plan_last_status(mxfft_plan_t pl, void* stream)

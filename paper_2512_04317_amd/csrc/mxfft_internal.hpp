@@ -62,7 +62,7 @@ size_t stats_parts(int n, int max_batch);
 struct PrescaleArgs {
     double target;      // T > 0
     double tau;         // percent
-    int32_t log2_tau_min;  // tau_min = 2^log2_tau_min
+    double tau_min;     // > 0
     int32_t k_min, k_max;
 };
 
@@ -85,6 +85,8 @@ struct LineArgs {
     int32_t axis;            // 0 rows (contiguous), 1 columns
     int32_t inverse;
     int32_t encode;          // MX-encode the pass input
+    float2* cap_mant;        // column pass: its encoded input's element values, or nullptr
+    int32_t* cap_exp;        // column pass: its input block exponents [slice][column][row block]
 };
 
 // MX formats, the 16-bit positive controls (per-operation rounding) and plain FP32
@@ -138,6 +140,11 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
                               int32_t* fix_count, int32_t* k_out, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 int line_lines_per_group(int n);
+// Debug capture from the register-resident MX intermediate: element values
+// [slice][row][col] and exponents [slice][col][row block] (plus kadd[slice]
+// when given) of batch slices.
+hipError_t launch_capture_mx(int mode, int n, int cb, const uint32_t* codes, const uint8_t* exps,
+                             const int32_t* kadd, int batch, float2* mant, int32_t* cap_exp, hipStream_t s);
 // Root-sum-of-squares coil combine of finished transforms (recon x coils slices).
 hipError_t launch_rss(const float2* T, int coils, size_t nn, long recon, float* rss, hipStream_t s);
 

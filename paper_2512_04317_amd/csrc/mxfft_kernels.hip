@@ -138,14 +138,17 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
     __shared__ uint32_t hist[kStatsBins];
     __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
     __shared__ uint32_t s_count, s_maxc, s_nonfin;
-    __shared__ int s_refine, s_bin_lo, s_bin_hi, s_emin, s_emax;
+    __shared__ int s_refine, s_thresh, s_bin_lo, s_bin_hi, s_emin, s_emax;
+    __shared__ unsigned long long s_m2_cut;
+    __shared__ uint32_t s_below;
+    __shared__ double s_tp;
     const int tid = threadIdx.x, slice = blockIdx.x;
     const float2* xs = x + (size_t)slice * nn;
     const StatPart* pt = parts + (size_t)slice * chunks;
 
     __shared__ uint32_t s_wave[4];
     if (tid == 0) {
-        s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0;
+        s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0; s_thresh = 0;
         s_emin = 0; s_emax = 0; s_bin_lo = -1; s_bin_hi = -1;
     }
     for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
@@ -210,10 +213,38 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
         }
     }
     __syncthreads();
+    // Alg. 1's tail floor: k2 = the smallest k with max(p, 1e-30) 2^k >= tau_min,
+    // i.e. min(k2(p), k2(1e-30)).  With p = fp 2^ep and tau_min = ft 2^et
+    // (frexp mantissas in [1/2, 1)), k2(p) = et - ep + (fp < ft).  The binade of
+    // p gives ep; fp < ft is needed only when tau_min is not a power of two.
+    int et;
+    const double ft = frexp(pa.tau_min, &et);
     if (tid == 0 && n && !s_nonfin) {
         s_refine = (s_bin_lo != s_bin_hi) && (fr != 0.0);
+        s_thresh = !s_refine && ft != 0.5;
         s_lo_max = 0;
         s_hi_min = ~0ull;
+        s_below = 0;
+        s_m2_cut = 0;
+        if (s_thresh) {
+            // p lies in binade s_bin_lo; T' = ft 2^ep is the threshold in it, and
+            // m = RN(sqrt(m2)) < T' iff m2 < the smallest FP64 x with
+            // RN(sqrt(x)) >= T' (sqrt and rounding are monotone)
+            const double tp = ldexp(ft, s_bin_lo - kBinOffset + 1);
+            double xq = tp * tp;
+            if (__dsqrt_rn(xq) >= tp) {
+                for (int it = 0; it < 64; it++) {
+                    const double y = __longlong_as_double(__double_as_longlong(xq) - 1);
+                    if (__dsqrt_rn(y) >= tp) xq = y;
+                    else break;
+                }
+            } else {
+                for (int it = 0; it < 64 && __dsqrt_rn(xq) < tp; it++)
+                    xq = __longlong_as_double(__double_as_longlong(xq) + 1);
+            }
+            s_m2_cut = (unsigned long long)__double_as_longlong(xq);
+            s_tp = tp;
+        }
     }
     __syncthreads();
     if (s_refine) {
@@ -230,6 +261,26 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
             }
         }
         __syncthreads();
+    } else if (s_thresh) {
+        // count the values below T', with the largest below and the smallest
+        // at or above it (the two order statistics when T' falls between them)
+        const unsigned long long cut = s_m2_cut;
+        uint32_t below = 0;
+        for (int i = tid; i < nn; i += blockDim.x) {
+            const float2 v = xs[i];
+            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+            if (m2 > 0.0) {
+                if (b < cut) {
+                    below++;
+                    atomicMax(&s_lo_max, b);
+                } else {
+                    atomicMin(&s_hi_min, b);
+                }
+            }
+        }
+        atomicAdd(&s_below, below);
+        __syncthreads();
     }
     if (tid == 0) {
         int32_t k = 0, st = 0;
@@ -238,22 +289,45 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
         } else if (n) {
             const double amax = __dsqrt_rn(__longlong_as_double((long long)s_m2));
             const int k1 = round_log2_ratio(pa.target, amax > 1e-30 ? amax : 1e-30);
-            int lp;  // floor(log2 p_tau)
+            // k2(v) for v > 0
+            auto k2_of = [&](double v) -> long long {
+                int ev;
+                const double fv = frexp(v, &ev);
+                return (long long)et - ev + (fv < ft ? 1 : 0);
+            };
+            long long k2p;
             if (s_refine) {
                 const double lo = __dsqrt_rn(__longlong_as_double((long long)s_lo_max));
                 const double hi = __dsqrt_rn(__longlong_as_double((long long)s_hi_min));
                 const double d = hi - lo;
                 const double fd = fr * d;
-                const double p = lo + fd;
-                int e;
-                frexp(p, &e);
-                lp = e - 1;
+                k2p = k2_of(lo + fd);
             } else {
-                lp = s_bin_lo - kBinOffset;
+                // p in binade lp: fp >= 1/2 >= ft for a power-of-two tau_min
+                const int lp = s_bin_lo - kBinOffset;
+                bool under = false;  // p < T' (i.e. fp < ft)
+                if (s_thresh) {
+                    const long long c = s_below;
+                    const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
+                    if (fr == 0.0 || r1 == ri) {
+                        under = c >= ri + 1;             // p = S[ri]
+                    } else if (c <= ri) {
+                        under = false;                   // T' <= S[ri] <= p
+                    } else if (c >= ri + 2) {
+                        under = true;                    // p <= S[ri+1] < T'
+                    } else {
+                        // S[ri] < T' <= S[ri+1]: p exactly
+                        const double lo = __dsqrt_rn(__longlong_as_double((long long)s_lo_max));
+                        const double hi = __dsqrt_rn(__longlong_as_double((long long)s_hi_min));
+                        const double d = hi - lo;
+                        const double fd = fr * d;
+                        under = (lo + fd) < s_tp;
+                    }
+                }
+                k2p = (long long)et - (lp + 1) + (under ? 1 : 0);
             }
-            lp = max(lp, -100);  // max(p, 1e-30): 1e-30 lies in binade -100
-            const int k2 = pa.log2_tau_min - lp;
-            long long kk = max(k1, k2);
+            const long long k2 = min(k2p, k2_of(1e-30));
+            long long kk = max((long long)k1, k2);
             kk = min(max(kk, (long long)pa.k_min), (long long)pa.k_max);
             k = (int32_t)kk;
             // every component scaled by 2^k must stay finite in FP32
@@ -414,8 +488,17 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
                 float2 v = lds[idx];
                 const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
                 const int E = mxd::block_exp<MODE>(am);
-                v.x = ldexpf(mxd::quant<MODE>(ldexpf(v.x, -E)), E);
-                v.y = ldexpf(mxd::quant<MODE>(ldexpf(v.y, -E)), E);
+                const float qx = mxd::quant<MODE>(ldexpf(v.x, -E)), qy = mxd::quant<MODE>(ldexpf(v.y, -E));
+                if (a.cap_mant && a.axis == 1) {
+                    // debug capture of the column pass input: line r is column
+                    // line0 + r, element e its row
+                    const int r = idx >> logn, e = idx & (N - 1), col = line0 + r;
+                    a.cap_mant[sbase + (size_t)e * N + col] = make_float2(qx, qy);
+                    if ((e & (a.cb - 1)) == 0)
+                        a.cap_exp[((size_t)slice * N + col) * (N >> a.logcb) + (e >> a.logcb)] = E;
+                }
+                v.x = ldexpf(qx, E);
+                v.y = ldexpf(qy, E);
                 lds[idx] = v;
             }
             __syncthreads();
@@ -472,6 +555,61 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
         v.y = ldexpf(v.y, kout);
         a.dst[g] = v;
     }
+}
+
+// Debug capture from the register-resident MX intermediate.  Its layout:
+// codes[slice][16-column group][row][8 words], the word of the group's
+// columns 2w, 2w + 1 at w ^ (((row >> 2) & 3) << 1), holding (re, im) of the
+// even column in its low half and of the odd one in its high half;
+// exps[slice][row block][column] as E + 127 (E offset by -kadd[slice] when
+// the row pass ran on the unscaled input).  One thread per (slice, row,
+// column pair).  MXFP6 codes travel as FP8 codes of the value times 2^-OFF.
+typedef float capf2 __attribute__((ext_vector_type(2)));
+__global__ void k_capture_mx(int fmt8, int off, int n, int logcb, const uint32_t* __restrict__ codes,
+                             const uint8_t* __restrict__ exps, const int32_t* __restrict__ kadd, long pairs,
+                             float2* __restrict__ mant, int32_t* __restrict__ cap_exp)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pairs) return;
+    const int half = n >> 1;
+    const long slice = i / ((long)n * half);
+    const int rem = (int)(i - slice * (long)n * half);
+    const int row = rem / half, c2 = 2 * (rem - row * half);
+    const uint32_t w = codes[(size_t)slice * n * n / 2 + ((size_t)(c2 >> 4) * n + row) * 8 +
+                             (((c2 & 15) >> 1) ^ (((row >> 2) & 3) << 1))];
+    const float us = __uint_as_float((uint32_t)(off + 127) << 23);   // 2^OFF
+    capf2 lo, hi;
+    if (fmt8 == 0) {
+        lo = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(w, us, false);
+        hi = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(w, us, true);
+    } else {
+        lo = __builtin_amdgcn_cvt_scalef32_pk_f32_bf8(w, us, false);
+        hi = __builtin_amdgcn_cvt_scalef32_pk_f32_bf8(w, us, true);
+    }
+    float2* m = mant + ((size_t)slice * n + row) * n + c2;
+    m[0] = make_float2(lo.x, lo.y);
+    m[1] = make_float2(hi.x, hi.y);
+    if ((row & ((1 << logcb) - 1)) == 0) {
+        const int nb = n >> logcb, rb = row >> logcb;
+        const int add = kadd ? kadd[slice] : 0;
+        const uint8_t* ex = exps + ((size_t)slice * nb + rb) * n + c2;
+        int32_t* o = cap_exp + ((size_t)slice * n + c2) * nb + rb;
+        o[0] = (int32_t)ex[0] - 127 + add;
+        o[nb] = (int32_t)ex[1] - 127 + add;
+    }
+}
+
+hipError_t launch_capture_mx(int mode, int n, int cb, const uint32_t* codes, const uint8_t* exps,
+                             const int32_t* kadd, int batch, float2* mant, int32_t* cap_exp, hipStream_t s)
+{
+    const int fmt8 = (mode == MODE_E5M2 || mode == MODE_E3M2) ? 1 : 0;
+    const int off = (mode == MODE_E2M3) ? 6 : (mode == MODE_E3M2) ? 12 : 0;
+    int logcb = 0;
+    while ((1 << logcb) < cb) logcb++;
+    const long pairs = (long)batch * n * (n / 2);
+    hipLaunchKernelGGL(k_capture_mx, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, fmt8, off, n, logcb,
+                       codes, exps, kadd, pairs, mant, cap_exp);
+    return hipGetLastError();
 }
 
 // Synthetic data for launch tuning: both parts uniform in [-1, 1) from a

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libmxfft.so")
 
 E4M3, E5M2, FP16, BF16, FP32, E2M3, E3M2 = 0, 1, 2, 3, 4, 5, 6
 FORMATS = {"e4m3": E4M3, "e5m2": E5M2, "fp16": FP16, "bf16": BF16, "fp32": FP32, "e2m3": E2M3, "e3m2": E3M2}
-NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_ROUNDTRIP = 0x1, 0x2, 0x4, 0x8
+NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_ROUNDTRIP, DEBUG_CAPTURE = 0x1, 0x2, 0x4, 0x8, 0x10
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ERANGE, EBUDGET, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 INT32_MIN, INT32_MAX = -(2 ** 31), 2 ** 31 - 1
 
@@ -28,7 +28,7 @@ EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_fo
            "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
            "mxfft_batch_destroy", "mxfft_plan_bytes", "mxfft_serve_create", "mxfft_serve_submit",
            "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy", "mxfft_rss",
-           "mxfft_ssim")
+           "mxfft_ssim", "mxfft_plan_capture")
 TUNE_FORCE = 0x1
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 
@@ -102,6 +102,8 @@ def lib():
         L.mxfft_inverse.argtypes = [P, P, P, i32, P, P]
         L.mxfft_plan_last_status.restype = i32
         L.mxfft_plan_last_status.argtypes = [P, P]
+        L.mxfft_plan_capture.restype = i32
+        L.mxfft_plan_capture.argtypes = [P, P, P, i32, P]
         L.mxfft_plan_profile.restype = i32
         L.mxfft_plan_profile.argtypes = [P, i32]
         L.mxfft_plan_profile_roles.restype = i32
@@ -281,6 +283,19 @@ class Plan:
         if st != OK:
             raise MxfftError(st, "mxfft_rss")
         return out, k_out
+
+    def capture(self, batch, stream=None):
+        """DEBUG_CAPTURE plans: the column pass's MX input of the last forward
+        call (its first `batch` slices): element values complex64 [batch, n, n]
+        and block exponents int32 [batch, n (columns), n / (B/2) (row blocks)]."""
+        cb = self.params.block // 2
+        dev = torch.device("cuda", torch.cuda.current_device())
+        mant = torch.empty((batch, self.n, self.n), dtype=torch.complex64, device=dev)
+        exps = torch.empty((batch, self.n, self.n // cb), dtype=torch.int32, device=dev)
+        st = lib().mxfft_plan_capture(self.handle, _ptr(mant), _ptr(exps), int(batch), _stream(stream))
+        if st != OK:
+            raise MxfftError(st, "mxfft_plan_capture")
+        return mant, exps
 
     def last_status(self, stream=None):
         return lib().mxfft_plan_last_status(self.handle, _stream(stream))

@@ -58,9 +58,11 @@ def plan_status(n, max_batch, **kw):
     (64, 1, dict(tau=101.0), mxfft.EINVAL),
     (64, 1, dict(target=0.0), mxfft.EINVAL),
     (64, 1, dict(target=float("nan")), mxfft.EINVAL),
-    (64, 1, dict(tau_min=0.3), mxfft.EUNSUPPORTED),  # tau_min must be a power of two
+    (64, 1, dict(tau_min=0.0), mxfft.EINVAL),       # tau_min > 0
+    (64, 1, dict(tau_min=float("inf")), mxfft.EINVAL),
     (64, 1, dict(k_min=3, k_max=2), mxfft.EINVAL),
     (64, 1, dict(flags=0x80), mxfft.EINVAL),
+    (64, 1, dict(fmt="fp16", flags=mxfft.DEBUG_CAPTURE), mxfft.EINVAL),   # capture: MX formats only
 ])
 def test_plan_argument_checks(n, mb, kw, st):
     assert plan_status(n, mb, **kw) == st
@@ -150,3 +152,10 @@ def test_plan_bytes_host():
         n, mb = bad.pop("n"), bad.pop("max_batch", 1)
         with pytest.raises(mxfft.MxfftError):
             mxfft.plan_bytes(n, mb, **bad)
+
+
+def test_any_positive_tau_min_is_accepted():
+    """Alg. 1 takes any tail floor: plans with tau_min not a power of two are
+    valid (checked host-side through mxfft_plan_bytes, no GPU call)."""
+    for t in (0.3, 1e-3, 3.0 * 2.0 ** -7, 314572.8):
+        assert mxfft.plan_bytes(256, 4, tau_min=t) > 0

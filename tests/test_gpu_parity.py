@@ -401,6 +401,92 @@ def test_fp6_scale_range_edges(N, fmt, B):
         assert_bitexact(yg, yo, "%d^2 %s %s B=%d range edges" % (N, op, fmt, B))
 
 
+def fp8_range_batch(N):
+    """Slices at both ends of the E8M0 scale range for MXFP8 (no prescale, or
+    a prescale clipped to keep them there): an impulse near 2^125 and two
+    near 2^122 (a plane wave of the same size after each pass), FP32-subnormal
+    noise and a tiny impulse (block exponents clamped at -127 and product
+    scales 2^(E_w + E_v + k_r) below 2^-127, which the kernels apply with
+    ldexp), a subnormal impulse that quantises to zero, and an ordinary slice
+    with a few rows of tiny values beside its normal ones."""
+    x = np.zeros((6, N, N), np.complex64)
+    x[0, 3, 5] = np.float32(2.0 ** 125 * 1.3) - 1j * np.float32(2.0 ** 124)
+    x[1, 1, 1] = np.float32(2.0 ** 122)
+    x[1, N - 3, N // 3] = 1j * np.float32(2.0 ** 121 * 1.7)
+    rng = np.random.default_rng([N, 8])
+    x[2] = ((rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * 1e-38).astype(np.complex64)
+    x[3, 9, 9] = np.float32(2.0 ** -120) - 1j * np.float32(2.0 ** -121)
+    x[4, 2, N - 1] = np.float32(2.0 ** -140)
+    x[5] = ((rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))).astype(np.complex64)
+    x[5, ::7] *= np.float32(2.0 ** -125)
+    return x
+
+
+@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e5m2", 16), ("e4m3", 64), ("e5m2", 64)])
+@pytest.mark.parametrize("N", [128, 512])
+def test_fp8_scale_range_edges(N, fmt, B):
+    """MXFP8 blocks at the E8M0 limits: block exponents clamped at -127, and
+    product scales below 2^-127 (the decode-then-ldexp branch of the butterfly),
+    on the register-resident passes (B = 16, 32) and the line kernels
+    (B = 64); forward and inverse without the prescale, and the forward with a
+    prescale clipped at k_max = 0 (the fused statistics then redo every tiny
+    slice literally at 512^2)."""
+    x = fp8_range_batch(N)
+    for op in ("forward", "inverse"):
+        yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B, flags=mxfft.NO_PRESCALE)
+        so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B, flags=O.NO_PRESCALE)
+        assert st == mxfft.OK and so == O.OK
+        assert np.isfinite(yo).all() and np.abs(yo).max() > 2.0 ** 124
+        assert_bitexact(yg, yo, "%d^2 %s %s B=%d E8M0 edges" % (N, op, fmt, B))
+    yg, kg, st = gpu_run(x, fmt=fmt, block=B, k_max=0)
+    so, yo, ko = orc_run(x, fmt=fmt, block=B, k_max=0)
+    assert st == mxfft.OK and so == O.OK
+    np.testing.assert_array_equal(kg, ko)
+    assert (ko[2:5] == 0).all()
+    assert_bitexact(yg, yo, "%d^2 forward %s B=%d k_max=0" % (N, fmt, B))
+
+
+def tau_min_batch(N, rng):
+    """Slices for Alg. 1 with a tail floor that is not a power of two
+    (tau_min = 0.3 * 2^20, mantissa 0.6): the percentile (tau = 5) between
+    two values a < T' <= b of one binade, T' = 0.6 * 2^(lp + 1) the floor's
+    threshold in that binade, with p = a + f (b - a) on either side of T';
+    the same with both order statistics below T'; synthetic k-space; and a
+    slice of values near 1e-30 (Alg. 1's guard max(p, 1e-30))."""
+    nn = N * N
+    ri = int(np.floor((nn - 1) * 5.0 / 100.0))
+    out = []
+    for a, b in ((0.14, 0.16), (0.14, 0.151), (0.13, 0.14)):
+        v = np.full(nn, b, np.float32)
+        v[:ri + 1] = a
+        rng.shuffle(v)
+        out.append(v.reshape(N, N).astype(np.complex64))
+    out.append(synth.kspace_batch(N, 6, 1, 1)[0])
+    tiny = (9e-31 * (1.0 + 0.01 * rng.random((N, N)))).astype(np.float32)
+    out.append(tiny.astype(np.complex64))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("N,fmt,B", [(512, "e4m3", 32), (256, "e5m2", 16), (64, "e4m3", 32), (512, "fp16", 32)])
+def test_tau_min_not_a_power_of_two(N, fmt, B):
+    """Alg. 1 with tau_min = 0.3 * 2^20 (and 0.3, where the 1e-30 guard
+    decides): k bit for bit against the oracle on the fused statistics (512^2
+    MX), the literal statistics (256^2, the 16-bit form) and the line kernels
+    (64^2), with the outputs; the floor's mantissa matters (the power-of-two
+    floor 2^18 gives another k for some of the first three slices)."""
+    rng = np.random.default_rng([N, 9])
+    x = tau_min_batch(N, rng)
+    for tm, tgt in ((0.3 * 2.0 ** 20, 2.0 ** 7), (0.3, 2.0 ** -90)):
+        yg, kg, st = gpu_run(x, fmt=fmt, block=B, tau_min=tm, target=tgt)
+        so, yo, ko = orc_run(x, fmt=fmt, block=B, tau_min=tm, target=tgt)
+        assert st == mxfft.OK and so == O.OK
+        np.testing.assert_array_equal(kg, ko)
+        assert_bitexact(yg, yo, "%d^2 %s tau_min=%g" % (N, fmt, tm))
+    k_pow2 = [O.prescale(x[i], tau_min=2.0 ** 18)[1] for i in range(3)]
+    k_gen = [O.prescale(x[i], tau_min=0.3 * 2.0 ** 20)[1] for i in range(3)]
+    assert any(g != q for g, q in zip(k_gen, k_pow2)), (k_gen, k_pow2)
+
+
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
 @pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e5m2", 8)])
 def test_n512_prescale_paths(op, fmt, B):
