@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven work list (sizes 128..1024)")
     ap.add_argument("--no-serving", action="store_true", help="skip the served request stream")
     ap.add_argument("--no-rss", action="store_true", help="skip the RSS-image quality and the fused RSS timing")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="skip the block-size table (256^2, 32 slices x 8 coils, E4M3/E5M2, B = 8..64)")
+    ap.add_argument("--no-small", action="store_true", help="skip the single 64^2 slice (latency, accuracy)")
     ap.add_argument("--cpu-sample", type=int, default=256, help="slices the CPU oracle transforms per run")
     ap.add_argument("--cpu-runs", type=int, default=3, help="timed oracle runs (median reported)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -137,6 +140,97 @@ def uneven_batch(args, torch, mxfft, synth):
     return res
 
 
+def nrmse_psnr(y, ref):
+    """Per-slice NRMSE and PSNR of y against ref (both [batch, n, n])."""
+    y = y.astype(np.complex128)
+    ref = ref.astype(np.complex128)
+    b = y.shape[0]
+    err = np.linalg.norm((y - ref).reshape(b, -1), axis=1) / np.linalg.norm(ref.reshape(b, -1), axis=1)
+    mse = np.mean(np.abs(y - ref) ** 2, axis=(1, 2))
+    psnr = 20 * np.log10(np.abs(ref).max(axis=(1, 2)) / np.sqrt(mse))
+    return err, psnr
+
+
+def block_table(args, torch, mxfft, synth):
+    """The block-size trade-off (the paper's Table 2, Sec. 4.2) on the
+    256^2 workload: 32 slices x 8 coils of synthetic k-space, MXFP8 E4M3 and
+    E5M2 at B = 8, 16, 32, 64, forward and round trip, Alg. 1 prescale.
+    Per entry: slices/s (one call over the 256 coil slices), the HBM fraction
+    of the algorithmic 16 B per element per call, and NRMSE / PSNR against
+    FP64 over every slice (forward: numpy's complex128 fft2; round trip: the
+    input itself)."""
+    w = synth.WORKLOADS["kspace256_32x8"]
+    N, batch = w["N"], w["slices"] * w["coils"]
+    x = synth.kspace_batch(N, w["config"], w["slices"], w["coils"], workers=min(16, os.cpu_count() or 1))
+    ref_f = np.fft.fft2(x.astype(np.complex128))
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    k = torch.empty(batch, dtype=torch.int32, device="cuda")
+    rows = []
+    steps = max(5, args.steps // 2)
+    for fmt in ("e4m3", "e5m2"):
+        for B in (8, 16, 32, 64):
+            with mxfft.Plan(N, batch, fmt=fmt, block=B) as pl:
+                fast = pl.tuning()["fast"]
+                for op, name, ref in ((mxfft.FORWARD, "forward", ref_f), (mxfft.ROUNDTRIP, "roundtrip", x)):
+                    fn = (lambda: pl.forward(xd, out=out, k_out=k)) if op == mxfft.FORWARD else \
+                         (lambda: pl.roundtrip(xd, out=out, k_out=k))
+                    wall, per = timed_steps(fn, steps, args.warmup, torch)
+                    assert pl.last_status() == mxfft.OK
+                    err, psnr = nrmse_psnr(out.cpu().numpy(), ref)
+                    sps = batch * steps / wall
+                    rows.append({"format": fmt, "block": B, "direction": name, "register_resident": bool(fast),
+                                 "slices_per_s": round(sps, 1), "ms_per_call": round(1e3 * wall / steps, 4),
+                                 "hbm_frac_algorithmic": round(sps * N * N * ALG_BYTES_PER_ELEM / (HBM_PEAK_GBS * 1e9), 4),
+                                 "nrmse_vs_fp64": {"mean": float("%.4g" % err.mean()), "max": float("%.4g" % err.max())},
+                                 "psnr_db_vs_fp64": round(float(psnr.mean()), 2)})
+    return {"workload": "kspace256_32x8: %d coil slices (32 x 8) of %dx%d complex64 k-space" % (batch, N, N),
+            "reference": "FP64: numpy complex128 fft2 (forward), the input (round trip)", "steps": steps,
+            "rows": rows}
+
+
+def small_slice(args, torch, mxfft, synth):
+    """The single 64^2 slice (one coil): latency of one forward call (HIP
+    events, many calls), bit parity with the oracle, NRMSE / PSNR against the
+    FP64 brute-force DFT, and the oracle's single-threaded time."""
+    import oracle
+    w = synth.WORKLOADS["kspace64_1x1"]
+    N = w["N"]
+    x = synth.kspace_batch(N, w["config"], 1, 1)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    k = torch.empty(1, dtype=torch.int32, device="cuda")
+    with mxfft.Plan(N, 1, fmt="e4m3", block=32) as pl:
+        fn = lambda: pl.forward(xd, out=out, k_out=k)   # noqa: E731
+        wall, per = timed_steps(fn, 200, 20, torch)
+        assert pl.last_status() == mxfft.OK
+        y = out.cpu().numpy()
+        kern = {}
+        pl.profile(True)
+        for _ in range(50):
+            fn()
+        for name, (n, t) in pl.kernel_times().items():
+            kern[name] = round(1e3 * t / n, 2)
+        pl.profile(False)
+    t0 = time.perf_counter()
+    st, yo, ko = oracle.transform(x, fmt=oracle.E4M3, B=32, nthreads=1)
+    t_orc = time.perf_counter() - t0
+    # FP64 brute-force DFT: separable O(N^3) matrix products in complex128
+    j = np.arange(N)
+    Fm = np.exp(-2j * np.pi * np.outer(j, j) / N)
+    ref = Fm @ x[0].astype(np.complex128) @ Fm.T
+    err, psnr = nrmse_psnr(y, ref[None])
+    return {"workload": "kspace64_1x1: one 64x64 complex64 k-space slice, MXFP8-E4M3 B=32, forward, Alg. 1 prescale",
+            "latency_us": {"p50": round(1e3 * float(np.percentile(per, 50)), 2),
+                           "p99": round(1e3 * float(np.percentile(per, 99)), 2),
+                           "what": "HIP events around one mxfft_forward call, 200 calls"},
+            "kernel_us": kern,
+            "bit_exact_vs_oracle": bool(st == oracle.OK and np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+                                        and int(k.cpu().numpy()[0]) == int(ko[0])),
+            "nrmse_vs_fp64_dft": float("%.4g" % err[0]), "psnr_db_vs_fp64_dft": round(float(psnr[0]), 2),
+            "oracle_s": round(t_orc, 4), "oracle_threads": 1}
+
+
 def serving_workload(count, seed=20251204):
     """Requests of the serving workload: Poisson arrivals at 2000 per second
     (seeded exponential gaps), size uniform over 128^2..1024^2, U{1..32}
@@ -164,30 +258,41 @@ def serving(args, torch, mxfft, synth, count=1000, slots=4, budget=64 << 30):
         pools[n] = d.repeat(4, 1, 1).contiguous()
         outs[n] = [torch.empty_like(pools[n]) for _ in range(16)]
     srv = mxfft.Server(budget, slots=slots)
-    passes = []
-    for rep in range(2):
+    slices = sum(c for _, _, c, _, _ in reqs)
+
+    def run(paced):
         tickets = []
         t0 = time.perf_counter()
         for i, (ta, n, c, op, fmt) in enumerate(reqs):
-            while time.perf_counter() - t0 < ta:
+            while paced and time.perf_counter() - t0 < ta:
                 pass
             kw = dict(fmt=fmt) if fmt == "fp16" else dict(fmt=fmt, block=args.block)
             tickets.append(srv.submit(pools[n][:c], outs[n][i % 16][:c], op=op, **kw))
         res = [srv.wait(t) for t in tickets]
-        passes.append(res)
+        assert all(r["status"] == mxfft.OK for r in res)
+        lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
+        span_s = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) / 1e3
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "slices_per_s": round(slices / span_s, 1),
+                "requests_per_s": round(count / span_s, 1)}
+
+    st0 = srv.stats()
+    cold = run(True)              # plans created as requests need them
+    st1 = srv.stats()
+    warm = run(True)              # plan pool warm
+    sat = run(False)              # every request submitted at once: the sustainable rate
     st = srv.stats()
     srv.close()
-    res = passes[-1]
-    assert all(r["status"] == mxfft.OK for r in res)
-    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
-    span_s = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) / 1e3
-    slices = sum(c for _, _, c, _, _ in reqs)
     return {"metric": "p50/p99 latency of Poisson-arriving requests (submission to completion)",
-            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_ms": round(float(lat.mean()), 3), "requests": count, "arrival_rate_per_s": 2000,
-            "slices_per_s": round(slices / span_s, 1), "requests_per_s": round(count / span_s, 1),
+            "p50_ms": warm["p50_ms"], "p99_ms": warm["p99_ms"], "mean_ms": warm["mean_ms"],
+            "requests": count, "arrival_rate_per_s": 2000,
+            "slices_per_s": warm["slices_per_s"], "requests_per_s": warm["requests_per_s"],
+            "cold": dict(cold, plans_created=st1["plans_created"] - st0["plans_created"]),
+            "warm": dict(warm, plans_created=st["plans_created"] - st1["plans_created"]),
+            "saturated": dict(sat, what="the same 1000 requests submitted back to back (no pacing)"),
             "slots": slots, "budget_GB": budget / 2 ** 30, "admitted": st["admitted"], "rejected": st["rejected"],
             "peak_plan_MB": round(st["peak_plan_bytes"] / 2 ** 20, 1), "plans_created": st["plans_created"],
+            "plans_evicted": st.get("plans_evicted"),
             "data": "pre-staged device pools; host-to-device transfer excluded"}
 
 
@@ -451,6 +556,12 @@ def main():
 
     if not args.no_rss:
         result["rss"] = rss_quality(args, torch, mxfft, x, xd, N)
+
+    if not args.no_blocks:
+        result["block_table"] = block_table(args, torch, mxfft, synth)
+
+    if not args.no_small:
+        result["small_64"] = small_slice(args, torch, mxfft, synth)
 
     if not args.no_uneven:
         result["uneven_batch"] = uneven_batch(args, torch, mxfft, synth)

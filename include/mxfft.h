@@ -248,14 +248,20 @@ uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
  * Sizes and formats without register-resident passes (n below 128 or above
  * 1024, MX blocks of 2, 64 and 128, MXFP6 blocks other than 16 and 32, FP32 at
  * every n but 512) run the generic line kernels: one work-group
- * holds `lines` whole lines of a pass in LDS, one thread per butterfly.  The
- * best `lines` depends on n, the format and the GPU, so it is measured. */
+ * holds `lines` whole lines of a pass in LDS, one thread per butterfly.  Slices
+ * of n <= 64 can instead run the whole 2D transform in one launch (one
+ * work-group per slice holding it in LDS: Alg. 1, the row and column passes,
+ * both halves of a round trip), the default there.  Which is faster, and the
+ * best `lines`, depend on n, the format, the batch and the GPU, so they are
+ * measured. */
 typedef struct {
     int32_t lines;   /* lines per work-group: a power of two, 1 <= lines <= n,
                         lines * n * 8 <= 65536; 0 = the default (8192 / n, at most n) */
     int32_t fast;    /* out: 1 when the plan runs the register-resident passes,
                         which have no such parameter (lines is then ignored) */
     double ms;       /* out (tuner): time of one forward call over its sample */
+    int32_t single;  /* n <= 64: 1 = the single-launch kernel (lines ignored),
+                        0 = the line kernels with `lines`; must be 0 for n > 64 */
 } mxfft_tuning;
 
 /* Set / read a plan's launch tuning.  Set: MXFFT_EINVAL for an invalid
@@ -266,10 +272,12 @@ mxfft_status mxfft_plan_get_tuning(mxfft_plan_t plan, mxfft_tuning* t);
 /* Autotuner.  Looks up (GPU architecture name, n, format, B) in the cache file
  * `cache_path` (NULL: no cache); on a miss, or with MXFFT_TUNE_FORCE, it times
  * one forward call of a plan of `sample` slices of synthetic data for every
- * candidate `lines` (the default and its halvings, at least 1), keeps the
- * fastest and records it in the cache (the file is rewritten whole through a
- * temporary file and a rename; entries of other keys are kept).  Allocates and
- * frees device memory and synchronises `stream`.  *out gets the choice. */
+ * candidate (the default `lines` and its halvings, at least 1; for n <= 64
+ * also the single-launch kernel), keeps the fastest and records it in the
+ * cache (the file is rewritten whole through a temporary file and a rename;
+ * entries of other keys are kept).  *out gets the choice; its `lines` is the
+ * best line-kernel candidate even when `single` wins.  Allocates and frees
+ * device memory and synchronises `stream`. */
 #define MXFFT_TUNE_FORCE 0x1u
 mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const char* cache_path,
                         uint32_t tune_flags, mxfft_tuning* out, void* stream);
@@ -277,7 +285,7 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
 /* Host-only cache lookup (no GPU call): MXFFT_OK and *out filled when the file
  * holds an entry for (arch, n, p->format, p->block), MXFFT_EINVAL when it does
  * not or the file cannot be read.  The file is plain text, one entry per line:
- *   {"arch": "gfx950", "n": 256, "format": 0, "block": 32, "lines": 8, "ms": 0.1}
+ *   {"arch": "gfx950", "n": 64, "format": 0, "block": 32, "lines": 8, "ms": 0.1, "single": 1}
  * (format as mxfft_format; block 0 for FP16/BF16/FP32). */
 mxfft_status mxfft_tune_cache_lookup(const char* cache_path, const char* arch, int32_t n,
                                      const mxfft_params* p, mxfft_tuning* out);

@@ -82,10 +82,19 @@ __device__ __forceinline__ int renorm_exp(uint32_t amax_key)
 }
 
 // Maximum over groups of `width` consecutive lanes (width a power of two,
-// 1 <= width <= 64); every lane of a group must be active.
+// 1 <= width <= 64) of non-negative values given as bits, every lane
+// receiving its group's value; every lane of a group must be active.  Inside
+// a DPP row of 16 lanes: quad_perm swaps 1 and 2 lanes apart, then the
+// half-row mirror (lane i <-> 7 - i) and the row mirror (i <-> 15 - i), each
+// of which meets the other half of the group reduced so far; lane permutes
+// beyond 16.
 __device__ __forceinline__ uint32_t group_max(uint32_t v, int width)
 {
-    for (int o = 1; o < width; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    if (width >= 2) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+    if (width >= 4) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+    if (width >= 8) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+    if (width >= 16) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
+    for (int o = 16; o < width; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
 

@@ -98,6 +98,8 @@ struct mxfft_plan_s {
     const int32_t* last_status = nullptr;
     // generic line kernels: lines per work-group (0 = line_lines_per_group)
     int lines = 0;
+    // n <= 64: the whole transform in one launch instead of the line kernels
+    bool single = false;
     // sizing only: nothing is allocated or uploaded
     bool dry = false;
     // register-resident passes: twiddles at [h + j]
@@ -128,9 +130,9 @@ struct mxfft_plan_s {
 
 namespace {
 
-enum Role { ROLE_STATS = 0, ROLE_ROW, ROLE_COL, ROLE_INV_ROW, ROLE_INV_COL, ROLE_FIX, ROLE_COUNT };
+enum Role { ROLE_STATS = 0, ROLE_ROW, ROLE_COL, ROLE_INV_ROW, ROLE_INV_COL, ROLE_FIX, ROLE_SMALL, ROLE_COUNT };
 const char* const kRoleNames[ROLE_COUNT] = {"prescale_stats", "row_pass", "column_pass", "inverse_row_pass",
-                                            "inverse_column_pass", "row_redo"};
+                                            "inverse_column_pass", "row_redo", "single_launch"};
 
 hipEvent_t take_event(mxfft_plan_s* pl)
 {
@@ -398,6 +400,41 @@ mxk::PrescaleArgs prescale_args(const mxfft_plan_s* pl)
     return pa;
 }
 
+int inverse_row_kind(const mxfft_plan_s* pl);
+
+// The whole transform of slices of n <= 64 in one launch.  op 0 forward,
+// 1 inverse, 2 round trip; stats: Alg. 1 on the input (else k from k_in or 0).
+mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, void* out, int op, bool stats,
+                   const int32_t* k_in, int32_t* k_out, int kin_mul, int kout_mul, int kout_add, bool capture,
+                   int batch, hipStream_t s)
+{
+    LaunchTimer timer(pl, ROLE_SMALL, s);
+    mxk::SmallArgs g{};
+    g.a.src = (const float2*)in;
+    g.a.dst = (float2*)out;
+    g.a.k_out = k_out;
+    g.a.tw = pl->d_tw;
+    g.a.tw_exp = pl->d_tw_exp;
+    std::memcpy(g.a.tw_exp_off, pl->tw_exp_off, sizeof(g.a.tw_exp_off));
+    g.a.n = pl->n;
+    g.a.logn = pl->logn;
+    g.a.cb = pl->cb;
+    g.a.logcb = pl->logcb;
+    g.a.cap_mant = capture ? pl->d_cap_mant : nullptr;
+    g.a.cap_exp = capture ? pl->d_cap_exp : nullptr;
+    g.pa = prescale_args(pl);
+    g.op = op;
+    g.stats = stats ? 1 : 0;
+    g.kin_mul = kin_mul;
+    g.kout_mul = kout_mul;
+    g.kout_add = kout_add;
+    g.raw_inverse_rows = (op == 2 && inverse_row_kind(pl) == mxk::ROW_RAW) ? 1 : 0;
+    g.k_in = k_in;
+    g.kp = stats ? w.kp : nullptr;
+    g.status = stats ? w.status : nullptr;
+    return mxk::launch_small(pl->mode, g, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
+}
+
 // Literal Alg. 1: a statistics pass over the input, then kp per slice.
 mxfft_status stats(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, int batch, hipStream_t s)
 {
@@ -506,6 +543,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
 
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
+    pl->single = !pl->fast && n <= mxk::kSmallN;
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw_exp, tw_exp.size());
@@ -647,7 +685,9 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     const int32_t* kp = pre ? w.kp : nullptr;
     const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
     const bool cap = pl->d_cap_mant != nullptr && batch <= pl->max_batch;   // capture buffers hold max_batch
-    if (pre && pl->fused) {
+    if (pl->single) {
+        MX_TRY(small(pl, w, in, out, 0, pre, nullptr, k_out, 1, kout_mul, 0, cap, batch, s));
+    } else if (pre && pl->fused) {
         MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
@@ -689,7 +729,9 @@ mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t b
         kp = w.kp;
         kin_mul = 1;
     }
-    if (pre && pl->fused) {
+    if (pl->single) {
+        MX_TRY(small(pl, w, in, out, 1, pre, pre ? nullptr : k_in, nullptr, kin_mul, -1, kout_add, false, batch, s));
+    } else if (pre && pl->fused) {
         MX_TRY(row_with_stats(pl, w, in, nullptr, 1, batch, s));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
@@ -712,16 +754,20 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
     const int32_t* kp = pre ? w.kp : nullptr;
-    if (pre && pl->fused) {
-        MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
+    if (pl->single) {
+        MX_TRY(small(pl, w, in, out, 2, pre, nullptr, k_out, 1, -1, -2 * pl->logn, false, batch, s));
     } else {
-        if (pre) MX_TRY(stats(pl, w, in, batch, s));
-        MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+        if (pre && pl->fused) {
+            MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
+            MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
+        } else {
+            if (pre) MX_TRY(stats(pl, w, in, batch, s));
+            MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+            MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+        }
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
+        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     }
-    MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
-    MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     pl->last_status = w.status;
@@ -867,7 +913,9 @@ mxfft_status mxfft_plan_set_tuning(mxfft_plan_t pl, const mxfft_tuning* t)
     if (!pl || !t) return MXFFT_EINVAL;
     const int r = t->lines;
     if (r != 0 && (r < 1 || r > pl->n || (r & (r - 1)) != 0 || (long)r * pl->n * 8 > 65536)) return MXFFT_EINVAL;
+    if (t->single != 0 && (t->single != 1 || pl->n > mxk::kSmallN)) return MXFFT_EINVAL;
     pl->lines = r;
+    pl->single = !pl->fast && t->single == 1;
     return MXFFT_OK;
 }
 
@@ -877,6 +925,7 @@ mxfft_status mxfft_plan_get_tuning(mxfft_plan_t pl, mxfft_tuning* t)
     t->lines = pl->fast ? 0 : (pl->lines ? pl->lines : mxk::line_lines_per_group(pl->n));
     t->fast = pl->fast ? 1 : 0;
     t->ms = 0.0;
+    t->single = pl->single ? 1 : 0;
     return MXFFT_OK;
 }
 

@@ -139,6 +139,22 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
                               int32_t* slice_status, const PrescaleArgs& pa, int32_t* kadd, int32_t* fix_list,
                               int32_t* fix_count, int32_t* k_out, hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
+
+// Single-launch transform of slices of n <= kSmallN (one work-group per
+// slice: Alg. 1, all passes and the output in LDS).
+constexpr int kSmallN = 64;
+struct SmallArgs {
+    LineArgs a;                // tables, n, block, src, dst, k_out, capture pointers
+    PrescaleArgs pa;
+    int32_t op;                // 0 forward, 1 inverse, 2 round trip
+    int32_t stats;             // Alg. 1 on the input; else k from k_in (or 0)
+    int32_t kin_mul, kout_mul, kout_add;  // input x 2^(kin_mul k); output x 2^(kout_mul k + kout_add)
+    int32_t raw_inverse_rows;  // round trip: the inverse row pass without the input MX encode
+    const int32_t* k_in;
+    int32_t* kp;               // per-slice k (stats), or nullptr
+    int32_t* status;           // per-slice status (stats), or nullptr
+};
+hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s);
 int line_lines_per_group(int n);
 // Debug capture from the register-resident MX intermediate: element values
 // [slice][row][col] and exponents [slice][col][row block] (plus kadd[slice]

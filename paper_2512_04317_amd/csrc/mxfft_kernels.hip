@@ -122,6 +122,202 @@ __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x
     }
 }
 
+// Shared state of Alg. 1 for one slice, worked on by one 256-thread work-group.
+struct Alg1Smem {
+    uint32_t hist[kStatsBins];        // nonzero finite |x| per binade floor(log2 |x|) + kBinOffset
+    unsigned long long m2, lo_max, hi_min, m2_cut;
+    uint32_t count, maxc, nonfin, below;
+    int refine, thresh, bin_lo, bin_hi, emin, emax;
+    double tp;
+    uint32_t wave[16];
+    int32_t k, st;                    // result: prescale exponent and status
+};
+
+// Clear the statistics (every thread; the caller synchronises afterwards).
+__device__ void alg1_init(Alg1Smem& S)
+{
+    if (threadIdx.x == 0) {
+        S.m2 = 0; S.count = 0; S.maxc = 0; S.nonfin = 0; S.refine = 0; S.thresh = 0;
+        S.emin = 0; S.emax = 0; S.bin_lo = -1; S.bin_hi = -1; S.k = 0; S.st = 0;
+    }
+    for (int i = threadIdx.x; i < kStatsBins; i += blockDim.x) S.hist[i] = 0;
+}
+
+// Alg. 1 from complete statistics in S (hist, count, m2, maxc, nonfin):
+// the tau-percentile's order statistics located in the histogram, refined
+// exactly from the slice xs[0..nn) when needed, then k = clip(max(k1, k2)).
+// Every thread of the work-group (64 to 1024 threads) calls it; S.k and S.st
+// hold the result for all of them on return.
+__device__ void alg1_finish(Alg1Smem& S, const float2* __restrict__ xs, int nn, const PrescaleArgs& pa)
+{
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const uint32_t n = S.count;
+    const double pos = ((double)(n ? n - 1 : 0) * pa.tau) / 100.0;
+    long long ri = (long long)floor(pos);
+    if (n && ri > (long long)n - 1) ri = (long long)n - 1;
+    const double fr = pos - (double)ri;
+    if (n && !S.nonfin) {
+        // binades holding the order statistics ri and ri + 1 (S[n] := S[n-1]):
+        // the bin b with (count below b) <= r < (count up to b).  Each thread
+        // owns bpt consecutive bins; their counts are prefix-summed over the
+        // work-group (wave scans, then the wave totals)
+        constexpr int MAXBPT = (kStatsBins + 63) / 64;
+        const int bpt = ((int)kStatsBins + (int)blockDim.x - 1) / (int)blockDim.x;
+        const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
+        const int b0 = tid * bpt;
+        uint32_t h[MAXBPT], mine = 0;
+        for (int j = 0; j < MAXBPT; j++) {
+            h[j] = (j < bpt && b0 + j < kStatsBins) ? S.hist[b0 + j] : 0u;
+            mine += h[j];
+        }
+        uint32_t incl = mine;                        // inclusive scan within the wave
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) S.wave[wave] = incl;
+        __syncthreads();
+        uint32_t below = incl - mine;                // counts of all lower bins
+        for (int w = 0; w < wave; w++) below += S.wave[w];
+        long long cum = below;
+        for (int j = 0; j < MAXBPT; j++) {
+            if (cum <= ri && ri < cum + (long long)h[j]) S.bin_lo = b0 + j;
+            if (cum <= r1 && r1 < cum + (long long)h[j]) S.bin_hi = b0 + j;
+            cum += h[j];
+        }
+    }
+    __syncthreads();
+    // Alg. 1's tail floor: k2 = the smallest k with max(p, 1e-30) 2^k >= tau_min,
+    // i.e. min(k2(p), k2(1e-30)).  With p = fp 2^ep and tau_min = ft 2^et
+    // (frexp mantissas in [1/2, 1)), k2(p) = et - ep + (fp < ft).  The binade of
+    // p gives ep; fp < ft is needed only when tau_min is not a power of two.
+    int et;
+    const double ft = frexp(pa.tau_min, &et);
+    if (tid == 0 && n && !S.nonfin) {
+        S.refine = (S.bin_lo != S.bin_hi) && (fr != 0.0);
+        S.thresh = !S.refine && ft != 0.5;
+        S.lo_max = 0;
+        S.hi_min = ~0ull;
+        S.below = 0;
+        S.m2_cut = 0;
+        if (S.thresh) {
+            // p lies in binade S.bin_lo; T' = ft 2^ep is the threshold in it, and
+            // m = RN(sqrt(m2)) < T' iff m2 < the smallest FP64 x with
+            // RN(sqrt(x)) >= T' (sqrt and rounding are monotone)
+            const double tp = ldexp(ft, S.bin_lo - kBinOffset + 1);
+            double xq = tp * tp;
+            if (__dsqrt_rn(xq) >= tp) {
+                for (int it = 0; it < 64; it++) {
+                    const double y = __longlong_as_double(__double_as_longlong(xq) - 1);
+                    if (__dsqrt_rn(y) >= tp) xq = y;
+                    else break;
+                }
+            } else {
+                for (int it = 0; it < 64 && __dsqrt_rn(xq) < tp; it++)
+                    xq = __longlong_as_double(__double_as_longlong(xq) + 1);
+            }
+            S.m2_cut = (unsigned long long)__double_as_longlong(xq);
+            S.tp = tp;
+        }
+    }
+    __syncthreads();
+    if (S.refine) {
+        // the two order statistics sit in different binades: S[ri] is the largest
+        // value of the lower one and S[ri+1] the smallest of the upper one
+        for (int i = tid; i < nn; i += blockDim.x) {
+            const float2 v = xs[i];
+            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+            if (m2 > 0.0) {
+                const int bin = ((((int)(b >> 52)) - 1023) >> 1) + kBinOffset;
+                if (bin == S.bin_lo) atomicMax(&S.lo_max, b);
+                if (bin == S.bin_hi) atomicMin(&S.hi_min, b);
+            }
+        }
+        __syncthreads();
+    } else if (S.thresh) {
+        // count the values below T', with the largest below and the smallest
+        // at or above it (the two order statistics when T' falls between them)
+        const unsigned long long cut = S.m2_cut;
+        uint32_t below = 0;
+        for (int i = tid; i < nn; i += blockDim.x) {
+            const float2 v = xs[i];
+            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+            if (m2 > 0.0) {
+                if (b < cut) {
+                    below++;
+                    atomicMax(&S.lo_max, b);
+                } else {
+                    atomicMin(&S.hi_min, b);
+                }
+            }
+        }
+        atomicAdd(&S.below, below);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int32_t k = 0, st = 0;
+        if (S.nonfin) {
+            st = -4;  // MXFFT_ENONFINITE
+        } else if (n) {
+            const double amax = __dsqrt_rn(__longlong_as_double((long long)S.m2));
+            const int k1 = round_log2_ratio(pa.target, amax > 1e-30 ? amax : 1e-30);
+            // k2(v) for v > 0
+            auto k2_of = [&](double v) -> long long {
+                int ev;
+                const double fv = frexp(v, &ev);
+                return (long long)et - ev + (fv < ft ? 1 : 0);
+            };
+            long long k2p;
+            if (S.refine) {
+                const double lo = __dsqrt_rn(__longlong_as_double((long long)S.lo_max));
+                const double hi = __dsqrt_rn(__longlong_as_double((long long)S.hi_min));
+                const double d = hi - lo;
+                const double fd = fr * d;
+                k2p = k2_of(lo + fd);
+            } else {
+                // p in binade lp: fp >= 1/2 >= ft for a power-of-two tau_min
+                const int lp = S.bin_lo - kBinOffset;
+                bool under = false;  // p < T' (i.e. fp < ft)
+                if (S.thresh) {
+                    const long long c = S.below;
+                    const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
+                    if (fr == 0.0 || r1 == ri) {
+                        under = c >= ri + 1;             // p = S[ri]
+                    } else if (c <= ri) {
+                        under = false;                   // T' <= S[ri] <= p
+                    } else if (c >= ri + 2) {
+                        under = true;                    // p <= S[ri+1] < T'
+                    } else {
+                        // S[ri] < T' <= S[ri+1]: p exactly
+                        const double lo = __dsqrt_rn(__longlong_as_double((long long)S.lo_max));
+                        const double hi = __dsqrt_rn(__longlong_as_double((long long)S.hi_min));
+                        const double d = hi - lo;
+                        const double fd = fr * d;
+                        under = (lo + fd) < S.tp;
+                    }
+                }
+                k2p = (long long)et - (lp + 1) + (under ? 1 : 0);
+            }
+            const long long k2 = min(k2p, k2_of(1e-30));
+            long long kk = max((long long)k1, k2);
+            kk = min(max(kk, (long long)pa.k_min), (long long)pa.k_max);
+            k = (int32_t)kk;
+            // every component scaled by 2^k must stay finite in FP32
+            if (S.maxc) {
+                const int e = __builtin_amdgcn_frexp_expf(__uint_as_float(S.maxc)) - 1;
+                if ((long long)e + kk > 127) st = -5;  // MXFFT_ERANGE
+            }
+        }
+        S.k = st ? INT32_MIN : k;
+        S.st = st;
+    }
+    __syncthreads();
+}
+
 // Alg. 1 for one slice from its chunk statistics (one work-group per slice).
 // With kadd given (chunk statistics from the row pass, which ran unscaled):
 // also decide whether that row pass stands for the scaled one -- every block
@@ -134,24 +330,11 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
                                                       int32_t* __restrict__ fix_list, int32_t* __restrict__ fix_count,
                                                       int32_t* __restrict__ k_out)
 {
-#pragma clang fp contract(off)
-    __shared__ uint32_t hist[kStatsBins];
-    __shared__ unsigned long long s_m2, s_lo_max, s_hi_min;
-    __shared__ uint32_t s_count, s_maxc, s_nonfin;
-    __shared__ int s_refine, s_thresh, s_bin_lo, s_bin_hi, s_emin, s_emax;
-    __shared__ unsigned long long s_m2_cut;
-    __shared__ uint32_t s_below;
-    __shared__ double s_tp;
+    __shared__ Alg1Smem S;
     const int tid = threadIdx.x, slice = blockIdx.x;
     const float2* xs = x + (size_t)slice * nn;
     const StatPart* pt = parts + (size_t)slice * chunks;
-
-    __shared__ uint32_t s_wave[4];
-    if (tid == 0) {
-        s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; s_refine = 0; s_thresh = 0;
-        s_emin = 0; s_emax = 0; s_bin_lo = -1; s_bin_hi = -1;
-    }
-    for (int i = tid; i < kStatsBins; i += blockDim.x) hist[i] = 0;
+    alg1_init(S);
     __syncthreads();
     // histograms of all chunks, read as one coalesced sweep (many loads in
     // flight per thread) and summed per bin in LDS
@@ -162,186 +345,28 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
         for (int w = tid; w < total; w += blockDim.x) {
             const int c = w / kStatsBins, i = w - c * kStatsBins;
             const uint32_t h = pt[c].hist[i];
-            if (h) atomicAdd(&hist[i], h);
+            if (h) atomicAdd(&S.hist[i], h);
             cnt += h;
         }
-        atomicAdd(&s_count, cnt);
+        atomicAdd(&S.count, cnt);
     }
     for (int c = tid; c < chunks; c += blockDim.x) {
-        atomicMax(&s_m2, pt[c].max_m2);
-        atomicMax(&s_maxc, pt[c].max_comp);
-        atomicOr(&s_nonfin, pt[c].nonfinite);
-        atomicMin(&s_emin, pt[c].emin);
-        atomicMax(&s_emax, pt[c].emax);
+        atomicMax(&S.m2, pt[c].max_m2);
+        atomicMax(&S.maxc, pt[c].max_comp);
+        atomicOr(&S.nonfin, pt[c].nonfinite);
+        atomicMin(&S.emin, pt[c].emin);
+        atomicMax(&S.emax, pt[c].emax);
     }
     __syncthreads();
-
-    const uint32_t n = s_count;
-    const double pos = ((double)(n ? n - 1 : 0) * pa.tau) / 100.0;
-    long long ri = (long long)floor(pos);
-    if (n && ri > (long long)n - 1) ri = (long long)n - 1;
-    const double fr = pos - (double)ri;
-    if (n && !s_nonfin) {
-        // binades holding the order statistics ri and ri + 1 (S[n] := S[n-1]):
-        // the bin b with (count below b) <= r < (count up to b).  Each thread
-        // owns BPT consecutive bins; their counts are prefix-summed over the
-        // work-group (wave scans, then the four wave totals)
-        static_assert(kStatsBins <= 2 * 256, "two bins per thread");
-        constexpr int BPT = 2;
-        const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
-        const int b0 = tid * BPT;
-        uint32_t h[BPT], mine = 0;
-        for (int j = 0; j < BPT; j++) {
-            h[j] = (b0 + j < kStatsBins) ? hist[b0 + j] : 0u;
-            mine += h[j];
-        }
-        uint32_t incl = mine;                        // inclusive scan within the wave
-        const int lane = tid & 63, wave = tid >> 6;
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        if (lane == 63) s_wave[wave] = incl;
-        __syncthreads();
-        uint32_t below = incl - mine;                // counts of all lower bins
-        for (int w = 0; w < wave; w++) below += s_wave[w];
-        long long cum = below;
-        for (int j = 0; j < BPT; j++) {
-            if (cum <= ri && ri < cum + (long long)h[j]) s_bin_lo = b0 + j;
-            if (cum <= r1 && r1 < cum + (long long)h[j]) s_bin_hi = b0 + j;
-            cum += h[j];
-        }
-    }
-    __syncthreads();
-    // Alg. 1's tail floor: k2 = the smallest k with max(p, 1e-30) 2^k >= tau_min,
-    // i.e. min(k2(p), k2(1e-30)).  With p = fp 2^ep and tau_min = ft 2^et
-    // (frexp mantissas in [1/2, 1)), k2(p) = et - ep + (fp < ft).  The binade of
-    // p gives ep; fp < ft is needed only when tau_min is not a power of two.
-    int et;
-    const double ft = frexp(pa.tau_min, &et);
-    if (tid == 0 && n && !s_nonfin) {
-        s_refine = (s_bin_lo != s_bin_hi) && (fr != 0.0);
-        s_thresh = !s_refine && ft != 0.5;
-        s_lo_max = 0;
-        s_hi_min = ~0ull;
-        s_below = 0;
-        s_m2_cut = 0;
-        if (s_thresh) {
-            // p lies in binade s_bin_lo; T' = ft 2^ep is the threshold in it, and
-            // m = RN(sqrt(m2)) < T' iff m2 < the smallest FP64 x with
-            // RN(sqrt(x)) >= T' (sqrt and rounding are monotone)
-            const double tp = ldexp(ft, s_bin_lo - kBinOffset + 1);
-            double xq = tp * tp;
-            if (__dsqrt_rn(xq) >= tp) {
-                for (int it = 0; it < 64; it++) {
-                    const double y = __longlong_as_double(__double_as_longlong(xq) - 1);
-                    if (__dsqrt_rn(y) >= tp) xq = y;
-                    else break;
-                }
-            } else {
-                for (int it = 0; it < 64 && __dsqrt_rn(xq) < tp; it++)
-                    xq = __longlong_as_double(__double_as_longlong(xq) + 1);
-            }
-            s_m2_cut = (unsigned long long)__double_as_longlong(xq);
-            s_tp = tp;
-        }
-    }
-    __syncthreads();
-    if (s_refine) {
-        // the two order statistics sit in different binades: S[ri] is the largest
-        // value of the lower one and S[ri+1] the smallest of the upper one
-        for (int i = tid; i < nn; i += blockDim.x) {
-            const float2 v = xs[i];
-            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
-            if (m2 > 0.0) {
-                const int bin = ((((int)(b >> 52)) - 1023) >> 1) + kBinOffset;
-                if (bin == s_bin_lo) atomicMax(&s_lo_max, b);
-                if (bin == s_bin_hi) atomicMin(&s_hi_min, b);
-            }
-        }
-        __syncthreads();
-    } else if (s_thresh) {
-        // count the values below T', with the largest below and the smallest
-        // at or above it (the two order statistics when T' falls between them)
-        const unsigned long long cut = s_m2_cut;
-        uint32_t below = 0;
-        for (int i = tid; i < nn; i += blockDim.x) {
-            const float2 v = xs[i];
-            const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-            const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
-            if (m2 > 0.0) {
-                if (b < cut) {
-                    below++;
-                    atomicMax(&s_lo_max, b);
-                } else {
-                    atomicMin(&s_hi_min, b);
-                }
-            }
-        }
-        atomicAdd(&s_below, below);
-        __syncthreads();
-    }
+    alg1_finish(S, xs, nn, pa);
     if (tid == 0) {
-        int32_t k = 0, st = 0;
-        if (s_nonfin) {
-            st = -4;  // MXFFT_ENONFINITE
-        } else if (n) {
-            const double amax = __dsqrt_rn(__longlong_as_double((long long)s_m2));
-            const int k1 = round_log2_ratio(pa.target, amax > 1e-30 ? amax : 1e-30);
-            // k2(v) for v > 0
-            auto k2_of = [&](double v) -> long long {
-                int ev;
-                const double fv = frexp(v, &ev);
-                return (long long)et - ev + (fv < ft ? 1 : 0);
-            };
-            long long k2p;
-            if (s_refine) {
-                const double lo = __dsqrt_rn(__longlong_as_double((long long)s_lo_max));
-                const double hi = __dsqrt_rn(__longlong_as_double((long long)s_hi_min));
-                const double d = hi - lo;
-                const double fd = fr * d;
-                k2p = k2_of(lo + fd);
-            } else {
-                // p in binade lp: fp >= 1/2 >= ft for a power-of-two tau_min
-                const int lp = s_bin_lo - kBinOffset;
-                bool under = false;  // p < T' (i.e. fp < ft)
-                if (s_thresh) {
-                    const long long c = s_below;
-                    const long long r1 = (ri + 1 < (long long)n) ? ri + 1 : ri;
-                    if (fr == 0.0 || r1 == ri) {
-                        under = c >= ri + 1;             // p = S[ri]
-                    } else if (c <= ri) {
-                        under = false;                   // T' <= S[ri] <= p
-                    } else if (c >= ri + 2) {
-                        under = true;                    // p <= S[ri+1] < T'
-                    } else {
-                        // S[ri] < T' <= S[ri+1]: p exactly
-                        const double lo = __dsqrt_rn(__longlong_as_double((long long)s_lo_max));
-                        const double hi = __dsqrt_rn(__longlong_as_double((long long)s_hi_min));
-                        const double d = hi - lo;
-                        const double fd = fr * d;
-                        under = (lo + fd) < s_tp;
-                    }
-                }
-                k2p = (long long)et - (lp + 1) + (under ? 1 : 0);
-            }
-            const long long k2 = min(k2p, k2_of(1e-30));
-            long long kk = max((long long)k1, k2);
-            kk = min(max(kk, (long long)pa.k_min), (long long)pa.k_max);
-            k = (int32_t)kk;
-            // every component scaled by 2^k must stay finite in FP32
-            if (s_maxc) {
-                const int e = __builtin_amdgcn_frexp_expf(__uint_as_float(s_maxc)) - 1;
-                if ((long long)e + kk > 127) st = -5;  // MXFFT_ERANGE
-            }
-        }
-        kp[slice] = st ? INT32_MIN : k;
+        const int32_t k = S.k, st = S.st;
+        kp[slice] = k;
         slice_status[slice] = st;
-        if (k_out) k_out[slice] = st ? INT32_MIN : k;
+        if (k_out) k_out[slice] = k;
         if (kadd) {
-            const bool inside = s_emin >= kEquivLo && s_emax <= kEquivHi && s_emin + (long long)k >= kEquivLo &&
-                                s_emax + (long long)k <= kEquivHi;
+            const bool inside = S.emin >= kEquivLo && S.emax <= kEquivHi && S.emin + (long long)k >= kEquivLo &&
+                                S.emax + (long long)k <= kEquivHi;
             if (st == 0 && !inside) {
                 kadd[slice] = 0;
                 fix_list[atomicAdd(fix_count, 1)] = slice;
@@ -609,6 +634,189 @@ hipError_t launch_capture_mx(int mode, int n, int cb, const uint32_t* codes, con
     const long pairs = (long)batch * n * (n / 2);
     hipLaunchKernelGGL(k_capture_mx, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, fmt8, off, n, logcb,
                        codes, exps, kadd, pairs, mant, cap_exp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Single-launch transform of small slices (n <= 64): one work-group per slice
+// holds the slice in LDS (row pitch n + 1, so column accesses spread over the
+// banks) and runs Alg. 1, every 1D pass (rows, then columns; both halves of a
+// round trip) and the output scaling with the same per-element arithmetic as
+// the line kernels.
+// ---------------------------------------------------------------------------
+
+constexpr int kSmallMaxN = kSmallN;
+constexpr int kSmallPitch = kSmallMaxN + 1;
+
+// One 1D pass over the n lines of the slice in buf: rows (element e of line r
+// at r * pitch + e) or columns (at e * pitch + r).  encode: MX-encode the
+// pass input (blocks of cb consecutive values along the line); the 16-bit
+// forms round it to the format instead, and round the pass result.  With
+// cap_mant set, the encoded input's element values and block exponents are
+// recorded (debug capture of the forward's column pass).
+template <int MODE>
+__device__ void small_pass(const LineArgs& a, float2* buf, bool cols, bool encode, float2* cap_mant,
+                           int32_t* cap_exp, int slice)
+{
+    const int N = a.n, logn = a.logn, tid = threadIdx.x, total = N * N;
+    auto at = [&](int r, int e) -> float2& { return cols ? buf[e * kSmallPitch + r] : buf[r * kSmallPitch + e]; };
+    if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
+        for (int idx = tid; idx < total; idx += blockDim.x) {
+            float2& v = at(idx >> logn, idx & (N - 1));
+            v = make_float2(mxd::round16<MODE>(v.x), mxd::round16<MODE>(v.y));
+        }
+        __syncthreads();
+    } else if constexpr (MODE != MODE_FP32) {
+        if (encode) {
+            for (int idx = tid; idx < total; idx += blockDim.x) {
+                const int r = idx >> logn, e = idx & (N - 1);
+                float2 v = at(r, e);
+                const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
+                const int E = mxd::block_exp<MODE>(am);
+                const float qx = mxd::quant<MODE>(ldexpf(v.x, -E)), qy = mxd::quant<MODE>(ldexpf(v.y, -E));
+                if (cap_mant) {
+                    // line r is column r, element e its row
+                    cap_mant[((size_t)slice * N + e) * N + r] = make_float2(qx, qy);
+                    if ((e & (a.cb - 1)) == 0)
+                        cap_exp[((size_t)slice * N + r) * (N >> a.logcb) + (e >> a.logcb)] = E;
+                }
+                at(r, e) = make_float2(ldexpf(qx, E), ldexpf(qy, E));
+            }
+            __syncthreads();
+        }
+    }
+    // bit reversal (decimation in time)
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        const int r = idx >> logn, e = idx & (N - 1);
+        const int rev = (int)(__brev((unsigned)e) >> (32 - logn));
+        if (rev > e) {
+            const float2 t = at(r, e);
+            at(r, e) = at(r, rev);
+            at(r, rev) = t;
+        }
+    }
+    __syncthreads();
+    const int half = N >> 1, nbf = total >> 1;
+    for (int st = 1; st <= logn; st++) {
+        const int h = 1 << (st - 1);
+        for (int b = tid; b < nbf; b += blockDim.x) {
+            const int r = b >> (logn - 1);
+            const int t = b & (half - 1);
+            const int g = t >> (st - 1), j = t & (h - 1);
+            const int iu = (g << st) + j, iv = iu + h;
+            float2 y0, y1;
+            butterfly<MODE>(a, st, j, at(r, iu), at(r, iv), y0, y1);
+            at(r, iu) = y0;
+            at(r, iv) = y1;
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
+        for (int idx = tid; idx < total; idx += blockDim.x) {
+            float2& v = at(idx >> logn, idx & (N - 1));
+            v = make_float2(mxd::round16<MODE>(v.x), mxd::round16<MODE>(v.y));
+        }
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_small(SmallArgs g)
+{
+    __shared__ float2 buf[kSmallMaxN * kSmallPitch];
+    __shared__ Alg1Smem S;
+    const int tid = threadIdx.x, slice = blockIdx.x, N = g.a.n, logn = g.a.logn, nn = N * N;
+    const float2* xs = g.a.src + (size_t)slice * nn;
+    if (g.stats) {
+        alg1_init(S);
+        __syncthreads();
+    }
+    // load; Alg. 1's statistics on the way (|x|^2 in FP64, binade histogram,
+    // maximum, largest part, non-finite check)
+    {
+        unsigned long long mm = 0;
+        uint32_t cnt = 0, mc = 0, nf = 0;
+        for (int i = tid; i < nn; i += blockDim.x) {
+            const float2 v = xs[i];
+            buf[(i >> logn) * kSmallPitch + (i & (N - 1))] = v;
+            if (g.stats) {
+                const uint32_t br = __float_as_uint(v.x), bi = __float_as_uint(v.y);
+                const uint32_t bad = ((br & 0x7f800000u) == 0x7f800000u) | ((bi & 0x7f800000u) == 0x7f800000u);
+                nf |= bad;
+                mc = max(mc, max(br & 0x7fffffffu, bi & 0x7fffffffu));
+                const double m2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                const unsigned long long b = (unsigned long long)__double_as_longlong(m2);
+                if (!bad && m2 > 0.0) {
+                    cnt++;
+                    mm = max(mm, b);
+                    atomicAdd(&S.hist[((((int)(b >> 52)) - 1023) >> 1) + kBinOffset], 1u);
+                }
+            }
+        }
+        if (g.stats) {
+            atomicMax(&S.m2, mm);
+            atomicAdd(&S.count, cnt);
+            atomicMax(&S.maxc, mc);
+            atomicOr(&S.nonfin, nf);
+        }
+    }
+    __syncthreads();
+    int k = 0;
+    if (g.stats) {
+        alg1_finish(S, xs, nn, g.pa);
+        k = S.k;
+        if (tid == 0) {
+            if (g.kp) g.kp[slice] = k;
+            if (g.status) g.status[slice] = S.st;
+            if (g.a.k_out) g.a.k_out[slice] = k;
+        }
+    } else {
+        k = g.k_in ? g.k_in[slice] : 0;
+        if (tid == 0 && g.a.k_out) g.a.k_out[slice] = k;
+    }
+    if (k == INT32_MIN) k = 0;  // failed slice: output undefined, keep it finite-safe
+    const int kin = g.kin_mul * k;
+    if (kin) {
+        for (int i = tid; i < nn; i += blockDim.x) {
+            float2& v = buf[(i >> logn) * kSmallPitch + (i & (N - 1))];
+            v = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
+        }
+        __syncthreads();
+    }
+    constexpr bool MX = MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16;
+    LineArgs a = g.a;
+    a.inverse = g.op == 1;
+    small_pass<MODE>(a, buf, false, MX, nullptr, nullptr, slice);
+    small_pass<MODE>(a, buf, true, MX, g.op == 0 ? g.a.cap_mant : nullptr, g.a.cap_exp, slice);
+    if (g.op == 2) {
+        a.inverse = 1;
+        small_pass<MODE>(a, buf, false, MX && !g.raw_inverse_rows, nullptr, nullptr, slice);
+        small_pass<MODE>(a, buf, true, MX, nullptr, nullptr, slice);
+    }
+    const int kout = g.kout_mul * k + g.kout_add;
+    float2* ys = g.a.dst + (size_t)slice * nn;
+    for (int i = tid; i < nn; i += blockDim.x) {
+        const float2 v = buf[(i >> logn) * kSmallPitch + (i & (N - 1))];
+        ys[i] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));
+    }
+}
+
+hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s)
+{
+    if (g.a.n > kSmallMaxN) return hipErrorInvalidValue;
+    // one thread per butterfly of a pass (at least one wave)
+    const int bf = g.a.n * g.a.n / 2;
+    const dim3 grid(batch), block(bf < 64 ? 64 : bf > 1024 ? 1024 : bf);
+    switch (mode) {
+    case MODE_E4M3: hipLaunchKernelGGL(k_small<MODE_E4M3>, grid, block, 0, s, g); break;
+    case MODE_E5M2: hipLaunchKernelGGL(k_small<MODE_E5M2>, grid, block, 0, s, g); break;
+    case MODE_E2M3: hipLaunchKernelGGL(k_small<MODE_E2M3>, grid, block, 0, s, g); break;
+    case MODE_E3M2: hipLaunchKernelGGL(k_small<MODE_E3M2>, grid, block, 0, s, g); break;
+    case MODE_FP16: hipLaunchKernelGGL(k_small<MODE_FP16>, grid, block, 0, s, g); break;
+    case MODE_BF16: hipLaunchKernelGGL(k_small<MODE_BF16>, grid, block, 0, s, g); break;
+    case MODE_FP32: hipLaunchKernelGGL(k_small<MODE_FP32>, grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
-// mxfft_tune.cpp -- launch autotuner of the generic line kernels and its
+// mxfft_tune.cpp -- launch autotuner of the generic line kernels (lines per
+// work-group, and for n <= 64 the single-launch kernel against them) and its
 // plain-text cache (one JSON object per line, keyed by GPU architecture, n,
 // format and block size).
 #include <hip/hip_runtime.h>
@@ -19,7 +20,7 @@ namespace {
 
 struct Entry {
     std::string arch;
-    int n = 0, format = 0, block = 0, lines = 0;
+    int n = 0, format = 0, block = 0, lines = 0, single = 0;
     double ms = 0.0;
 };
 
@@ -66,14 +67,18 @@ bool parse(const std::string& line, Entry* e)
     e->block = (int)b;
     e->lines = (int)l;
     e->ms = ms;
+    double one = 0.0;
+    e->single = find_num(line, "single", &one) ? (int)one : 0;   // absent in older entries
     return true;
 }
 
 std::string format_entry(const Entry& e)
 {
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "{\"arch\": \"%s\", \"n\": %d, \"format\": %d, \"block\": %d, \"lines\": %d, \"ms\": %.6f}",
-                  e.arch.c_str(), e.n, e.format, e.block, e.lines, e.ms);
+    std::snprintf(buf, sizeof(buf),
+                  "{\"arch\": \"%s\", \"n\": %d, \"format\": %d, \"block\": %d, \"lines\": %d, \"ms\": %.6f, "
+                  "\"single\": %d}",
+                  e.arch.c_str(), e.n, e.format, e.block, e.lines, e.ms, e.single);
     return buf;
 }
 
@@ -147,6 +152,7 @@ mxfft_status mxfft_tune_cache_lookup(const char* cache_path, const char* arch, i
             out->lines = e.lines;
             out->fast = 0;
             out->ms = e.ms;
+            out->single = (n <= mxk::kSmallN) ? e.single : 0;
             return MXFFT_OK;
         }
     }
@@ -183,20 +189,23 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
     ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     ok = ok && mxk::launch_fill(x, count, 0x5EEDu + (uint32_t)n, s) == hipSuccess;
 
-    // candidates: the default and its halvings down to 1 (the register-resident
-    // passes have none; they are timed once for the record)
+    // candidates: the default and its halvings down to 1, and for n <= 64 the
+    // single-launch kernel (-1); the register-resident passes have none (they
+    // are timed once for the record)
     std::vector<int> cand;
     if (cur.fast) {
         cand.push_back(0);
     } else {
-        for (int r = cur.lines; r >= 1 && (int)cand.size() < 5; r /= 2) cand.push_back(r);
+        for (int r = mxk::line_lines_per_group(n); r >= 1 && (int)cand.size() < 5; r /= 2) cand.push_back(r);
+        if (n <= mxk::kSmallN) cand.push_back(-1);
     }
-    int best = cand.empty() ? 0 : cand[0];
-    double best_ms = 1e30;
+    int best = cand.empty() ? 0 : cand[0], best_lines = best;
+    double best_ms = 1e30, best_lines_ms = 1e30;
     for (int r : cand) {
         if (!ok) break;
         mxfft_tuning t{};
-        t.lines = r;
+        t.lines = r < 0 ? 0 : r;
+        t.single = r < 0 ? 1 : 0;
         if (!cur.fast && mxfft_plan_set_tuning(plan, &t) != MXFFT_OK) continue;
         std::vector<float> ms;
         for (int rep = 0; rep < 4 && ok; rep++) {
@@ -214,6 +223,10 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
             best_ms = med;
             best = r;
         }
+        if (r >= 0 && med < best_lines_ms) {
+            best_lines_ms = med;
+            best_lines = r;
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -222,12 +235,14 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
     (void)hipFree(k);
     mxfft_plan_destroy(plan);
     if (!ok) return MXFFT_EHIP;
-    out->lines = cur.fast ? 0 : best;
+    out->lines = cur.fast ? 0 : best_lines;
     out->fast = cur.fast;
     out->ms = best_ms;
+    out->single = best < 0 ? 1 : 0;
     if (!cur.fast && cache_path) {
         Entry e = key_of(arch.c_str(), n, p);
-        e.lines = best;
+        e.lines = best_lines;
+        e.single = out->single;
         e.ms = best_ms;
         if (!store(cache_path, e)) return MXFFT_EINVAL;
     }

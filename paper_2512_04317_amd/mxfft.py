@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("lines", ctypes.c_int32), ("fast", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("lines", ctypes.c_int32), ("fast", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("single", ctypes.c_int32)]
 
 
 class Group(ctypes.Structure):
@@ -330,10 +331,12 @@ class Plan:
         st = lib().mxfft_plan_get_tuning(self.handle, ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_plan_get_tuning")
-        return {"lines": t.lines, "fast": bool(t.fast)}
+        return {"lines": t.lines, "fast": bool(t.fast), "single": bool(t.single)}
 
-    def set_tuning(self, lines):
-        t = Tuning(int(lines), 0, 0.0)
+    def set_tuning(self, lines, single=False):
+        """Line kernels with `lines` per work-group, or (n <= 64, single=True)
+        the single-launch kernel."""
+        t = Tuning(int(lines), 0, 0.0, 1 if single else 0)
         st = lib().mxfft_plan_set_tuning(self.handle, ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_plan_set_tuning")
@@ -369,7 +372,7 @@ def tune(n, sample=16, cache=None, force=False, stream=None, **params):
                           ctypes.byref(t), _stream(stream))
     if st != OK:
         raise MxfftError(st, "mxfft_tune")
-    return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms}
+    return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single)}
 
 
 def tune_cache_lookup(cache, arch, n, **params):
@@ -377,7 +380,7 @@ def tune_cache_lookup(cache, arch, n, **params):
     p = make_params(**params)
     t = Tuning()
     st = lib().mxfft_tune_cache_lookup(_cpath(cache), arch.encode(), int(n), ctypes.byref(p), ctypes.byref(t))
-    return None if st != OK else {"lines": t.lines, "ms": t.ms}
+    return None if st != OK else {"lines": t.lines, "ms": t.ms, "single": bool(t.single)}
 
 
 class Batch:
@@ -435,7 +438,7 @@ class Batch:
         st = lib().mxfft_batch_group_tuning(self.handle, int(g), ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_batch_group_tuning")
-        return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms}
+        return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single)}
 
     def close(self):
         if getattr(self, "handle", None):
