@@ -107,37 +107,70 @@ def uneven_workload(seed=20251204):
 
 
 def uneven_batch(args, torch, mxfft, synth):
-    """One graph launch over the uneven work list.  The pool holds the slices
-    grouped by size (one group per size, as a scheduler that packs same-size
-    slices would lay them out); its data repeats 8 distinct synthetic coil
-    slices per size (the transform's time does not depend on the values)."""
+    """One graph launch over the uneven work list, laid out per
+    reconstruction: the 512 reconstructions in arrival order, each its coils
+    contiguous at its own offset of one pool.  The library runs one branch
+    per size over that size's slices (through a per-slice offset table), the
+    branches side by side.  Also timed: each size's branch alone (the same
+    slices, in a batch of that size only) and the same slices grouped by size
+    in the pool, to show what the concurrent branches gain and what the
+    per-reconstruction layout costs.  The data repeats 8 distinct synthetic
+    coil slices per size (the time does not depend on the values)."""
     recon = uneven_workload()
-    counts = {}
+    groups, off = [], 0
     for n, c in recon:
-        counts[n] = counts.get(n, 0) + c
-    groups = [(n, counts[n]) for n in sorted(counts)]
+        groups.append((n, c, off))
+        off += c * n * n
     b = mxfft.Batch(groups, fmt=args.fmt, block=args.block)
     pool = torch.empty(b.pool_elems, dtype=torch.complex64, device="cuda")
-    for (n, c, o) in b.groups:
-        distinct = torch.from_numpy(synth.kspace_batch(n, 4, 1, 8)).cuda()
-        reps = (c + 7) // 8
-        pool[o:o + c * n * n].view(c, n, n).copy_(distinct.repeat(reps, 1, 1)[:c])
+    distinct = {n: torch.from_numpy(synth.kspace_batch(n, 4, 1, 8)).cuda() for n in (128, 256, 512, 1024)}
+    for i, (n, c, o) in enumerate(b.groups):
+        src = distinct[n].repeat((c + 7) // 8 + 1, 1, 1)
+        pool[o:o + c * n * n].view(c, n, n).copy_(src[i % 8:i % 8 + c])
     out = torch.empty_like(pool)
     k = torch.empty(b.slices, dtype=torch.int32, device="cuda")
-    run = lambda: b.forward(pool, out, k)   # noqa: E731
-    wall, per = timed_steps(run, args.steps, args.warmup, torch)
+    wall, per = timed_steps(lambda: b.forward(pool, out, k), args.steps, args.warmup, torch)
     assert b.last_status() == mxfft.OK
-    elems = sum(n * n * c for n, c in groups)
-    res = {"metric": "slices/s of one graph launch over the uneven work list", "value": round(b.slices * args.steps / wall, 1),
-           "unit": "slices/s", "ms_per_step": round(1e3 * wall / args.steps, 4),
-           "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4), "p99": round(float(np.percentile(per, 99)), 4)},
-           "hbm_frac_algorithmic": round(elems * 16.0 * args.steps / wall / (HBM_PEAK_GBS * 1e9), 4),
-           "reconstructions": len(recon), "slices": b.slices,
-           "groups": [{"n": n, "slices": c, "tuning": b.group_tuning(i)} for i, (n, c) in enumerate(groups)],
-           "format": args.fmt, "block": args.block, "direction": "forward",
-           "data": "synthetic: 8 distinct coil slices per size, repeated"}
+    elems = sum(n * n * c for n, c, _ in groups)
+    sizes = sorted(set(n for n, _, _ in groups))
+    tuning = {n: b.group_tuning(next(i for i, g in enumerate(groups) if g[0] == n)) for n in sizes}
     b.close()
-    return res
+    # each size's branch alone (same pool positions), then the sum
+    alone = {}
+    for n in sizes:
+        sub = [g for g in groups if g[0] == n]
+        with mxfft.Batch(sub, fmt=args.fmt, block=args.block) as bn:
+            kk = torch.empty(bn.slices, dtype=torch.int32, device="cuda")
+            w_n, _ = timed_steps(lambda: bn.forward(pool, out, kk), args.steps, args.warmup, torch)
+            alone[n] = {"slices": bn.slices, "ms": round(1e3 * w_n / args.steps, 4)}
+    # the same slices grouped by size (one contiguous group per size)
+    grouped, off = [], 0
+    for n in sizes:
+        c = sum(cc for nn, cc, _ in groups if nn == n)
+        grouped.append((n, c, off))
+        off += c * n * n
+    with mxfft.Batch(grouped, fmt=args.fmt, block=args.block) as bg:
+        pg = torch.empty(bg.pool_elems, dtype=torch.complex64, device="cuda")
+        for n, c, o in bg.groups:
+            pg[o:o + c * n * n].view(c, n, n).copy_(distinct[n].repeat((c + 7) // 8, 1, 1)[:c])
+        og = torch.empty_like(pg)
+        kg = torch.empty(bg.slices, dtype=torch.int32, device="cuda")
+        w_g, _ = timed_steps(lambda: bg.forward(pg, og, kg), args.steps, args.warmup, torch)
+        del pg, og
+    ms = 1e3 * wall / args.steps
+    sum_alone = sum(v["ms"] for v in alone.values())
+    return {"metric": "slices/s of one graph launch over the uneven work list (per-reconstruction layout)",
+            "value": round(sum(c for _, c, _ in groups) * args.steps / wall, 1),
+            "unit": "slices/s", "ms_per_step": round(ms, 4),
+            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4), "p99": round(float(np.percentile(per, 99)), 4)},
+            "hbm_frac_algorithmic": round(elems * 16.0 * args.steps / wall / (HBM_PEAK_GBS * 1e9), 4),
+            "reconstructions": len(recon), "slices": sum(c for _, c, _ in groups),
+            "sizes": {str(n): dict(alone[n], tuning=tuning[n]) for n in sizes},
+            "sum_of_branches_alone_ms": round(sum_alone, 4),
+            "concurrency_gain": round(sum_alone / ms, 3),
+            "grouped_by_size_ms": round(1e3 * w_g / args.steps, 4),
+            "format": args.fmt, "block": args.block, "direction": "forward",
+            "data": "synthetic: 8 distinct coil slices per size, repeated"}
 
 
 def nrmse_psnr(y, ref):

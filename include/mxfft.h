@@ -294,12 +294,16 @@ mxfft_status mxfft_tune_cache_lookup(const char* cache_path, const char* arch, i
  * A work list of slice groups of different sizes, transformed by one call
  * that launches one HIP graph.  Group g holds `count` slices of n x n at
  * element offset `offset` (complex values from the pool base) of both the
- * input and the output pool; groups must not overlap.  The graph holds one
- * independent branch per group (its own plan, workspace and stream), so small
- * groups run beside large ones; it is captured on the first call for a given
- * (operation, input, output, k) and replayed while those stay the same.
- * k per slice goes to k_out[kbase_g + i], kbase_g = the slices of the groups
- * before g.  Every slice's result is bit-identical to a single-plan call. */
+ * input and the output pool; groups must not overlap, and may lie anywhere
+ * (one group per reconstruction of several coils, in arrival order, for
+ * example).  The groups of one size form one branch of the graph: one plan
+ * and one launch sequence over all their slices, which the kernels address
+ * through a per-slice offset table (at most 65535 slices per size); the
+ * branches of different sizes run side by side.  The graph is captured on the
+ * first call for a given (operation, input, output, k) and replayed while
+ * those stay the same.  k per slice goes to k_out[kbase_g + i], kbase_g = the
+ * slices of the groups before g.  Every slice's result is bit-identical to a
+ * single-plan call. */
 typedef struct {
     int32_t n;        /* slice size (power of two, 2..4096) */
     int32_t count;    /* slices in the group (>= 1) */
@@ -308,10 +312,10 @@ typedef struct {
 
 typedef struct mxfft_batch_s* mxfft_batch_t;
 
-/* Plans every group (params p for all; n = 512 groups use the register-
- * resident passes), autotunes each distinct n that runs the generic kernels
- * through mxfft_tune with `tune_cache` (may be NULL: tune without a cache),
- * and creates the branch streams.  Allocates device memory; synchronises. */
+/* Plans one branch per distinct n (params p for all), autotunes each through
+ * mxfft_tune with `tune_cache` (may be NULL: tune without a cache) on up to
+ * 64 slices of that size, uploads the offset tables and creates the branch
+ * streams.  Allocates device memory; synchronises. */
 mxfft_status mxfft_batch_create(mxfft_batch_t* out, const mxfft_group* groups, int32_t ngroups,
                                 const mxfft_params* p, const char* tune_cache, void* stream);
 

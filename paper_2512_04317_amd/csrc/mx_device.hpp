@@ -81,6 +81,13 @@ __device__ __forceinline__ int renorm_exp(uint32_t amax_key)
     return max(k, 0);
 }
 
+// Element offset of slice `slice` in a pool: from the per-slice table when
+// there is one (slices anywhere in the pool), else slice * nn (contiguous).
+__device__ __forceinline__ size_t slice_base(const unsigned long long* off, int slice, size_t nn)
+{
+    return off ? (size_t)off[slice] : (size_t)slice * nn;
+}
+
 // Maximum over groups of `width` consecutive lanes (width a power of two,
 // 1 <= width <= 64) of non-negative values given as bits, every lane
 // receiving its group's value; every lane of a group must be active.  Inside

@@ -1,5 +1,8 @@
-// mxfft_batch.cpp -- uneven batches: groups of slices of different sizes,
-// transformed by one HIP graph launch with one independent branch per group.
+// mxfft_batch.cpp -- uneven batches: a work list of slice groups of different
+// sizes anywhere in one pool, transformed by one HIP graph launch.  Groups of
+// the same size share one branch (one plan, one stream, one launch sequence
+// over all their slices, addressed through a per-slice offset table); the
+// branches of different sizes run side by side.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,15 +10,23 @@
 #include <vector>
 
 #include "mxfft.h"
+#include "mxfft_internal.hpp"
 
 struct mxfft_batch_s {
     struct Group {
         mxfft_group g{};
         int32_t kbase = 0;            // first k_out index of the group
+        int branch = 0;
+    };
+    struct Branch {
+        int n = 0, count = 0;
         mxfft_plan_t plan = nullptr;
         hipStream_t stream = nullptr;  // branch stream (captured, never launched on directly)
         hipEvent_t done = nullptr;
         mxfft_tuning tuning{};
+        unsigned long long* d_off = nullptr;  // element offset of each slice in the pools
+        int32_t* d_kidx = nullptr;            // k_out index of each slice
+        int32_t* d_k = nullptr;               // k of each slice in branch order
     };
     struct Graph {
         bool valid = false;
@@ -26,6 +37,7 @@ struct mxfft_batch_s {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<Group> groups;
+    std::vector<Branch> branches;
     hipStream_t capture = nullptr;
     hipEvent_t fork = nullptr;
     Graph graphs[3];                   // forward, inverse, round trip
@@ -45,10 +57,13 @@ void release(mxfft_batch_s* b)
 {
     (void)hipDeviceSynchronize();
     for (auto& gr : b->graphs) drop_graph(gr);
-    for (auto& g : b->groups) {
-        if (g.plan) mxfft_plan_destroy(g.plan);
-        if (g.done) (void)hipEventDestroy(g.done);
-        if (g.stream) (void)hipStreamDestroy(g.stream);
+    for (auto& br : b->branches) {
+        if (br.plan) mxfft_plan_destroy(br.plan);
+        if (br.done) (void)hipEventDestroy(br.done);
+        if (br.stream) (void)hipStreamDestroy(br.stream);
+        (void)hipFree(br.d_off);
+        (void)hipFree(br.d_kidx);
+        (void)hipFree(br.d_k);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -57,17 +72,22 @@ void release(mxfft_batch_s* b)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-mxfft_status run_group(const mxfft_batch_s::Group& g, int op, const void* in, void* out, int32_t* k)
+// One branch: the plan's launch sequence over every slice of that size, the
+// slices addressed in the pools through the offset table; k to the branch's
+// own array, then scattered to the callers' slice order.
+mxfft_status run_branch(const mxfft_batch_s::Branch& br, int op, const void* in, void* out, int32_t* k)
 {
-    const size_t off = (size_t)g.g.offset * 8;
-    const void* src = (const char*)in + off;
-    void* dst = (char*)out + off;
-    int32_t* kg = k ? k + g.kbase : nullptr;
+    mxk::Workspace w = mxk::plan_workspace(br.plan);
+    w.slice_off = br.d_off;
+    int32_t* kb = k ? br.d_k : nullptr;
+    mxfft_status st;
     switch (op) {
-    case 0: return mxfft_forward(g.plan, src, dst, g.g.count, kg, g.stream);
-    case 1: return mxfft_inverse(g.plan, src, dst, g.g.count, nullptr, g.stream);
-    default: return mxfft_roundtrip(g.plan, src, dst, g.g.count, kg, g.stream);
+    case 0: st = mxk::plan_forward_ws(br.plan, w, in, out, br.count, kb, br.stream); break;
+    case 1: st = mxk::plan_inverse_ws(br.plan, w, in, out, br.count, nullptr, br.stream); break;
+    default: st = mxk::plan_roundtrip_ws(br.plan, w, in, out, br.count, kb, br.stream); break;
     }
+    if (st != MXFFT_OK || !kb) return st;
+    return mxk::launch_scatter_k(kb, br.d_kidx, k, br.count, br.stream) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
 // Capture op over every group into gr: fork from the capture stream, one
@@ -78,12 +98,12 @@ mxfft_status capture(mxfft_batch_s* b, int op, const void* in, void* out, int32_
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return MXFFT_EHIP;
     mxfft_status st = MXFFT_OK;
     bool ok = hipEventRecord(b->fork, b->capture) == hipSuccess;
-    for (auto& g : b->groups) {
+    for (auto& br : b->branches) {
         if (!ok || st != MXFFT_OK) break;
-        ok = hipStreamWaitEvent(g.stream, b->fork, 0) == hipSuccess;
-        if (ok) st = run_group(g, op, in, out, k);
-        ok = ok && hipEventRecord(g.done, g.stream) == hipSuccess;
-        ok = ok && hipStreamWaitEvent(b->capture, g.done, 0) == hipSuccess;
+        ok = hipStreamWaitEvent(br.stream, b->fork, 0) == hipSuccess;
+        if (ok) st = run_branch(br, op, in, out, k);
+        ok = ok && hipEventRecord(br.done, br.stream) == hipSuccess;
+        ok = ok && hipStreamWaitEvent(b->capture, br.done, 0) == hipSuccess;
     }
     hipGraph_t graph = nullptr;
     const bool ended = hipStreamEndCapture(b->capture, &graph) == hipSuccess;
@@ -132,33 +152,50 @@ mxfft_status mxfft_batch_create(mxfft_batch_t* out, const mxfft_group* groups, i
     mxfft_status st = MXFFT_OK;
     bool ok = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
-    // one tuning per distinct n (sample: up to 64 slices of that size)
-    std::vector<std::pair<int, mxfft_tuning>> tuned;
+    // the work list: groups in the caller's order, merged into one branch per
+    // distinct n (branches in order of first appearance)
+    std::vector<std::vector<unsigned long long>> offs;
+    std::vector<std::vector<int32_t>> kidx;
     int32_t kbase = 0;
-    for (int i = 0; i < ngroups && ok && st == MXFFT_OK; i++) {
+    for (int i = 0; i < ngroups; i++) {
         mxfft_batch_s::Group g;
         g.g = groups[i];
         g.kbase = kbase;
         kbase += g.g.count;
-        b->groups.push_back(g);
-        auto& G = b->groups.back();
-        st = mxfft_plan(&G.plan, G.g.n, G.g.count, p, stream);
-        if (st != MXFFT_OK) break;
-        ok = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&G.done, hipEventDisableTiming) == hipSuccess;
-        auto it = std::find_if(tuned.begin(), tuned.end(), [&](const auto& t) { return t.first == G.g.n; });
-        if (it == tuned.end()) {
-            int sample = 0;
-            for (int j = 0; j < ngroups; j++)
-                if (groups[j].n == G.g.n) sample += groups[j].count;
-            mxfft_tuning t{};
-            st = mxfft_tune(G.g.n, p, std::min(sample, 64), tune_cache, 0, &t, stream);
-            if (st != MXFFT_OK) break;
-            tuned.emplace_back(G.g.n, t);
-            it = tuned.end() - 1;
+        auto it = std::find_if(b->branches.begin(), b->branches.end(), [&](const auto& br) { return br.n == g.g.n; });
+        if (it == b->branches.end()) {
+            b->branches.emplace_back();
+            b->branches.back().n = g.g.n;
+            offs.emplace_back();
+            kidx.emplace_back();
+            it = b->branches.end() - 1;
         }
-        G.tuning = it->second;
-        if (!G.tuning.fast) st = mxfft_plan_set_tuning(G.plan, &G.tuning);
+        g.branch = (int)(it - b->branches.begin());
+        for (int j = 0; j < g.g.count; j++) {
+            offs[g.branch].push_back(g.g.offset + (unsigned long long)j * g.g.n * g.g.n);
+            kidx[g.branch].push_back(g.kbase + j);
+        }
+        it->count += g.g.count;
+        b->groups.push_back(g);
+    }
+    for (size_t r = 0; r < b->branches.size() && ok && st == MXFFT_OK; r++) {
+        auto& br = b->branches[r];
+        st = mxfft_plan(&br.plan, br.n, br.count, p, stream);
+        if (st != MXFFT_OK) break;
+        ok = hipStreamCreateWithFlags(&br.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&br.done, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipMalloc((void**)&br.d_off, offs[r].size() * sizeof(unsigned long long)) == hipSuccess;
+        ok = ok && hipMalloc((void**)&br.d_kidx, kidx[r].size() * sizeof(int32_t)) == hipSuccess;
+        ok = ok && hipMalloc((void**)&br.d_k, kidx[r].size() * sizeof(int32_t)) == hipSuccess;
+        ok = ok && hipMemcpy(br.d_off, offs[r].data(), offs[r].size() * sizeof(unsigned long long),
+                             hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(br.d_kidx, kidx[r].data(), kidx[r].size() * sizeof(int32_t), hipMemcpyHostToDevice) ==
+                       hipSuccess;
+        if (!ok) break;
+        // tuned on a sample of up to 64 slices of that size
+        st = mxfft_tune(br.n, p, std::min(br.count, 64), tune_cache, 0, &br.tuning, stream);
+        if (st != MXFFT_OK) break;
+        if (!br.tuning.fast) st = mxfft_plan_set_tuning(br.plan, &br.tuning);
     }
     ok = ok && hipStreamSynchronize((hipStream_t)stream) == hipSuccess;
     if (!ok || st != MXFFT_OK) {
@@ -187,8 +224,8 @@ mxfft_status mxfft_batch_last_status(mxfft_batch_t b, void* stream)
 {
     if (!b) return MXFFT_EINVAL;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MXFFT_EHIP;
-    for (auto& g : b->groups) {
-        const mxfft_status st = mxfft_plan_last_status(g.plan, g.stream);
+    for (auto& br : b->branches) {
+        const mxfft_status st = mxfft_plan_last_status(br.plan, br.stream);
         if (st != MXFFT_OK) return st;
     }
     return MXFFT_OK;
@@ -197,7 +234,7 @@ mxfft_status mxfft_batch_last_status(mxfft_batch_t b, void* stream)
 mxfft_status mxfft_batch_group_tuning(mxfft_batch_t b, int32_t g, mxfft_tuning* out)
 {
     if (!b || !out || g < 0 || g >= (int32_t)b->groups.size()) return MXFFT_EINVAL;
-    *out = b->groups[g].tuning;
+    *out = b->branches[b->groups[g].branch].tuning;
     return MXFFT_OK;
 }
 

@@ -74,6 +74,7 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
     g.tw16 = p.tw16;
     g.rss = p.rss;
     g.coils = p.coils;
+    g.slice_off = p.slice_off;
     // the redo pass strides over its list: tiles of at most 64 slices in the grid
     if (row && kind == ROW_FIX && batch > 64) batch = 64;
     switch (mode * 4096 + n) {

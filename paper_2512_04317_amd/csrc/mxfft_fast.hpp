@@ -435,6 +435,7 @@ struct FastArgs {
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
     float* rss;              // column pass with the coil combine: [reconstruction][N][N] FP32
     int32_t coils;           // coil slices per reconstruction (consecutive slices)
+    const unsigned long long* slice_off;  // element offset of each slice in src / dst, or nullptr
 };
 
 using mxk::kStatsBins;
@@ -867,7 +868,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     const int kp = slice_k(g, slice);
     const int kin = ST ? 0 : g.kin_mul * kp;
     if (KIND == ROW_PLAIN && g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
-    const float2* x = g.src + ((size_t)slice * N + row) * N;
+    const float2* x = g.src + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + (size_t)row * N;
     float* plane = s_plane + wave * WPL + line_base(line);
     uint32_t* hist = (uint32_t*)s_plane;                 // statistics only, before the planes are used
     const int rm = (int)(__brev((unsigned)m) >> (32 - LOG_LPL));   // m bit-reversed
@@ -1012,7 +1013,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
     if constexpr (F == FP32) {
-        float2* y = g.dst + ((size_t)slice * N + row) * N;
+        float2* y = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + (size_t)row * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
     } else if constexpr (is_16(F)) {
         // 16-bit intermediate [slice][16-column group][row][16 words]: in-lane
@@ -1234,7 +1235,7 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
         // rows are read whole (128 bytes = the work-group's 16 columns) into an
         // LDS tile, 256 rows at a time; lanes then take rows 16k + rev4(m)
         // (layout 0: offset rev5(k)), whose low 4 bits are the lane bits
-        const float2* xs = g.src + (size_t)slice * N * N + cb16 * LINES;
+        const float2* xs = g.src + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + cb16 * LINES;
         sfor<2>([&](auto H) {
             if constexpr (H == 1) __syncthreads();
 #pragma unroll
@@ -1357,7 +1358,7 @@ __attribute__((amdgpu_waves_per_eu(waves_target(F == BF16), 8))) void k_col(Fast
     constexpr int LM = lane_mask<CL, KL>();
     static_assert(HB >= 0 && (LM & 1) == 0 && (LM >> (LOGN - 1)) == 0, "top row bit and bit 0 in-lane");
     const int pmL = posM<CL, KL>(m);
-    float2* ys = g.dst + (size_t)slice * N * N + cb16 * LINES;
+    float2* ys = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + cb16 * LINES;
     sfor<2>([&](auto H) {
         __syncthreads();
         sfor<P>([&](auto O) {

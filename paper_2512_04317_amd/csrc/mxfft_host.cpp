@@ -361,6 +361,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
         f.kadd = kadd;
         f.fix_list = w.fix_list;
         f.fix_count = w.fix_count;
+        f.slice_off = w.slice_off;
         return mxk::launch_fast(pl->mode, pl->n, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
                    ? MXFFT_OK
                    : MXFFT_EHIP;
@@ -386,6 +387,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     a.encode = mxk::is_mx_mode(pl->mode) && kind != mxk::ROW_RAW;
     a.cap_mant = capture ? pl->d_cap_mant : nullptr;
     a.cap_exp = capture ? pl->d_cap_exp : nullptr;
+    a.slice_off = w.slice_off;
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -422,6 +424,7 @@ mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, vo
     g.a.logcb = pl->logcb;
     g.a.cap_mant = capture ? pl->d_cap_mant : nullptr;
     g.a.cap_exp = capture ? pl->d_cap_exp : nullptr;
+    g.a.slice_off = w.slice_off;
     g.pa = prescale_args(pl);
     g.op = op;
     g.stats = stats ? 1 : 0;
@@ -440,7 +443,7 @@ mxfft_status stats(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, in
 {
     const mxk::PrescaleArgs pa = prescale_args(pl);
     LaunchTimer timer(pl, ROLE_STATS, s);
-    if (mxk::launch_stats((const float2*)in, pl->n, batch, w.parts, w.kp, w.status, pa, s) != hipSuccess)
+    if (mxk::launch_stats((const float2*)in, pl->n, batch, w.parts, w.kp, w.status, pa, w.slice_off, s) != hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
 }
@@ -462,7 +465,7 @@ mxfft_status row_with_stats(mxfft_plan_s* pl, const mxk::Workspace& w, const voi
         const mxk::PrescaleArgs pa = prescale_args(pl);
         LaunchTimer timer(pl, ROLE_STATS, s);
         if (mxk::launch_stats_final((const float2*)in, pl->n, batch, mxk::fast_row_tiles(pl->n), w.parts, w.kp,
-                                    w.status, pa, w.kadd, w.fix_list, w.fix_count, k_out, s) != hipSuccess)
+                                    w.status, pa, w.kadd, w.fix_list, w.fix_count, k_out, w.slice_off, s) != hipSuccess)
             return MXFFT_EHIP;
     }
     return pass(pl, w, in, nullptr, w.kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
@@ -619,6 +622,8 @@ bool plan_has_status(mxfft_plan_t pl) { return !(pl->p.flags & MXFFT_NO_PRESCALE
 
 int plan_device(const mxfft_plan_s* pl) { return pl->device; }
 
+const Workspace& plan_workspace(const mxfft_plan_s* pl) { return pl->ws; }
+
 void plan_workspace_layout(const mxfft_plan_s* pl, int batch, char* base, Workspace* w, size_t* bytes)
 {
     const WsCounts c = ws_counts(pl, batch);
@@ -718,7 +723,24 @@ mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t b
 {
     MX_TRY(check_call(pl, in, out, batch));
     if (batch == 0) return MXFFT_OK;
-    const mxk::Workspace& w = pl->ws;
+    return mxk::plan_inverse_ws(pl, pl->ws, in, out, batch, k_in, stream);
+}
+
+mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t batch, int32_t* k_out,
+                             void* stream)
+{
+    MX_TRY(check_call(pl, in, out, batch));
+    if (batch == 0) return MXFFT_OK;
+    return mxk::plan_roundtrip_ws(pl, pl->ws, in, out, batch, k_out, stream);
+}
+
+}  // extern "C"
+
+namespace mxk {
+
+mxfft_status plan_inverse_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                             const int32_t* k_in, void* stream)
+{
     hipStream_t s = (hipStream_t)stream;
     const int kout_add = (pl->p.flags & MXFFT_NORMALIZE) ? -2 * pl->logn : 0;
     bool pre = false;
@@ -745,12 +767,9 @@ mxfft_status mxfft_inverse(mxfft_plan_t pl, const void* in, void* out, int32_t b
     return MXFFT_OK;
 }
 
-mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t batch, int32_t* k_out,
-                             void* stream)
+mxfft_status plan_roundtrip_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                               int32_t* k_out, void* stream)
 {
-    MX_TRY(check_call(pl, in, out, batch));
-    if (batch == 0) return MXFFT_OK;
-    const mxk::Workspace& w = pl->ws;
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
     const int32_t* kp = pre ? w.kp : nullptr;
@@ -773,6 +792,10 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t pl, const void* in, void* out, int32_t
     pl->last_status = w.status;
     return MXFFT_OK;
 }
+
+}  // namespace mxk
+
+extern "C" {
 
 mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, float* rss, int32_t recon,
                        int32_t coils, int32_t* k_out, void* stream)

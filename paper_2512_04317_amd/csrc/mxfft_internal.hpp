@@ -50,6 +50,9 @@ struct Workspace {
     int32_t* kadd = nullptr;      // fused statistics: exponent offset per slice
     int32_t* fix_list = nullptr;  // fused statistics: slices whose row pass is redone
     int32_t* fix_count = nullptr; // length of fix_list (cleared by the row pass)
+    // element offset of each slice in the caller's input and output pools, or
+    // nullptr for [batch][n][n] (uneven batches: slices anywhere in the pool)
+    const unsigned long long* slice_off = nullptr;
 };
 
 // Chunks per slice for a batch: enough work-groups to fill the chip, at
@@ -87,6 +90,7 @@ struct LineArgs {
     int32_t encode;          // MX-encode the pass input
     float2* cap_mant;        // column pass: its encoded input's element values, or nullptr
     int32_t* cap_exp;        // column pass: its input block exponents [slice][column][row block]
+    const unsigned long long* slice_off;  // slice offsets in src / dst, or nullptr (contiguous)
 };
 
 // MX formats, the 16-bit positive controls (per-operation rounding) and plain FP32
@@ -113,6 +117,7 @@ struct FastPassArgs {
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves at [h + j]
     float* rss;              // COL_RSS: [reconstruction][n][n] root-sum-of-squares image
     int32_t coils;           // COL_RSS: coil slices per reconstruction
+    const unsigned long long* slice_off;  // slice offsets in src / dst, or nullptr (contiguous)
 };
 
 // Row pass kinds of the register-resident passes.
@@ -130,14 +135,16 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
 int fast_row_tiles(int n);
 
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
-                        int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s);
+                        int32_t* slice_status, const PrescaleArgs& pa, const unsigned long long* slice_off,
+                        hipStream_t s);
 // Alg. 1 from chunk statistics already in `parts` ([slice][chunks]) that the
 // row pass wrote; also the equivariance check: kadd[slice] = kp when the
 // unscaled row pass may stand, else 0 with the slice appended to fix_list.
 // k_out (nullable) receives kp.
 hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, const StatPart* parts, int32_t* kp,
                               int32_t* slice_status, const PrescaleArgs& pa, int32_t* kadd, int32_t* fix_list,
-                              int32_t* fix_count, int32_t* k_out, hipStream_t s);
+                              int32_t* fix_count, int32_t* k_out, const unsigned long long* slice_off,
+                              hipStream_t s);
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 
 // Single-launch transform of slices of n <= kSmallN (one work-group per
@@ -180,6 +187,13 @@ void plan_release_idle(mxfft_plan_s* pl);
 mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
                              int32_t* k_out, void* stream);
 
+// Inverse and round trip of a checked call with the workspace w (as
+// plan_forward_ws).
+mxfft_status plan_inverse_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                             const int32_t* k_in, void* stream);
+mxfft_status plan_roundtrip_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
+                               int32_t* k_out, void* stream);
+
 // Workspace of a plan's forward call over `batch` slices laid out from
 // `base` (each buffer 256-byte aligned): *bytes gets the extent; with base
 // non-null, *w gets the buffer addresses.
@@ -187,6 +201,13 @@ void plan_workspace_layout(const mxfft_plan_s* pl, int batch, char* base, Worksp
 
 // Device the plan was created on.
 int plan_device(const mxfft_plan_s* pl);
+
+// The plan's own workspace (sized for its max_batch).
+const Workspace& plan_workspace(const mxfft_plan_s* pl);
+
+// dst[idx[i]] = src[i] for i < count (k of a merged batch branch back in the
+// caller's slice order).
+hipError_t launch_scatter_k(const int32_t* src, const int32_t* idx, int32_t* dst, int count, hipStream_t s);
 
 // Device status words of a plan (one int32 per slice of its last call, written
 // by the prescale statistics), and whether its calls write them.

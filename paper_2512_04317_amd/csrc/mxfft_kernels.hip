@@ -46,13 +46,14 @@ __device__ int round_log2_ratio(double T, double a)
 // are the only possible collision, which the 32-bank LDS pays anyway.
 constexpr int kHistCopies = 32;
 __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x, int nn, int chunk,
-                                                     int chunks, StatPart* __restrict__ parts)
+                                                     int chunks, StatPart* __restrict__ parts,
+                                                     const unsigned long long* __restrict__ slice_off)
 {
     __shared__ __align__(16) uint32_t hist[kStatsBins * kHistCopies];
     __shared__ unsigned long long s_m2;
     __shared__ uint32_t s_count, s_maxc, s_nonfin;
     const int tid = threadIdx.x, slice = blockIdx.y, copy = tid & (kHistCopies - 1);
-    const float2* xs = x + (size_t)slice * nn;
+    const float2* xs = x + mxd::slice_base(slice_off, slice, (size_t)nn);
 
     for (int i = tid; i < kStatsBins * kHistCopies / 4; i += blockDim.x) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
     if (tid == 0) { s_m2 = 0; s_count = 0; s_maxc = 0; s_nonfin = 0; }
@@ -328,11 +329,12 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
                                                       int32_t* __restrict__ kp, int32_t* __restrict__ slice_status,
                                                       PrescaleArgs pa, int32_t* __restrict__ kadd,
                                                       int32_t* __restrict__ fix_list, int32_t* __restrict__ fix_count,
-                                                      int32_t* __restrict__ k_out)
+                                                      int32_t* __restrict__ k_out,
+                                                      const unsigned long long* __restrict__ slice_off)
 {
     __shared__ Alg1Smem S;
     const int tid = threadIdx.x, slice = blockIdx.x;
-    const float2* xs = x + (size_t)slice * nn;
+    const float2* xs = x + mxd::slice_base(slice_off, slice, (size_t)nn);
     const StatPart* pt = parts + (size_t)slice * chunks;
     alg1_init(S);
     __syncthreads();
@@ -396,24 +398,27 @@ size_t stats_parts(int n, int max_batch)
 }
 
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
-                        int32_t* slice_status, const PrescaleArgs& pa, hipStream_t s)
+                        int32_t* slice_status, const PrescaleArgs& pa, const unsigned long long* slice_off,
+                        hipStream_t s)
 {
     const int nn = n * n;
     const int chunks = stats_chunks(n, batch);
-    hipLaunchKernelGGL(k_stats_part, dim3(chunks, batch), dim3(256), 0, s, x, nn, nn / chunks, chunks, parts);
+    hipLaunchKernelGGL(k_stats_part, dim3(chunks, batch), dim3(256), 0, s, x, nn, nn / chunks, chunks, parts,
+                       slice_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, nn, chunks, parts, kp, slice_status, pa,
-                       nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, slice_off);
     return hipGetLastError();
 }
 
 hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, const StatPart* parts, int32_t* kp,
                               int32_t* slice_status, const PrescaleArgs& pa, int32_t* kadd, int32_t* fix_list,
-                              int32_t* fix_count, int32_t* k_out, hipStream_t s)
+                              int32_t* fix_count, int32_t* k_out, const unsigned long long* slice_off,
+                              hipStream_t s)
 {
     hipLaunchKernelGGL(k_stats_final, dim3(batch), dim3(256), 0, s, x, n * n, chunks, parts, kp, slice_status, pa,
-                       kadd, fix_list, fix_count, k_out);
+                       kadd, fix_list, fix_count, k_out, slice_off);
     return hipGetLastError();
 }
 
@@ -471,7 +476,8 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     extern __shared__ float2 lds[];
     const int N = a.n, logn = a.logn, R = a.lines, tid = threadIdx.x;
     const int slice = blockIdx.y;
-    const size_t sbase = (size_t)slice * N * N;
+    const size_t sbase = mxd::slice_base(a.slice_off, slice, (size_t)N * N);   // slice in src / dst
+    const size_t cbase = (size_t)slice * N * N;                               // slice in the capture
     const int line0 = blockIdx.x * R;
     int kp = a.kp ? a.kp[slice] : 0;
     if (kp == INT32_MIN) kp = 0;  // failed slice: output undefined, keep it finite-safe
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
                     // debug capture of the column pass input: line r is column
                     // line0 + r, element e its row
                     const int r = idx >> logn, e = idx & (N - 1), col = line0 + r;
-                    a.cap_mant[sbase + (size_t)e * N + col] = make_float2(qx, qy);
+                    a.cap_mant[cbase + (size_t)e * N + col] = make_float2(qx, qy);
                     if ((e & (a.cb - 1)) == 0)
                         a.cap_exp[((size_t)slice * N + col) * (N >> a.logcb) + (e >> a.logcb)] = E;
                 }
@@ -726,7 +732,7 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
     __shared__ float2 buf[kSmallMaxN * kSmallPitch];
     __shared__ Alg1Smem S;
     const int tid = threadIdx.x, slice = blockIdx.x, N = g.a.n, logn = g.a.logn, nn = N * N;
-    const float2* xs = g.a.src + (size_t)slice * nn;
+    const float2* xs = g.a.src + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
     if (g.stats) {
         alg1_init(S);
         __syncthreads();
@@ -794,7 +800,7 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
         small_pass<MODE>(a, buf, true, MX, nullptr, nullptr, slice);
     }
     const int kout = g.kout_mul * k + g.kout_add;
-    float2* ys = g.a.dst + (size_t)slice * nn;
+    float2* ys = g.a.dst + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
     for (int i = tid; i < nn; i += blockDim.x) {
         const float2 v = buf[(i >> logn) * kSmallPitch + (i & (N - 1))];
         ys[i] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));
@@ -817,6 +823,19 @@ hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s)
     case MODE_FP32: hipLaunchKernelGGL(k_small<MODE_FP32>, grid, block, 0, s, g); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+__global__ void k_scatter_k(const int32_t* __restrict__ src, const int32_t* __restrict__ idx,
+                            int32_t* __restrict__ dst, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[idx[i]] = src[i];
+}
+
+hipError_t launch_scatter_k(const int32_t* src, const int32_t* idx, int32_t* dst, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter_k, dim3((count + 255) / 256), dim3(256), 0, s, src, idx, dst, count);
     return hipGetLastError();
 }
 

@@ -161,3 +161,49 @@ def test_tuner_cache_round_trip(tmp_path):
     with pytest.raises(mxfft.MxfftError):
         pl.set_tuning(128)                         # more lines than the slice has
     pl.close()
+
+
+def test_per_reconstruction_work_list():
+    """Reconstructions in arrival order, each its coils contiguous at its own
+    offset, sizes interleaved (so each size's branch addresses its slices
+    through the offset table): every slice bit for bit against a single-plan
+    call, a sample against the oracle, k in the callers' order; a tiny coil
+    takes the fused statistics' literal redo, a non-finite one fails alone."""
+    rng = np.random.default_rng([20251204, 41])
+    sizes = rng.choice([32, 64, 128, 256, 512], size=24)
+    coils = rng.integers(1, 4, size=24)
+    groups, off = [], 0
+    for n, c in zip(sizes.tolist(), coils.tolist()):
+        groups.append((n, c, off))
+        off += c * n * n + 8
+    print("work list: %d reconstructions, %s" % (len(groups), groups), flush=True)
+    xs = [synth.kspace_batch(n, 4, 1, c) for n, c, _ in groups]
+    big = [i for i, (n, _, _) in enumerate(groups) if n == 512]
+    xs[big[0]][0] *= np.float32(2.0 ** -110)            # outside the fused statistics' window
+    bad = [i for i, (n, _, _) in enumerate(groups) if n == 128][0]
+    xs[bad][-1, 3, 3] = np.float32(np.nan)
+    b = mxfft.Batch(groups, fmt="e4m3", block=32)
+    pool = torch.from_numpy(pool_of(b, xs)).cuda()
+    for op in (mxfft.FORWARD, mxfft.ROUNDTRIP):
+        out, k = b.execute(op, pool)
+        assert b.last_status() == mxfft.ENONFINITE
+        yb = b.views(out.cpu())
+        kb = k.cpu().numpy()
+        kbase = 0
+        for gi, ((n, c, _), x) in enumerate(zip(groups, xs)):
+            with mxfft.Plan(n, c, fmt="e4m3", block=32) as pl:
+                xd = torch.from_numpy(x).cuda()
+                y, ks = pl.forward(xd) if op == mxfft.FORWARD else pl.roundtrip(xd)
+                torch.cuda.synchronize()
+                ks = ks.cpu().numpy()
+                assert np.array_equal(kb[kbase:kbase + c], ks), "group %d k" % gi
+                ok = ks != mxfft.INT32_MIN
+                assert np.array_equal(bits(yb[gi].numpy()[ok]), bits(y.cpu().numpy()[ok])), "group %d op %d" % (gi, op)
+            kbase += c
+        assert kb[sum(c for _, c, _ in groups[:bad]) + groups[bad][1] - 1] == mxfft.INT32_MIN
+        for gi in (big[0], 0, len(groups) - 1):
+            st, yo, ko = O.transform(xs[gi], op=O.FORWARD if op == mxfft.FORWARD else O.ROUNDTRIP, fmt=O.E4M3, B=32,
+                                     nthreads=NTHREADS)
+            if gi != bad:
+                assert st == O.OK and np.array_equal(bits(yb[gi].numpy()), bits(yo)), "group %d vs oracle" % gi
+    b.close()
