@@ -262,10 +262,19 @@ typedef struct {
     double ms;       /* out (tuner): time of one forward call over its sample */
     int32_t single;  /* n <= 64: 1 = the single-launch kernel (lines ignored),
                         0 = the line kernels with `lines`; must be 0 for n > 64 */
+    int32_t stats;   /* Alg. 1 with the prescale: 0 = gathered by the row pass
+                        where the plan can (register-resident MX passes at
+                        n = 512 and 1024), 1 = a separate statistics read of
+                        the input before the row pass (the only way elsewhere) */
+    int32_t chunks;  /* work-groups per slice of that separate read: 0 = by the
+                        batch (enough to fill the GPU), else a power of two
+                        with n * n / chunks >= 1024 (lowered when a batch's
+                        statistics would not fit the plan's workspace) */
 } mxfft_tuning;
 
 /* Set / read a plan's launch tuning.  Set: MXFFT_EINVAL for an invalid
- * `lines`; takes effect from the next call (no synchronisation). */
+ * field; takes effect from the next call (no synchronisation).  Every choice
+ * gives bit-identical results. */
 mxfft_status mxfft_plan_set_tuning(mxfft_plan_t plan, const mxfft_tuning* t);
 mxfft_status mxfft_plan_get_tuning(mxfft_plan_t plan, mxfft_tuning* t);
 
@@ -312,10 +321,13 @@ typedef struct {
 
 typedef struct mxfft_batch_s* mxfft_batch_t;
 
-/* Plans one branch per distinct n (params p for all), autotunes each through
- * mxfft_tune with `tune_cache` (may be NULL: tune without a cache) on up to
- * 64 slices of that size, uploads the offset tables and creates the branch
- * streams.  Allocates device memory; synchronises. */
+/* Plans one branch per distinct n (params p for all), autotunes each size on
+ * the line kernels through mxfft_tune with `tune_cache` (may be NULL: tune
+ * without a cache) on up to 1024 slices of that size, uploads the offset
+ * tables and creates the branch streams.  Sizes on the register-resident
+ * passes keep the plans' defaults (the branches share the GPU, and the
+ * choices that win for one size alone were measured slower beside the other
+ * sizes).  Allocates device memory; synchronises. */
 mxfft_status mxfft_batch_create(mxfft_batch_t* out, const mxfft_group* groups, int32_t ngroups,
                                 const mxfft_params* p, const char* tune_cache, void* stream);
 
@@ -328,7 +340,7 @@ mxfft_status mxfft_batch_execute(mxfft_batch_t b, int32_t op, const void* in, vo
 /* Synchronise `stream`; the first non-OK device status of the last call. */
 mxfft_status mxfft_batch_last_status(mxfft_batch_t b, void* stream);
 
-/* Tuning chosen for group g (lines, fast, ms). */
+/* Tuning chosen for group g's size. */
 mxfft_status mxfft_batch_group_tuning(mxfft_batch_t b, int32_t g, mxfft_tuning* out);
 
 /* Release the batch, its plans, streams and graphs (synchronises the device). */

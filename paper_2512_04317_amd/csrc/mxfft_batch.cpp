@@ -192,10 +192,15 @@ mxfft_status mxfft_batch_create(mxfft_batch_t* out, const mxfft_group* groups, i
         ok = ok && hipMemcpy(br.d_kidx, kidx[r].data(), kidx[r].size() * sizeof(int32_t), hipMemcpyHostToDevice) ==
                        hipSuccess;
         if (!ok) break;
-        // tuned on a sample of up to 64 slices of that size
-        st = mxfft_tune(br.n, p, std::min(br.count, 64), tune_cache, 0, &br.tuning, stream);
+        // the line kernels are tuned on up to 1024 slices of that size; the
+        // register-resident passes keep their defaults here: the choices that
+        // win for one size alone (a separate statistics read) were measured
+        // slower with the other sizes' branches beside them
+        st = mxfft_plan_get_tuning(br.plan, &br.tuning);
+        if (st != MXFFT_OK || br.tuning.fast) continue;
+        st = mxfft_tune(br.n, p, std::min(br.count, 1024), tune_cache, 0, &br.tuning, stream);
         if (st != MXFFT_OK) break;
-        if (!br.tuning.fast) st = mxfft_plan_set_tuning(br.plan, &br.tuning);
+        st = mxfft_plan_set_tuning(br.plan, &br.tuning);
     }
     ok = ok && hipStreamSynchronize((hipStream_t)stream) == hipSuccess;
     if (!ok || st != MXFFT_OK) {

@@ -100,6 +100,10 @@ struct mxfft_plan_s {
     int lines = 0;
     // n <= 64: the whole transform in one launch instead of the line kernels
     bool single = false;
+    // Alg. 1 as a separate read even where the row pass could gather it, and
+    // work-groups per slice of that read (0 = by batch)
+    bool literal_stats = false;
+    int chunks = 0;
     // sizing only: nothing is allocated or uploaded
     bool dry = false;
     // register-resident passes: twiddles at [h + j]
@@ -404,6 +408,9 @@ mxk::PrescaleArgs prescale_args(const mxfft_plan_s* pl)
 
 int inverse_row_kind(const mxfft_plan_s* pl);
 
+// whether a call with the prescale gathers Alg. 1's statistics in the row pass
+bool fused_stats(const mxfft_plan_s* pl) { return pl->fused && !pl->literal_stats; }
+
 // The whole transform of slices of n <= 64 in one launch.  op 0 forward,
 // 1 inverse, 2 round trip; stats: Alg. 1 on the input (else k from k_in or 0).
 mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, void* out, int op, bool stats,
@@ -443,7 +450,11 @@ mxfft_status stats(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, in
 {
     const mxk::PrescaleArgs pa = prescale_args(pl);
     LaunchTimer timer(pl, ROLE_STATS, s);
-    if (mxk::launch_stats((const float2*)in, pl->n, batch, w.parts, w.kp, w.status, pa, w.slice_off, s) != hipSuccess)
+    // a chunk count the workspace cannot hold for this batch falls back to the default
+    int chunks = pl->chunks;
+    if (chunks > 0 && (size_t)chunks * batch > mxk::stats_parts(pl->n, batch)) chunks = 0;
+    if (mxk::launch_stats((const float2*)in, pl->n, batch, w.parts, w.kp, w.status, pa, w.slice_off, chunks, s) !=
+        hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
 }
@@ -692,7 +703,7 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     const bool cap = pl->d_cap_mant != nullptr && batch <= pl->max_batch;   // capture buffers hold max_batch
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 0, pre, nullptr, k_out, 1, kout_mul, 0, cap, batch, s));
-    } else if (pre && pl->fused) {
+    } else if (pre && fused_stats(pl)) {
         MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
@@ -703,7 +714,7 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     }
     if (cap && pl->fast) {
         // the register-resident intermediate holds the column pass input
-        if (mxk::launch_capture_mx(pl->mode, pl->n, pl->cb, w.codes, w.exps, (pre && pl->fused) ? w.kadd : nullptr,
+        if (mxk::launch_capture_mx(pl->mode, pl->n, pl->cb, w.codes, w.exps, (pre && fused_stats(pl)) ? w.kadd : nullptr,
                                    batch, pl->d_cap_mant, pl->d_cap_exp, s) != hipSuccess)
             return MXFFT_EHIP;
     }
@@ -753,7 +764,7 @@ mxfft_status plan_inverse_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     }
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 1, pre, pre ? nullptr : k_in, nullptr, kin_mul, -1, kout_add, false, batch, s));
-    } else if (pre && pl->fused) {
+    } else if (pre && fused_stats(pl)) {
         MX_TRY(row_with_stats(pl, w, in, nullptr, 1, batch, s));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
@@ -776,7 +787,7 @@ mxfft_status plan_roundtrip_ws(mxfft_plan_s* pl, const Workspace& w, const void*
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 2, pre, nullptr, k_out, 1, -1, -2 * pl->logn, false, batch, s));
     } else {
-        if (pre && pl->fused) {
+        if (pre && fused_stats(pl)) {
             MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
             MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
         } else {
@@ -823,7 +834,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     const int32_t* kp = pre ? w.kp : nullptr;
     if (op == 0) {
         const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
-        if (pre && pl->fused) {
+        if (pre && fused_stats(pl)) {
             MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
             MX_TRY(pass(pl, w, work, nullptr, kp, nullptr, 0, kout_mul, 0, 1, 0, recon, s, mxk::COL_RSS, w.kadd,
                         rss, coils));
@@ -835,7 +846,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
         }
     } else {
         // round trip: the forward result (kept scaled) goes to `work`
-        if (pre && pl->fused) {
+        if (pre && fused_stats(pl)) {
             MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
             MX_TRY(pass(pl, w, work, work, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
         } else {
@@ -937,8 +948,14 @@ mxfft_status mxfft_plan_set_tuning(mxfft_plan_t pl, const mxfft_tuning* t)
     const int r = t->lines;
     if (r != 0 && (r < 1 || r > pl->n || (r & (r - 1)) != 0 || (long)r * pl->n * 8 > 65536)) return MXFFT_EINVAL;
     if (t->single != 0 && (t->single != 1 || pl->n > mxk::kSmallN)) return MXFFT_EINVAL;
+    if (t->stats != 0 && t->stats != 1) return MXFFT_EINVAL;
+    const long nn = (long)pl->n * pl->n;
+    if (t->chunks != 0 && (t->chunks < 1 || (t->chunks & (t->chunks - 1)) != 0 || nn / t->chunks < 1024))
+        return MXFFT_EINVAL;
     pl->lines = r;
     pl->single = !pl->fast && t->single == 1;
+    pl->literal_stats = t->stats == 1;
+    pl->chunks = t->chunks;
     return MXFFT_OK;
 }
 
@@ -949,6 +966,8 @@ mxfft_status mxfft_plan_get_tuning(mxfft_plan_t pl, mxfft_tuning* t)
     t->fast = pl->fast ? 1 : 0;
     t->ms = 0.0;
     t->single = pl->single ? 1 : 0;
+    t->stats = (pl->fused && !pl->literal_stats) ? 0 : 1;
+    t->chunks = pl->chunks;
     return MXFFT_OK;
 }
 

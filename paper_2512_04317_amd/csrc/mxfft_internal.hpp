@@ -134,9 +134,10 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
 // Tiles (row chunks) per slice of the row pass with statistics.
 int fast_row_tiles(int n);
 
+// chunks: work-groups per slice (a power of two dividing n * n), 0 = by batch
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, const unsigned long long* slice_off,
-                        hipStream_t s);
+                        int chunks, hipStream_t s);
 // Alg. 1 from chunk statistics already in `parts` ([slice][chunks]) that the
 // row pass wrote; also the equivariance check: kadd[slice] = kp when the
 // unscaled row pass may stand, else 0 with the slice appended to fix_list.

@@ -399,10 +399,10 @@ size_t stats_parts(int n, int max_batch)
 
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,
                         int32_t* slice_status, const PrescaleArgs& pa, const unsigned long long* slice_off,
-                        hipStream_t s)
+                        int chunks, hipStream_t s)
 {
     const int nn = n * n;
-    const int chunks = stats_chunks(n, batch);
+    if (chunks <= 0 || nn % chunks != 0) chunks = stats_chunks(n, batch);
     hipLaunchKernelGGL(k_stats_part, dim3(chunks, batch), dim3(256), 0, s, x, nn, nn / chunks, chunks, parts,
                        slice_off);
     hipError_t e = hipGetLastError();

@@ -20,7 +20,7 @@ namespace {
 
 struct Entry {
     std::string arch;
-    int n = 0, format = 0, block = 0, lines = 0, single = 0;
+    int n = 0, format = 0, block = 0, lines = 0, single = 0, stats = 0, chunks = 0;
     double ms = 0.0;
 };
 
@@ -67,8 +67,10 @@ bool parse(const std::string& line, Entry* e)
     e->block = (int)b;
     e->lines = (int)l;
     e->ms = ms;
-    double one = 0.0;
-    e->single = find_num(line, "single", &one) ? (int)one : 0;   // absent in older entries
+    double one = 0.0;   // keys absent in older entries: the defaults
+    e->single = find_num(line, "single", &one) ? (int)one : 0;
+    e->stats = find_num(line, "stats", &one) ? (int)one : 0;
+    e->chunks = find_num(line, "chunks", &one) ? (int)one : 0;
     return true;
 }
 
@@ -77,8 +79,8 @@ std::string format_entry(const Entry& e)
     char buf[512];
     std::snprintf(buf, sizeof(buf),
                   "{\"arch\": \"%s\", \"n\": %d, \"format\": %d, \"block\": %d, \"lines\": %d, \"ms\": %.6f, "
-                  "\"single\": %d}",
-                  e.arch.c_str(), e.n, e.format, e.block, e.lines, e.ms, e.single);
+                  "\"single\": %d, \"stats\": %d, \"chunks\": %d}",
+                  e.arch.c_str(), e.n, e.format, e.block, e.lines, e.ms, e.single, e.stats, e.chunks);
     return buf;
 }
 
@@ -153,6 +155,8 @@ mxfft_status mxfft_tune_cache_lookup(const char* cache_path, const char* arch, i
             out->fast = 0;
             out->ms = e.ms;
             out->single = (n <= mxk::kSmallN) ? e.single : 0;
+            out->stats = e.stats;
+            out->chunks = e.chunks;
             return MXFFT_OK;
         }
     }
@@ -170,11 +174,12 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
     mxfft_tuning cur{};
     mxfft_plan_get_tuning(plan, &cur);
     const std::string arch = arch_name();
-    if (!cur.fast && cache_path && !(tune_flags & MXFFT_TUNE_FORCE)) {
+    if (cache_path && !(tune_flags & MXFFT_TUNE_FORCE)) {
         mxfft_tuning hit{};
         if (mxfft_tune_cache_lookup(cache_path, arch.c_str(), n, p, &hit) == MXFFT_OK &&
             mxfft_plan_set_tuning(plan, &hit) == MXFFT_OK) {
             *out = hit;
+            out->fast = cur.fast;
             return mxfft_plan_destroy(plan);
         }
     }
@@ -189,24 +194,43 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
     ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     ok = ok && mxk::launch_fill(x, count, 0x5EEDu + (uint32_t)n, s) == hipSuccess;
 
-    // candidates: the default and its halvings down to 1, and for n <= 64 the
-    // single-launch kernel (-1); the register-resident passes have none (they
-    // are timed once for the record)
-    std::vector<int> cand;
+    // candidates.  Line kernels: the default lines and its halvings down to
+    // 1, and for n <= 64 the single-launch kernel.  Register-resident passes:
+    // where the row pass can gather Alg. 1's statistics, that against the
+    // separate statistics read; the read with work-groups per slice by batch
+    // (0) or fixed at 1, 4, 16 (while a chunk keeps >= 1024 values and the
+    // sample's statistics fit the workspace)
+    std::vector<mxfft_tuning> cand;
     if (cur.fast) {
-        cand.push_back(0);
-    } else {
-        for (int r = mxk::line_lines_per_group(n); r >= 1 && (int)cand.size() < 5; r /= 2) cand.push_back(r);
-        if (n <= mxk::kSmallN) cand.push_back(-1);
-    }
-    int best = cand.empty() ? 0 : cand[0], best_lines = best;
-    double best_ms = 1e30, best_lines_ms = 1e30;
-    for (int r : cand) {
-        if (!ok) break;
+        const bool pre = !(p->flags & MXFFT_NO_PRESCALE);
         mxfft_tuning t{};
-        t.lines = r < 0 ? 0 : r;
-        t.single = r < 0 ? 1 : 0;
-        if (!cur.fast && mxfft_plan_set_tuning(plan, &t) != MXFFT_OK) continue;
+        if (cur.stats == 0) cand.push_back(t);   // fused statistics
+        t.stats = 1;
+        if (pre) {
+            for (int c : {0, 1, 4, 16}) {
+                if (c && ((long)n * n / c < 1024 || (size_t)c * sample > mxk::stats_parts(n, sample))) continue;
+                t.chunks = c;
+                cand.push_back(t);
+            }
+        }
+        if (cand.empty()) cand.push_back(mxfft_tuning{});
+    } else {
+        for (int r = mxk::line_lines_per_group(n); r >= 1 && (int)cand.size() < 5; r /= 2) {
+            mxfft_tuning t{};
+            t.lines = r;
+            cand.push_back(t);
+        }
+        if (n <= mxk::kSmallN) {
+            mxfft_tuning t{};
+            t.single = 1;
+            cand.push_back(t);
+        }
+    }
+    mxfft_tuning best = cand[0], best_lines = cand[0];
+    double best_ms = 1e30, best_lines_ms = 1e30;
+    for (const mxfft_tuning& t : cand) {
+        if (!ok) break;
+        if (mxfft_plan_set_tuning(plan, &t) != MXFFT_OK) continue;
         std::vector<float> ms;
         for (int rep = 0; rep < 4 && ok; rep++) {
             ok = hipEventRecord(e0, s) == hipSuccess;
@@ -221,11 +245,11 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
         const double med = ms[ms.size() / 2];
         if (med < best_ms) {
             best_ms = med;
-            best = r;
+            best = t;
         }
-        if (r >= 0 && med < best_lines_ms) {
+        if (!cur.fast && !t.single && med < best_lines_ms) {
             best_lines_ms = med;
-            best_lines = r;
+            best_lines = t;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -235,14 +259,16 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
     (void)hipFree(k);
     mxfft_plan_destroy(plan);
     if (!ok) return MXFFT_EHIP;
-    out->lines = cur.fast ? 0 : best_lines;
+    *out = best;
     out->fast = cur.fast;
     out->ms = best_ms;
-    out->single = best < 0 ? 1 : 0;
-    if (!cur.fast && cache_path) {
+    if (!cur.fast) out->lines = best_lines.lines;   // the line-kernel choice, even when single wins
+    if (cache_path) {
         Entry e = key_of(arch.c_str(), n, p);
-        e.lines = best_lines;
+        e.lines = out->lines;
         e.single = out->single;
+        e.stats = out->stats;
+        e.chunks = out->chunks;
         e.ms = best_ms;
         if (!store(cache_path, e)) return MXFFT_EINVAL;
     }

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("lines", ctypes.c_int32), ("fast", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("single", ctypes.c_int32)]
+                ("single", ctypes.c_int32), ("stats", ctypes.c_int32), ("chunks", ctypes.c_int32)]
 
 
 class Group(ctypes.Structure):
@@ -331,12 +331,14 @@ class Plan:
         st = lib().mxfft_plan_get_tuning(self.handle, ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_plan_get_tuning")
-        return {"lines": t.lines, "fast": bool(t.fast), "single": bool(t.single)}
+        return {"lines": t.lines, "fast": bool(t.fast), "single": bool(t.single), "stats": t.stats, "chunks": t.chunks}
 
-    def set_tuning(self, lines, single=False):
+    def set_tuning(self, lines=0, single=False, stats=0, chunks=0):
         """Line kernels with `lines` per work-group, or (n <= 64, single=True)
-        the single-launch kernel."""
-        t = Tuning(int(lines), 0, 0.0, 1 if single else 0)
+        the single-launch kernel; stats=1: Alg. 1 as a separate read (with
+        `chunks` work-groups per slice, 0 = by batch) where the row pass could
+        gather it."""
+        t = Tuning(int(lines), 0, 0.0, 1 if single else 0, int(stats), int(chunks))
         st = lib().mxfft_plan_set_tuning(self.handle, ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_plan_set_tuning")
@@ -372,7 +374,8 @@ def tune(n, sample=16, cache=None, force=False, stream=None, **params):
                           ctypes.byref(t), _stream(stream))
     if st != OK:
         raise MxfftError(st, "mxfft_tune")
-    return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single)}
+    return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single),
+            "stats": t.stats, "chunks": t.chunks}
 
 
 def tune_cache_lookup(cache, arch, n, **params):
@@ -380,7 +383,8 @@ def tune_cache_lookup(cache, arch, n, **params):
     p = make_params(**params)
     t = Tuning()
     st = lib().mxfft_tune_cache_lookup(_cpath(cache), arch.encode(), int(n), ctypes.byref(p), ctypes.byref(t))
-    return None if st != OK else {"lines": t.lines, "ms": t.ms, "single": bool(t.single)}
+    return None if st != OK else {"lines": t.lines, "ms": t.ms, "single": bool(t.single),
+            "stats": t.stats, "chunks": t.chunks}
 
 
 class Batch:
@@ -438,7 +442,8 @@ class Batch:
         st = lib().mxfft_batch_group_tuning(self.handle, int(g), ctypes.byref(t))
         if st != OK:
             raise MxfftError(st, "mxfft_batch_group_tuning")
-        return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single)}
+        return {"lines": t.lines, "fast": bool(t.fast), "ms": t.ms, "single": bool(t.single),
+            "stats": t.stats, "chunks": t.chunks}
 
     def close(self):
         if getattr(self, "handle", None):

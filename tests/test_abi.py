@@ -94,13 +94,13 @@ def test_tune_cache_lookup_host(tmp_path):
         '{"arch": "gfx950:sramecc+:xnack-", "n": 64, "format": 2, "block": 0, "lines": 16, "ms": 0.125}\n'
         '{"arch": "gfx950:sramecc+:xnack-", "n": 32, "format": 0, "block": 32, "lines": 8, "ms": 0.1, "single": 1}\n')
     arch = "gfx950:sramecc+:xnack-"
-    off = {"single": False}
+    off = {"single": False, "stats": 0, "chunks": 0}
     assert mxfft.tune_cache_lookup(str(path), arch, 256) == dict(off, lines=8, ms=0.25)
     assert mxfft.tune_cache_lookup(str(path), arch, 256, block=16) == dict(off, lines=4, ms=0.5)
     assert mxfft.tune_cache_lookup(str(path), "gfx942", 256) == dict(off, lines=2, ms=1.0)
     assert mxfft.tune_cache_lookup(str(path), arch, 64, fmt="fp16", block=8) == dict(off, lines=16, ms=0.125)
     # n <= 64: the single-launch choice (entries without the key keep the line kernels)
-    assert mxfft.tune_cache_lookup(str(path), arch, 32) == {"lines": 8, "ms": 0.1, "single": True}
+    assert mxfft.tune_cache_lookup(str(path), arch, 32) == dict(off, lines=8, ms=0.1, single=True)
     assert mxfft.tune_cache_lookup(str(path), arch, 128) is None
     assert mxfft.tune_cache_lookup(str(path), arch, 256, fmt="e5m2") is None
     assert mxfft.tune_cache_lookup(str(tmp_path / "missing.json"), arch, 256) is None

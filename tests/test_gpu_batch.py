@@ -207,3 +207,29 @@ def test_per_reconstruction_work_list():
             if gi != bad:
                 assert st == O.OK and np.array_equal(bits(yb[gi].numpy()), bits(yo)), "group %d vs oracle" % gi
     b.close()
+
+
+@pytest.mark.parametrize("n,fmt,block", [(512, "e4m3", 32), (1024, "e5m2", 16), (256, "e4m3", 8), (512, "fp16", 32)])
+def test_register_resident_tuning_choices_are_bit_identical(n, fmt, block):
+    """The tuned choices of the register-resident passes (Alg. 1 gathered by
+    the row pass or read separately, work-groups per slice of that read) give
+    the same bits and k; the tuner records its pick."""
+    x = synth.kspace_batch(n, 4, 1, 5)
+    x[2] *= np.float32(2.0 ** -110)                      # a literal redo under the fused statistics
+    xd = torch.from_numpy(x).cuda()
+    print("tuning choices: %d^2 %s B=%d" % (n, fmt, block), flush=True)
+    with mxfft.Plan(n, 5, fmt=fmt, block=block) as pl:
+        y0, k0 = pl.forward(xd)
+        y0, k0 = y0.cpu().numpy().copy(), k0.cpu().numpy().copy()
+        for stats, chunks in ((1, 0), (1, 1), (1, 4), (0, 16)):
+            pl.set_tuning(stats=stats, chunks=chunks)
+            assert pl.tuning()["chunks"] == chunks
+            y, k = pl.forward(xd)
+            assert pl.last_status() == mxfft.OK
+            torch.cuda.synchronize()
+            assert np.array_equal(bits(y.cpu().numpy()), bits(y0)), (stats, chunks)
+            assert np.array_equal(k.cpu().numpy(), k0)
+        with pytest.raises(mxfft.MxfftError):
+            pl.set_tuning(chunks=3)
+    t = mxfft.tune(n, sample=8, force=True, fmt=fmt, block=block)
+    assert t["fast"] and t["stats"] in (0, 1) and t["ms"] > 0
