@@ -400,6 +400,14 @@ def rss_quality(args, torch, mxfft, x, xd, N, recon=8, coils=16):
                                   "output_bytes_per_slice": N * N * 4 / coils}}
 
 
+def apply_tuning(mxfft, plan, n, batch, kw):
+    """Run the autotuner for this plan's shape on the batch size and apply its
+    pick; returns the choice."""
+    t = mxfft.tune(n, sample=batch, force=True, **kw)
+    plan.set_tuning(t["lines"], single=t["single"], stats=t["stats"], chunks=t["chunks"])
+    return {k: t[k] for k in ("fast", "lines", "single", "stats", "chunks")}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -460,6 +468,9 @@ def main():
         torch.cuda.synchronize()
 
     plan = mxfft.Plan(N, batch, fmt=args.fmt, block=args.block)
+    # the library's autotuner picks the launch choices for this batch (every
+    # choice gives the same bits); its pick is part of the configuration
+    tuned = apply_tuning(mxfft, plan, N, batch, dict(fmt=args.fmt, block=args.block))
     fwd = lambda: plan.forward(xd, out=out, k_out=kout)   # noqa: E731
     for _ in range(args.warmup):
         fwd()
@@ -533,6 +544,7 @@ def main():
                                "forward with Alg. 1 prescale" % (args.workload, batch, w["slices"], w["coils"],
                                                                   N, N, args.fmt.upper(), args.block),
                    "n": N, "batch": batch, "format": args.fmt, "block": args.block, "direction": "forward",
+                   "tuning": tuned,
                    "prescale": {"target": 128.0, "tau_pct": 5.0, "tau_min": 2.0 ** -6}},
         "roofline": roofline,
         "hbm_frac_whole_step": round(step_frac, 4),
@@ -559,6 +571,7 @@ def main():
                          ("fp16", dict(fmt="fp16")), ("bf16", dict(fmt="bf16")),
                          ("fp32", dict(fmt="fp32", flags=mxfft.NO_PRESCALE))):
             pl = mxfft.Plan(N, batch, **kw)
+            t_sw = apply_tuning(mxfft, pl, N, batch, kw)
             fn = lambda: pl.forward(xd, out=out, k_out=kout)   # noqa: E731
             wall_f, _ = timed_steps(fn, args.steps, args.warmup, torch)
             assert pl.last_status() == mxfft.OK, name
@@ -568,7 +581,7 @@ def main():
             psf = 20 * np.log10(np.abs(ref).max(axis=(1, 2)) / np.sqrt(msef))
             sweep[name] = {"value": round(batch * args.steps / wall_f, 1), "ms_per_step": round(1e3 * wall_f / args.steps, 4),
                            "nrmse_vs_fp64": {"mean": float("%.4g" % ef.mean()), "max": float("%.4g" % ef.max())},
-                           "psnr_db_vs_fp64": round(float(psf.mean()), 2)}
+                           "psnr_db_vs_fp64": round(float(psf.mean()), 2), "tuning": t_sw}
             pl.close()
         result["precision_sweep"] = {"unit": "slices/s", "direction": "forward", "formats": sweep}
         result["speedup_vs_fp32"] = round(slices_per_s / sweep["fp32"]["value"], 3)

@@ -226,23 +226,46 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
             cand.push_back(t);
         }
     }
+    // timing: the GPU first runs the default for at least 20 ms (clocks up
+    // from idle), then the candidates take turns, one call each per round,
+    // so that clock drift touches them all alike; median over 5 rounds
+    auto timed_call = [&](float* t_ms) {
+        bool r = hipEventRecord(e0, s) == hipSuccess;
+        r = r && mxfft_forward(plan, x, y, sample, k, stream) == MXFFT_OK;
+        r = r && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        return r && hipEventElapsedTime(t_ms, e0, e1) == hipSuccess;
+    };
+    std::vector<char> usable(cand.size(), 0);
+    for (size_t c = 0; c < cand.size() && ok; c++) {
+        usable[c] = mxfft_plan_set_tuning(plan, &cand[c]) == MXFFT_OK;
+        float t_ms = 0.f;
+        if (usable[c]) ok = timed_call(&t_ms);   // first call of each candidate: warm-up
+    }
+    if (ok) {
+        const mxfft_tuning d{};
+        ok = mxfft_plan_set_tuning(plan, &cand[0]) == MXFFT_OK || mxfft_plan_set_tuning(plan, &d) == MXFFT_OK;
+        float spent = 0.f;
+        for (int w = 0; w < 200 && ok && spent < 20.f; w++) {
+            float t_ms = 0.f;
+            ok = timed_call(&t_ms);
+            spent += t_ms;
+        }
+    }
+    std::vector<std::vector<float>> ms(cand.size());
+    for (int round = 0; round < 5 && ok; round++)
+        for (size_t c = 0; c < cand.size() && ok; c++) {
+            if (!usable[c]) continue;
+            float t_ms = 0.f;
+            ok = mxfft_plan_set_tuning(plan, &cand[c]) == MXFFT_OK && timed_call(&t_ms);
+            ms[c].push_back(t_ms);
+        }
     mxfft_tuning best = cand[0], best_lines = cand[0];
     double best_ms = 1e30, best_lines_ms = 1e30;
-    for (const mxfft_tuning& t : cand) {
-        if (!ok) break;
-        if (mxfft_plan_set_tuning(plan, &t) != MXFFT_OK) continue;
-        std::vector<float> ms;
-        for (int rep = 0; rep < 4 && ok; rep++) {
-            ok = hipEventRecord(e0, s) == hipSuccess;
-            ok = ok && mxfft_forward(plan, x, y, sample, k, stream) == MXFFT_OK;
-            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-            float t_ms = 0.f;
-            ok = ok && hipEventElapsedTime(&t_ms, e0, e1) == hipSuccess;
-            if (rep > 0) ms.push_back(t_ms);   // the first call warms up
-        }
-        if (!ok || ms.empty()) break;
-        std::sort(ms.begin(), ms.end());
-        const double med = ms[ms.size() / 2];
+    for (size_t c = 0; c < cand.size() && ok; c++) {
+        if (ms[c].empty()) continue;
+        std::sort(ms[c].begin(), ms[c].end());
+        const double med = ms[c][ms[c].size() / 2];
+        const mxfft_tuning& t = cand[c];
         if (med < best_ms) {
             best_ms = med;
             best = t;

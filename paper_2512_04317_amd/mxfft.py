@@ -367,7 +367,9 @@ def _cpath(path):
 
 
 def tune(n, sample=16, cache=None, force=False, stream=None, **params):
-    """Autotune the generic line kernels for n (see mxfft_tune)."""
+    """Autotune the launch choices for n x n plans of these parameters on
+    `sample` slices (see mxfft_tune): lines and the single launch on the line
+    kernels, the statistics read on the register-resident passes."""
     p = make_params(**params)
     t = Tuning()
     st = lib().mxfft_tune(int(n), ctypes.byref(p), int(sample), _cpath(cache), TUNE_FORCE if force else 0,
