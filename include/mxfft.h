@@ -210,10 +210,17 @@ mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t cou
  *   mant: complex64 [batch][n][n] element values (the decoded codes without
  *         the block scale: E4M3/E5M2/E2M3/E3M2 values, signed zeros kept);
  *   exps: int32 [batch][n][n / (B/2)] shared exponent E of column c and row
- *         block r at [slice][c][r] (value = mant * 2^E).
+ *         block r at [slice][c][r] (value = mant * 2^E);
+ *   trace (nullable): int32 [batch][log2 n][n / B][3], for row 0 of each
+ *         slice's row pass, every stage's butterfly blocks' (E_v, k_r,
+ *         E_out) of Alg. 2 (v's shared exponent, the renormalisation, the
+ *         product's scale exponent E_w + E_v + k_r).  Recorded by the line
+ *         kernels and the single-launch kernel only: MXFFT_EUNSUPPORTED when
+ *         the call ran on the register-resident passes.
  * 1 <= batch <= the batch of that call; MXFFT_EINVAL otherwise (also for a
  * plan without the flag or before any forward call). */
-mxfft_status mxfft_plan_capture(mxfft_plan_t plan, void* mant, int32_t* exps, int32_t batch, void* stream);
+mxfft_status mxfft_plan_capture(mxfft_plan_t plan, void* mant, int32_t* exps, int32_t* trace, int32_t batch,
+                                void* stream);
 
 /* Synchronise `stream` and return the device status of the plan's last call
  * (MXFFT_OK, MXFFT_ENONFINITE or MXFFT_ERANGE). */
@@ -260,8 +267,10 @@ typedef struct {
     int32_t fast;    /* out: 1 when the plan runs the register-resident passes,
                         which have no such parameter (lines is then ignored) */
     double ms;       /* out (tuner): time of one forward call over its sample */
-    int32_t single;  /* n <= 64: 1 = the single-launch kernel (lines ignored),
-                        0 = the line kernels with `lines`; must be 0 for n > 64 */
+    int32_t single;  /* n <= 128: 1 = the single-launch kernel (the default
+                        for n <= 64; lines ignored), 0 = the line kernels with
+                        `lines` or the register-resident passes; must be 0
+                        for n > 128 */
     int32_t stats;   /* Alg. 1 with the prescale: 0 = gathered by the row pass
                         where the plan can (register-resident MX passes at
                         n = 512 and 1024), 1 = a separate statistics read of

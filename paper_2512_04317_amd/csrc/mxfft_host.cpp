@@ -115,7 +115,9 @@ struct mxfft_plan_s {
     // MXFFT_DEBUG_CAPTURE: the column pass input of the last forward call
     float2* d_cap_mant = nullptr;
     int32_t* d_cap_exp = nullptr;
+    int32_t* d_cap_trace = nullptr;  // row pass line 0: (E_v, k_r, E_out) per stage and block
     int cap_batch = 0;
+    bool cap_trace_ok = false;       // the last capture ran on kernels that record the trace
     uint64_t bytes = 0;
     int last_batch = 0;
     bool last_has_stats = false;
@@ -238,6 +240,7 @@ void release(mxfft_plan_s* pl)
     (void)hipFree(pl->d_tw16);
     (void)hipFree(pl->d_cap_mant);
     (void)hipFree(pl->d_cap_exp);
+    (void)hipFree(pl->d_cap_trace);
     (void)hipFree(pl->ws.parts);
     (void)hipFree(pl->ws.kp);
     (void)hipFree(pl->ws.status);
@@ -391,6 +394,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     a.encode = mxk::is_mx_mode(pl->mode) && kind != mxk::ROW_RAW;
     a.cap_mant = capture ? pl->d_cap_mant : nullptr;
     a.cap_exp = capture ? pl->d_cap_exp : nullptr;
+    a.cap_trace = capture ? pl->d_cap_trace : nullptr;
     a.slice_off = w.slice_off;
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
@@ -431,6 +435,7 @@ mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, vo
     g.a.logcb = pl->logcb;
     g.a.cap_mant = capture ? pl->d_cap_mant : nullptr;
     g.a.cap_exp = capture ? pl->d_cap_exp : nullptr;
+    g.a.cap_trace = capture ? pl->d_cap_trace : nullptr;
     g.a.slice_off = w.slice_off;
     g.pa = prescale_args(pl);
     g.op = op;
@@ -557,7 +562,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
 
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
-    pl->single = !pl->fast && n <= mxk::kSmallN;
+    pl->single = !pl->fast && n <= mxk::kSmallDefaultN;
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw_exp, tw_exp.size());
@@ -575,6 +580,8 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     if (st == MXFFT_OK && (p->flags & MXFFT_DEBUG_CAPTURE)) {
         st = dev_alloc(pl, &pl->d_cap_mant, (size_t)max_batch * n * n);
         if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_cap_exp, (size_t)max_batch * n * (n / pl->cb));
+        if (st == MXFFT_OK)
+            st = dev_alloc(pl, &pl->d_cap_trace, (size_t)max_batch * pl->logn * (n / (2 * pl->cb)) * 3);
     }
     std::vector<float2> twf;
     std::vector<uint32_t> tw16;
@@ -708,17 +715,20 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
         if (pre) MX_TRY(stats(pl, w, in, batch, s));
-        MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
+        MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr, 0, cap));
         MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr,
                     0, cap));
     }
-    if (cap && pl->fast) {
+    if (cap && pl->fast && !pl->single) {
         // the register-resident intermediate holds the column pass input
         if (mxk::launch_capture_mx(pl->mode, pl->n, pl->cb, w.codes, w.exps, (pre && fused_stats(pl)) ? w.kadd : nullptr,
                                    batch, pl->d_cap_mant, pl->d_cap_exp, s) != hipSuccess)
             return MXFFT_EHIP;
     }
-    if (cap) pl->cap_batch = batch;
+    if (cap) {
+        pl->cap_batch = batch;
+        pl->cap_trace_ok = pl->single || !pl->fast;
+    }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     pl->last_status = w.status;
@@ -872,14 +882,19 @@ mxfft_status mxfft_ssim(const float* x, const float* ref, int32_t n, int32_t cou
     return mxk::launch_ssim(x, ref, n, count, ssim, (hipStream_t)stream) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
-mxfft_status mxfft_plan_capture(mxfft_plan_t pl, void* mant, int32_t* exps, int32_t batch, void* stream)
+mxfft_status mxfft_plan_capture(mxfft_plan_t pl, void* mant, int32_t* exps, int32_t* trace, int32_t batch,
+                                void* stream)
 {
     if (!pl || !mant || !exps || !pl->d_cap_mant || batch < 1 || batch > pl->cap_batch) return MXFFT_EINVAL;
+    if (trace && !pl->cap_trace_ok) return MXFFT_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const size_t nn = (size_t)pl->n * pl->n, b = (size_t)batch;
     if (hipMemcpyAsync(mant, pl->d_cap_mant, b * nn * sizeof(float2), hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(exps, pl->d_cap_exp, b * pl->n * (pl->n / pl->cb) * sizeof(int32_t), hipMemcpyDeviceToDevice,
                        s) != hipSuccess)
+        return MXFFT_EHIP;
+    if (trace && hipMemcpyAsync(trace, pl->d_cap_trace, b * pl->logn * (pl->n / (2 * pl->cb)) * 3 * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MXFFT_EHIP;
     return MXFFT_OK;
 }
@@ -953,7 +968,7 @@ mxfft_status mxfft_plan_set_tuning(mxfft_plan_t pl, const mxfft_tuning* t)
     if (t->chunks != 0 && (t->chunks < 1 || (t->chunks & (t->chunks - 1)) != 0 || nn / t->chunks < 1024))
         return MXFFT_EINVAL;
     pl->lines = r;
-    pl->single = !pl->fast && t->single == 1;
+    pl->single = t->single == 1;
     pl->literal_stats = t->stats == 1;
     pl->chunks = t->chunks;
     return MXFFT_OK;

@@ -91,6 +91,8 @@ struct LineArgs {
     float2* cap_mant;        // column pass: its encoded input's element values, or nullptr
     int32_t* cap_exp;        // column pass: its input block exponents [slice][column][row block]
     const unsigned long long* slice_off;  // slice offsets in src / dst, or nullptr (contiguous)
+    int32_t* cap_trace;      // row pass, debug capture: (E_v, k_r, E_out) per stage and block of line 0,
+                             // [slice][log2 n][n / B][3], or nullptr
 };
 
 // MX formats, the 16-bit positive controls (per-operation rounding) and plain FP32
@@ -149,8 +151,10 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 
 // Single-launch transform of slices of n <= kSmallN (one work-group per
-// slice: Alg. 1, all passes and the output in LDS).
-constexpr int kSmallN = 64;
+// slice: Alg. 1, all passes and the output in LDS); the default for n <= 64,
+// a tuning choice at 128.
+constexpr int kSmallN = 128;
+constexpr int kSmallDefaultN = 64;
 struct SmallArgs {
     LineArgs a;                // tables, n, block, src, dst, k_out, capture pointers
     PrescaleArgs pa;

@@ -426,9 +426,10 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
 // One radix-2 pass over lines held in LDS
 // ---------------------------------------------------------------------------
 
+// tr (MX, nullable): receives the block's (E_v, k_r, E_out) of Alg. 2.
 template <int MODE>
 __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float2 u, float2 v,
-                                          float2& y0, float2& y1)
+                                          float2& y0, float2& y1, int32_t* tr = nullptr)
 {
     const int h = 1 << (s - 1);
     float2 w = a.tw[h - 1 + j];
@@ -463,6 +464,11 @@ __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float
         const float cr = mxd::quant<F>(ldexpf(qr, -kr));
         const float ci = mxd::quant<F>(ldexpf(qi, -kr));
         const int Eo = Ew + Ev + kr;
+        if (tr) {
+            tr[0] = Ev;
+            tr[1] = kr;
+            tr[2] = Eo;
+        }
         pr = ldexpf(cr, Eo);
         pi = ldexpf(ci, Eo);
     }
@@ -557,7 +563,11 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
             const int g = t >> (s - 1), j = t & (h - 1);
             const int iu = r * N + (g << s) + j, iv = iu + h;
             float2 y0, y1;
-            butterfly<MODE>(a, s, j, lds[iu], lds[iv], y0, y1);
+            // debug capture: the block exponents of line 0 of the row pass
+            int32_t* tr = nullptr;
+            if (a.cap_trace && a.axis == 0 && line0 + r == 0 && (t & (a.cb - 1)) == 0)
+                tr = a.cap_trace + ((size_t)slice * logn + (s - 1)) * 3 * (half >> a.logcb) + 3 * (t >> a.logcb);
+            butterfly<MODE>(a, s, j, lds[iu], lds[iv], y0, y1, tr);
             lds[iu] = y0;
             lds[iv] = y1;
         }
@@ -652,7 +662,6 @@ hipError_t launch_capture_mx(int mode, int n, int cb, const uint32_t* codes, con
 // ---------------------------------------------------------------------------
 
 constexpr int kSmallMaxN = kSmallN;
-constexpr int kSmallPitch = kSmallMaxN + 1;
 
 // One 1D pass over the n lines of the slice in buf: rows (element e of line r
 // at r * pitch + e) or columns (at e * pitch + r).  encode: MX-encode the
@@ -662,10 +671,10 @@ constexpr int kSmallPitch = kSmallMaxN + 1;
 // recorded (debug capture of the forward's column pass).
 template <int MODE>
 __device__ void small_pass(const LineArgs& a, float2* buf, bool cols, bool encode, float2* cap_mant,
-                           int32_t* cap_exp, int slice)
+                           int32_t* cap_exp, int32_t* cap_trace, int slice)
 {
-    const int N = a.n, logn = a.logn, tid = threadIdx.x, total = N * N;
-    auto at = [&](int r, int e) -> float2& { return cols ? buf[e * kSmallPitch + r] : buf[r * kSmallPitch + e]; };
+    const int N = a.n, logn = a.logn, tid = threadIdx.x, total = N * N, pitch = N + 1;
+    auto at = [&](int r, int e) -> float2& { return cols ? buf[e * pitch + r] : buf[r * pitch + e]; };
     if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
         for (int idx = tid; idx < total; idx += blockDim.x) {
             float2& v = at(idx >> logn, idx & (N - 1));
@@ -711,7 +720,10 @@ __device__ void small_pass(const LineArgs& a, float2* buf, bool cols, bool encod
             const int g = t >> (st - 1), j = t & (h - 1);
             const int iu = (g << st) + j, iv = iu + h;
             float2 y0, y1;
-            butterfly<MODE>(a, st, j, at(r, iu), at(r, iv), y0, y1);
+            int32_t* tr = nullptr;   // debug capture: the block exponents of line 0
+            if (cap_trace && r == 0 && (t & (a.cb - 1)) == 0)
+                tr = cap_trace + ((size_t)slice * logn + (st - 1)) * 3 * (half >> a.logcb) + 3 * (t >> a.logcb);
+            butterfly<MODE>(a, st, j, at(r, iu), at(r, iv), y0, y1, tr);
             at(r, iu) = y0;
             at(r, iv) = y1;
         }
@@ -729,9 +741,9 @@ __device__ void small_pass(const LineArgs& a, float2* buf, bool cols, bool encod
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
 {
-    __shared__ float2 buf[kSmallMaxN * kSmallPitch];
+    extern __shared__ float2 buf[];     // n x (n + 1) complex values
     __shared__ Alg1Smem S;
-    const int tid = threadIdx.x, slice = blockIdx.x, N = g.a.n, logn = g.a.logn, nn = N * N;
+    const int tid = threadIdx.x, slice = blockIdx.x, N = g.a.n, logn = g.a.logn, nn = N * N, pitch = N + 1;
     const float2* xs = g.a.src + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
     if (g.stats) {
         alg1_init(S);
@@ -744,7 +756,7 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
         uint32_t cnt = 0, mc = 0, nf = 0;
         for (int i = tid; i < nn; i += blockDim.x) {
             const float2 v = xs[i];
-            buf[(i >> logn) * kSmallPitch + (i & (N - 1))] = v;
+            buf[(i >> logn) * pitch + (i & (N - 1))] = v;
             if (g.stats) {
                 const uint32_t br = __float_as_uint(v.x), bi = __float_as_uint(v.y);
                 const uint32_t bad = ((br & 0x7f800000u) == 0x7f800000u) | ((bi & 0x7f800000u) == 0x7f800000u);
@@ -784,7 +796,7 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
     const int kin = g.kin_mul * k;
     if (kin) {
         for (int i = tid; i < nn; i += blockDim.x) {
-            float2& v = buf[(i >> logn) * kSmallPitch + (i & (N - 1))];
+            float2& v = buf[(i >> logn) * pitch + (i & (N - 1))];
             v = make_float2(ldexpf(v.x, kin), ldexpf(v.y, kin));
         }
         __syncthreads();
@@ -792,17 +804,17 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
     constexpr bool MX = MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16;
     LineArgs a = g.a;
     a.inverse = g.op == 1;
-    small_pass<MODE>(a, buf, false, MX, nullptr, nullptr, slice);
-    small_pass<MODE>(a, buf, true, MX, g.op == 0 ? g.a.cap_mant : nullptr, g.a.cap_exp, slice);
+    small_pass<MODE>(a, buf, false, MX, nullptr, nullptr, g.op == 0 ? g.a.cap_trace : nullptr, slice);
+    small_pass<MODE>(a, buf, true, MX, g.op == 0 ? g.a.cap_mant : nullptr, g.a.cap_exp, nullptr, slice);
     if (g.op == 2) {
         a.inverse = 1;
-        small_pass<MODE>(a, buf, false, MX && !g.raw_inverse_rows, nullptr, nullptr, slice);
-        small_pass<MODE>(a, buf, true, MX, nullptr, nullptr, slice);
+        small_pass<MODE>(a, buf, false, MX && !g.raw_inverse_rows, nullptr, nullptr, nullptr, slice);
+        small_pass<MODE>(a, buf, true, MX, nullptr, nullptr, nullptr, slice);
     }
     const int kout = g.kout_mul * k + g.kout_add;
     float2* ys = g.a.dst + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
     for (int i = tid; i < nn; i += blockDim.x) {
-        const float2 v = buf[(i >> logn) * kSmallPitch + (i & (N - 1))];
+        const float2 v = buf[(i >> logn) * pitch + (i & (N - 1))];
         ys[i] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));
     }
 }
@@ -810,17 +822,19 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
 hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s)
 {
     if (g.a.n > kSmallMaxN) return hipErrorInvalidValue;
-    // one thread per butterfly of a pass (at least one wave)
+    // one thread per butterfly of a pass (at least one wave); the slice in LDS
+    // with a row pitch of n + 1 (132 KiB at 128^2)
     const int bf = g.a.n * g.a.n / 2;
     const dim3 grid(batch), block(bf < 64 ? 64 : bf > 1024 ? 1024 : bf);
+    const size_t lds = (size_t)g.a.n * (g.a.n + 1) * sizeof(float2);
     switch (mode) {
-    case MODE_E4M3: hipLaunchKernelGGL(k_small<MODE_E4M3>, grid, block, 0, s, g); break;
-    case MODE_E5M2: hipLaunchKernelGGL(k_small<MODE_E5M2>, grid, block, 0, s, g); break;
-    case MODE_E2M3: hipLaunchKernelGGL(k_small<MODE_E2M3>, grid, block, 0, s, g); break;
-    case MODE_E3M2: hipLaunchKernelGGL(k_small<MODE_E3M2>, grid, block, 0, s, g); break;
-    case MODE_FP16: hipLaunchKernelGGL(k_small<MODE_FP16>, grid, block, 0, s, g); break;
-    case MODE_BF16: hipLaunchKernelGGL(k_small<MODE_BF16>, grid, block, 0, s, g); break;
-    case MODE_FP32: hipLaunchKernelGGL(k_small<MODE_FP32>, grid, block, 0, s, g); break;
+    case MODE_E4M3: hipLaunchKernelGGL(k_small<MODE_E4M3>, grid, block, lds, s, g); break;
+    case MODE_E5M2: hipLaunchKernelGGL(k_small<MODE_E5M2>, grid, block, lds, s, g); break;
+    case MODE_E2M3: hipLaunchKernelGGL(k_small<MODE_E2M3>, grid, block, lds, s, g); break;
+    case MODE_E3M2: hipLaunchKernelGGL(k_small<MODE_E3M2>, grid, block, lds, s, g); break;
+    case MODE_FP16: hipLaunchKernelGGL(k_small<MODE_FP16>, grid, block, lds, s, g); break;
+    case MODE_BF16: hipLaunchKernelGGL(k_small<MODE_BF16>, grid, block, lds, s, g); break;
+    case MODE_FP32: hipLaunchKernelGGL(k_small<MODE_FP32>, grid, block, lds, s, g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

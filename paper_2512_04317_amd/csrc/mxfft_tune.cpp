@@ -214,6 +214,11 @@ mxfft_status mxfft_tune(int32_t n, const mxfft_params* p, int32_t sample, const 
             }
         }
         if (cand.empty()) cand.push_back(mxfft_tuning{});
+        if (n <= mxk::kSmallN) {   // 128^2: the single launch against the register-resident passes
+            mxfft_tuning one{};
+            one.single = 1;
+            cand.push_back(one);
+        }
     } else {
         for (int r = mxk::line_lines_per_group(n); r >= 1 && (int)cand.size() < 5; r /= 2) {
             mxfft_tuning t{};

@@ -104,7 +104,7 @@ def lib():
         L.mxfft_plan_last_status.restype = i32
         L.mxfft_plan_last_status.argtypes = [P, P]
         L.mxfft_plan_capture.restype = i32
-        L.mxfft_plan_capture.argtypes = [P, P, P, i32, P]
+        L.mxfft_plan_capture.argtypes = [P, P, P, P, i32, P]
         L.mxfft_plan_profile.restype = i32
         L.mxfft_plan_profile.argtypes = [P, i32]
         L.mxfft_plan_profile_roles.restype = i32
@@ -285,18 +285,23 @@ class Plan:
             raise MxfftError(st, "mxfft_rss")
         return out, k_out
 
-    def capture(self, batch, stream=None):
+    def capture(self, batch, trace=False, stream=None):
         """DEBUG_CAPTURE plans: the column pass's MX input of the last forward
         call (its first `batch` slices): element values complex64 [batch, n, n]
-        and block exponents int32 [batch, n (columns), n / (B/2) (row blocks)]."""
+        and block exponents int32 [batch, n (columns), n / (B/2) (row blocks)];
+        with trace, also int32 [batch, log2 n, n / B, 3]: (E_v, k_r, E_out)
+        per stage and block of row 0's row pass."""
         cb = self.params.block // 2
         dev = torch.device("cuda", torch.cuda.current_device())
         mant = torch.empty((batch, self.n, self.n), dtype=torch.complex64, device=dev)
         exps = torch.empty((batch, self.n, self.n // cb), dtype=torch.int32, device=dev)
-        st = lib().mxfft_plan_capture(self.handle, _ptr(mant), _ptr(exps), int(batch), _stream(stream))
+        tr = None
+        if trace:
+            tr = torch.empty((batch, self.n.bit_length() - 1, self.n // (2 * cb), 3), dtype=torch.int32, device=dev)
+        st = lib().mxfft_plan_capture(self.handle, _ptr(mant), _ptr(exps), _ptr(tr), int(batch), _stream(stream))
         if st != OK:
             raise MxfftError(st, "mxfft_plan_capture")
-        return mant, exps
+        return (mant, exps, tr) if trace else (mant, exps)
 
     def last_status(self, stream=None):
         return lib().mxfft_plan_last_status(self.handle, _stream(stream))

@@ -62,6 +62,40 @@ def test_column_pass_input_matches_oracle_encode(N, fmt, B):
             s, bad.sum(), np.argwhere(bad)[:3].tolist())
 
 
+@pytest.mark.parametrize("N,fmt,B,single", [(8, "e4m3", 4, True), (64, "e5m2", 16, True), (64, "e4m3", 32, False),
+                                            (128, "e2m3", 16, True), (256, "e4m3", 64, False)])
+def test_stage_exponents_match_oracle_trace(N, fmt, B, single):
+    """Alg. 2's block exponents at every stage (E_v, k_r, E_out) of row 0's
+    row pass, recorded by the single-launch kernel and the line kernels, bit
+    for bit against the oracle's trace of its own row pass."""
+    batch = 3
+    x = synth.kspace_batch(N, 8, 1, batch)
+    x[2] *= np.float32(2.0 ** -100)
+    print("trace case: N=%d %s B=%d single=%s" % (N, fmt, B, single), flush=True)
+    with mxfft.Plan(N, batch, fmt=fmt, block=B, flags=mxfft.DEBUG_CAPTURE) as plan:
+        plan.set_tuning(0, single=single)
+        xd = torch.from_numpy(x).cuda()
+        _, k = plan.forward(xd)
+        assert plan.last_status() == mxfft.OK
+        _, _, tr = plan.capture(batch, trace=True)
+        torch.cuda.synchronize()
+        trg = tr.cpu().numpy()
+    for s in range(batch):
+        st, ko = O.prescale(x[s])
+        xs = np.ldexp(x[s].view(np.float32), ko).astype(np.float32).view(np.complex64)
+        _, tro = O.pass_lines(xs[:1], mode=O.MODE_MX, fmt=FMTS[fmt], B=B, trace=True)
+        np.testing.assert_array_equal(trg[s], tro, err_msg="slice %d stage exponents" % s)
+
+
+def test_trace_needs_the_line_or_single_kernels():
+    with mxfft.Plan(256, 1, fmt="e4m3", block=32, flags=mxfft.DEBUG_CAPTURE) as plan:
+        plan.forward(torch.from_numpy(synth.kspace_batch(256, 8, 1, 1)).cuda())
+        plan.capture(1)                                    # the register-resident intermediate: fine
+        with pytest.raises(mxfft.MxfftError) as e:
+            plan.capture(1, trace=True)
+        assert e.value.status == mxfft.EUNSUPPORTED
+
+
 def test_capture_needs_the_flag_and_a_call():
     with mxfft.Plan(64, 2, fmt="e4m3", block=32) as plan:
         with pytest.raises(mxfft.MxfftError):

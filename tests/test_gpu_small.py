@@ -158,6 +158,32 @@ def test_tuner_times_the_single_launch():
     with mxfft.Plan(64, 4) as pl:
         pl.set_tuning(t["lines"], single=t["single"])
         assert pl.tuning()["single"] == t["single"]
-    with mxfft.Plan(128, 1) as big:
+    with mxfft.Plan(256, 1) as big:
         with pytest.raises(mxfft.MxfftError):
-            big.set_tuning(0, single=True)                   # n > 64 has no single-launch kernel
+            big.set_tuning(0, single=True)                   # n > 128 has no single-launch kernel
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e2m3", 16), ("fp16", 0), ("e5m2", 64)])
+def test_single_launch_at_128(fmt, B, op):
+    """n = 128 (a tuning choice there: 132 KiB of LDS per slice) against the
+    plan's default kernels and the oracle, bit for bit."""
+    N = 128
+    x = batch_of(N, 3)
+    kw = dict(fmt=fmt) if B == 0 else dict(fmt=fmt, block=B)
+    xd = torch.from_numpy(x).cuda()
+    print("single-launch case: N=128 %s B=%d %s" % (fmt, B, op), flush=True)
+    with mxfft.Plan(N, x.shape[0], **kw) as plan:
+        assert not plan.tuning()["single"]
+        yd, kd, std = run(plan, op, xd)
+        plan.set_tuning(0, single=True)
+        assert plan.tuning()["single"]
+        ys, ks, sts = run(plan, op, xd)
+    assert std == sts == mxfft.OK
+    assert np.array_equal(bits(ys), bits(yd))
+    if ks is not None:
+        np.testing.assert_array_equal(ks, kd)
+    so, yo, ko = oracle(x, op, fmt, max(B, 2))
+    bad = bits(ys) != bits(yo)
+    bad &= ~(np.isnan(ys.view(np.float32)) & np.isnan(yo.view(np.float32)))
+    assert not bad.any(), "%d words differ from the oracle" % bad.sum()
