@@ -81,6 +81,106 @@ __device__ __forceinline__ int renorm_exp(uint32_t amax_key)
     return max(k, 0);
 }
 
+// ---------------------------------------------------------------------------
+// gfx950 element conversions (v_cvt_scalef32_pk_*): bit-identical to OCP
+// rounding (round to nearest even, subnormals, signed zero) once the values
+// are clamped to the largest element; they do not saturate by themselves
+// ---------------------------------------------------------------------------
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// 2^E as the E8M0-style scale operand, -127 <= E <= 127.
+__device__ __forceinline__ float e8(int E) { return __uint_as_float((uint32_t)(E + 127) << 23); }
+
+// Conversion hardware of element format F.  MXFP6 travels in the FP8
+// conversions: an E2M3 value times 2^-6 is an E4M3 value and an E3M2 value
+// times 2^-12 an E5M2 value (same mantissa width, subnormal spacing and
+// smallest normal), so encoding x / 2^E to FP6 is encoding x / 2^(E + OFF)
+// to FP8 and decoding multiplies by 2^(E + OFF).
+template <int F> struct Hw { static constexpr int FMT = F, OFF = 0; };
+template <> struct Hw<5> { static constexpr int FMT = 0, OFF = 6; };    // E2M3 via E4M3
+template <> struct Hw<6> { static constexpr int FMT = 1, OFF = 12; };   // E3M2 via E5M2
+
+// Mantissa field of MAXV (0x600000 for 1.75, 0x700000 for 1.875).
+template <int F>
+constexpr uint32_t maxv_frac() { return __builtin_bit_cast(uint32_t, Elem<F>::MAXV) & 0x007FFFFFu; }
+
+// MAXV * 2^E, the saturation bound at block scale 2^E.
+template <int F>
+__device__ __forceinline__ float lim_of(int E)
+{
+    constexpr uint32_t MF = maxv_frac<F>();
+    return __uint_as_float(((uint32_t)(E + Elem<F>::EMAX + 127) << 23) | MF);
+}
+
+// Block scale at exponent E for the conversions: the scale operand s, a
+// factor pre applied to the values before encoding (and to the saturation
+// bound) and post applied after decoding.  FP8: s = 2^E.  FP6: s = 2^(E+OFF),
+// unless E + OFF is above the scale range; then s = 2^E with pre = 2^-OFF and
+// post = 2^OFF (exact: such blocks hold values near 2^(127 - OFF)).
+struct Blk {
+    float s, pre, post;
+};
+template <int F>
+__device__ __forceinline__ Blk blk(int E)
+{
+    constexpr int OFF = Hw<F>::OFF;
+    if constexpr (OFF == 0) {
+        return Blk{e8(E), 1.0f, 1.0f};
+    } else {
+        const bool hi = E > 127 - OFF;
+        return Blk{e8(hi ? E : E + OFF), hi ? e8(-OFF) : 1.0f, hi ? e8(OFF) : 1.0f};
+    }
+}
+// v * f, only for the formats with a scale offset
+template <int F>
+__device__ __forceinline__ float2 mulp(float2 v, float f)
+{
+    if constexpr (Hw<F>::OFF == 0) return v;
+    else return make_float2(v.x * f, v.y * f);
+}
+template <int F>
+__device__ __forceinline__ float mulp1(float v, float f)
+{
+    if constexpr (Hw<F>::OFF == 0) return v;
+    else return v * f;
+}
+// scale operand that decodes codes to element values (2^OFF)
+template <int F>
+__device__ __forceinline__ float unit_scale() { return e8(Hw<F>::OFF); }
+
+// codes of (a, b) / 2^E in the low (W = 0) or high (W = 1) half of `old`
+template <int F, bool W>
+__device__ __forceinline__ uint32_t enc2(uint32_t old, float a, float b, float scale)
+{
+    short2v o;
+    __builtin_memcpy(&o, &old, 4);
+    short2v r;
+    if constexpr (Hw<F>::FMT == 0) r = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(o, a, b, scale, W);
+    else r = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(o, a, b, scale, W);
+    uint32_t u;
+    __builtin_memcpy(&u, &r, 4);
+    return u;
+}
+
+// element values of the two codes in half W, times 2^E
+template <int F, bool W>
+__device__ __forceinline__ float2 dec2(uint32_t codes, float scale)
+{
+    float2v d;
+    if constexpr (Hw<F>::FMT == 0) d = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(codes, scale, W);
+    else d = __builtin_amdgcn_cvt_scalef32_pk_f32_bf8(codes, scale, W);
+    return make_float2(d.x, d.y);
+}
+
+// v clamped to +-lim (the saturation of the element format at scale lim / MAXV)
+__device__ __forceinline__ float2 clamp2(float2 v, float lim)
+{
+    return make_float2(__builtin_amdgcn_fmed3f(v.x, -lim, lim), __builtin_amdgcn_fmed3f(v.y, -lim, lim));
+}
+
+
 // Element offset of slice `slice` in a pool: from the per-slice table when
 // there is one (slices anywhere in the pool), else slice * nn (contiguous).
 __device__ __forceinline__ size_t slice_base(const unsigned long long* off, int slice, size_t nn)

@@ -426,6 +426,18 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
 // One radix-2 pass over lines held in LDS
 // ---------------------------------------------------------------------------
 
+// Element values (qx, qy) of v in a block of shared exponent E (the encode of
+// EncodeBlockMX, by the scaled conversions after the saturating clamp).
+template <int F>
+__device__ __forceinline__ void mx_encode_value(float2 v, int E, float& qx, float& qy)
+{
+    const mxd::Blk b = mxd::blk<F>(E);
+    const float2 c = mxd::clamp2(mxd::mulp<F>(v, b.pre), mxd::mulp1<F>(mxd::lim_of<F>(E), b.pre));
+    const float2 q = mxd::dec2<F, false>(mxd::enc2<F, false>(0u, c.x, c.y, b.s), mxd::unit_scale<F>());
+    qx = q.x;
+    qy = q.y;
+}
+
 // tr (MX, nullable): receives the block's (E_v, k_r, E_out) of Alg. 2.
 template <int MODE>
 __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float2 u, float2 v,
@@ -450,27 +462,39 @@ __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float
         constexpr int F = MODE;
         // twiddle block: min(cb, h) consecutive j share one exponent
         const int Ew = a.tw_exp[a.tw_exp_off[s] + (a.cb <= h ? (j >> a.logcb) : 0)];
-        // operand v: EncodeBlockMX over the cb butterflies of this block (cb lanes)
+        // operand v: EncodeBlockMX over the cb butterflies of this block (cb
+        // lanes), element values from the scaled conversions (clamped first:
+        // they do not saturate)
         const uint32_t av = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
         const int Ev = mxd::block_exp<F>(av);
-        const float yr = mxd::quant<F>(ldexpf(v.x, -Ev));
-        const float yi = mxd::quant<F>(ldexpf(v.y, -Ev));
+        const mxd::Blk bv = mxd::blk<F>(Ev);
+        const float2 vc = mxd::clamp2(mxd::mulp<F>(v, bv.pre), mxd::mulp1<F>(mxd::lim_of<F>(Ev), bv.pre));
+        const float2 y = mxd::dec2<F, false>(mxd::enc2<F, false>(0u, vc.x, vc.y, bv.s), mxd::unit_scale<F>());
         // mantissa-space product: products of 8-bit elements are exact in FP32
-        const float qr = w.x * yr - w.y * yi;
-        const float qi = w.x * yi + w.y * yr;
+        const float qr = w.x * y.x - w.y * y.y;
+        const float qi = w.x * y.y + w.y * y.x;
         // renormalise the product block when it exceeds the element range
         const uint32_t ap = mxd::group_max(max(mxd::abs_key(qr), mxd::abs_key(qi)), a.cb);
         const int kr = mxd::renorm_exp<F>(ap);
-        const float cr = mxd::quant<F>(ldexpf(qr, -kr));
-        const float ci = mxd::quant<F>(ldexpf(qi, -kr));
         const int Eo = Ew + Ev + kr;
         if (tr) {
             tr[0] = Ev;
             tr[1] = kr;
             tr[2] = Eo;
         }
-        pr = ldexpf(cr, Eo);
-        pi = ldexpf(ci, Eo);
+        // the renormalised product needs no clamp; decoded with its scale
+        // 2^Eo, or (a scale outside the E8M0 range) decoded and then ldexp
+        constexpr int OFF = mxd::Hw<F>::OFF;
+        const uint32_t cp = mxd::enc2<F, false>(0u, qr, qi, mxd::e8(kr + OFF));
+        if ((OFF == 0) ? (Eo >= -127) : (Eo + OFF >= -127 && Eo + OFF <= 127)) {
+            const float2 p = mxd::dec2<F, false>(cp, mxd::e8(Eo + OFF));
+            pr = p.x;
+            pi = p.y;
+        } else {
+            const float2 q = mxd::dec2<F, false>(cp, mxd::unit_scale<F>());
+            pr = ldexpf(q.x, Eo);
+            pi = ldexpf(q.y, Eo);
+        }
     }
     y0 = make_float2(u.x + pr, u.y + pi);
     y1 = make_float2(u.x - pr, u.y - pi);
@@ -525,7 +549,8 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
                 float2 v = lds[idx];
                 const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
                 const int E = mxd::block_exp<MODE>(am);
-                const float qx = mxd::quant<MODE>(ldexpf(v.x, -E)), qy = mxd::quant<MODE>(ldexpf(v.y, -E));
+                float qx, qy;
+                mx_encode_value<MODE>(v, E, qx, qy);
                 if (a.cap_mant && a.axis == 1) {
                     // debug capture of the column pass input: line r is column
                     // line0 + r, element e its row
@@ -688,7 +713,8 @@ __device__ void small_pass(const LineArgs& a, float2* buf, bool cols, bool encod
                 float2 v = at(r, e);
                 const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
                 const int E = mxd::block_exp<MODE>(am);
-                const float qx = mxd::quant<MODE>(ldexpf(v.x, -E)), qy = mxd::quant<MODE>(ldexpf(v.y, -E));
+                float qx, qy;
+                mx_encode_value<MODE>(v, E, qx, qy);
                 if (cap_mant) {
                     // line r is column r, element e its row
                     cap_mant[((size_t)slice * N + e) * N + r] = make_float2(qx, qy);
