@@ -256,11 +256,12 @@ uint64_t mxfft_plan_device_bytes(mxfft_plan_t plan);
  * 1024, MX blocks of 2, 64 and 128, MXFP6 blocks other than 16 and 32, FP32 at
  * every n but 512) run the generic line kernels: one work-group
  * holds `lines` whole lines of a pass in LDS, one thread per butterfly.  Slices
- * of n <= 64 can instead run the whole 2D transform in one launch (one
+ * of n <= 128 can instead run the whole 2D transform in one launch (one
  * work-group per slice holding it in LDS: Alg. 1, the row and column passes,
- * both halves of a round trip), the default there.  Which is faster, and the
- * best `lines`, depend on n, the format, the batch and the GPU, so they are
- * measured. */
+ * both halves of a round trip; its work-group size follows the batch), the
+ * default for every n <= 128 without register-resident passes.  Which is
+ * faster, and the best `lines`, depend on n, the format, the batch and the
+ * GPU, so they are measured. */
 typedef struct {
     int32_t lines;   /* lines per work-group: a power of two, 1 <= lines <= n,
                         lines * n * 8 <= 65536; 0 = the default (8192 / n, at most n) */
@@ -268,9 +269,9 @@ typedef struct {
                         which have no such parameter (lines is then ignored) */
     double ms;       /* out (tuner): time of one forward call over its sample */
     int32_t single;  /* n <= 128: 1 = the single-launch kernel (the default
-                        for n <= 64; lines ignored), 0 = the line kernels with
-                        `lines` or the register-resident passes; must be 0
-                        for n > 128 */
+                        without register-resident passes; lines ignored),
+                        0 = the line kernels with `lines` or the
+                        register-resident passes; must be 0 for n > 128 */
     int32_t stats;   /* Alg. 1 with the prescale: 0 = gathered by the row pass
                         where the plan can (register-resident MX passes at
                         n = 512 and 1024), 1 = a separate statistics read of
@@ -290,8 +291,9 @@ mxfft_status mxfft_plan_get_tuning(mxfft_plan_t plan, mxfft_tuning* t);
 /* Autotuner.  Looks up (GPU architecture name, n, format, B) in the cache file
  * `cache_path` (NULL: no cache); on a miss, or with MXFFT_TUNE_FORCE, it times
  * one forward call of a plan of `sample` slices of synthetic data for every
- * candidate (the default `lines` and its halvings, at least 1; for n <= 64
- * also the single-launch kernel), keeps the fastest and records it in the
+ * candidate (the default `lines` and its halvings, at least 1, or the
+ * register-resident passes' statistics choices; for n <= 128 also the
+ * single-launch kernel), keeps the fastest and records it in the
  * cache (the file is rewritten whole through a temporary file and a rename;
  * entries of other keys are kept).  *out gets the choice; its `lines` is the
  * best line-kernel candidate even when `single` wins.  Allocates and frees

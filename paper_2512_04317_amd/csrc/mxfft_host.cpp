@@ -98,8 +98,11 @@ struct mxfft_plan_s {
     const int32_t* last_status = nullptr;
     // generic line kernels: lines per work-group (0 = line_lines_per_group)
     int lines = 0;
-    // n <= 64: the whole transform in one launch instead of the line kernels
+    // n <= 128: the whole transform in one launch instead of the line kernels
     bool single = false;
+    // the device's compute units and LDS bytes per CU (the single launch's
+    // work-group size follows them and the batch)
+    int cus = 256, lds_per_cu = 160 * 1024;
     // Alg. 1 as a separate read even where the row pass could gather it, and
     // work-groups per slice of that read (0 = by batch)
     bool literal_stats = false;
@@ -447,7 +450,7 @@ mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, vo
     g.k_in = k_in;
     g.kp = stats ? w.kp : nullptr;
     g.status = stats ? w.status : nullptr;
-    return mxk::launch_small(pl->mode, g, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
+    return mxk::launch_small(pl->mode, g, batch, pl->cus, pl->lds_per_cu, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
 // Literal Alg. 1: a statistics pass over the input, then kp per slice.
@@ -553,7 +556,15 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
         pl->cb = p->block / 2;
         pl->logcb = ilog2(pl->cb);
     }
-    if (!dry) (void)hipGetDevice(&pl->device);
+    if (!dry) {
+        (void)hipGetDevice(&pl->device);
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && v > 0)
+            pl->cus = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, pl->device) == hipSuccess &&
+            v > 0)
+            pl->lds_per_cu = v;
+    }
     hipStream_t s = (hipStream_t)stream;
 
     std::vector<float2> tw;
@@ -562,7 +573,7 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
 
     pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
     pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
-    pl->single = !pl->fast && n <= mxk::kSmallDefaultN;
+    pl->single = !pl->fast && n <= mxk::kSmallN;
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw_exp, tw_exp.size());

@@ -151,10 +151,10 @@ hipError_t launch_stats_final(const float2* x, int n, int batch, int chunks, con
 hipError_t launch_lines(int mode, const LineArgs& a, int batch, hipStream_t s);
 
 // Single-launch transform of slices of n <= kSmallN (one work-group per
-// slice: Alg. 1, all passes and the output in LDS); the default for n <= 64,
-// a tuning choice at 128.
+// slice: Alg. 1, all passes and the output in LDS); the default there
+// wherever the plan has no register-resident passes, a tuning choice where it
+// has them (128^2).
 constexpr int kSmallN = 128;
-constexpr int kSmallDefaultN = 64;
 struct SmallArgs {
     LineArgs a;                // tables, n, block, src, dst, k_out, capture pointers
     PrescaleArgs pa;
@@ -166,7 +166,10 @@ struct SmallArgs {
     int32_t* kp;               // per-slice k (stats), or nullptr
     int32_t* status;           // per-slice status (stats), or nullptr
 };
-hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s);
+// cus, lds_per_cu: the device's compute units and LDS bytes per CU (they
+// set the work-group size; see small_block)
+hipError_t launch_small(int mode, const SmallArgs& g, int batch, int cus, int lds_per_cu, hipStream_t s);
+int small_block(int n, int batch, int cus, int lds_per_cu);
 int line_lines_per_group(int n);
 // Debug capture from the register-resident MX intermediate: element values
 // [slice][row][col] and exponents [slice][col][row block] (plus kadd[slice]

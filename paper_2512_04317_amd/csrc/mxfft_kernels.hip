@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "mx_device.hpp"
 #include "mxfft_internal.hpp"
 
@@ -845,13 +847,29 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
     }
 }
 
-hipError_t launch_small(int mode, const SmallArgs& g, int batch, hipStream_t s)
+// Threads per work-group of the single-launch kernel (results do not depend
+// on it).  While the batch gives a CU at most one slice, 8 waves per slice
+// (16 where only one slice fits the CU's LDS); with more slices per CU, 16
+// waves shared among the slices a CU holds at once, so that each thread runs
+// several butterflies of a stage and a barrier spans fewer waves.  Never more
+// than one thread per butterfly, never less than one wave.
+int small_block(int n, int batch, int cus, int lds_per_cu)
+{
+    const int bf = n * n / 2;
+    const long lds = (long)n * (n + 1) * (long)sizeof(float2);
+    const int fit = std::max(1, (int)(lds_per_cu / lds));
+    const int per_cu = (batch + std::max(cus, 1) - 1) / std::max(cus, 1);
+    int waves = 16 / std::min(std::min(fit, per_cu), 16);
+    if (fit > 1) waves = std::min(waves, 8);
+    waves = std::max(1, std::min(waves, bf / 64));
+    return 64 * waves;
+}
+
+hipError_t launch_small(int mode, const SmallArgs& g, int batch, int cus, int lds_per_cu, hipStream_t s)
 {
     if (g.a.n > kSmallMaxN) return hipErrorInvalidValue;
-    // one thread per butterfly of a pass (at least one wave); the slice in LDS
-    // with a row pitch of n + 1 (132 KiB at 128^2)
-    const int bf = g.a.n * g.a.n / 2;
-    const dim3 grid(batch), block(bf < 64 ? 64 : bf > 1024 ? 1024 : bf);
+    // the slice in LDS with a row pitch of n + 1 (132 KiB at 128^2)
+    const dim3 grid(batch), block(small_block(g.a.n, batch, cus, lds_per_cu));
     const size_t lds = (size_t)g.a.n * (g.a.n + 1) * sizeof(float2);
     switch (mode) {
     case MODE_E4M3: hipLaunchKernelGGL(k_small<MODE_E4M3>, grid, block, lds, s, g); break;

@@ -339,7 +339,7 @@ class Plan:
         return {"lines": t.lines, "fast": bool(t.fast), "single": bool(t.single), "stats": t.stats, "chunks": t.chunks}
 
     def set_tuning(self, lines=0, single=False, stats=0, chunks=0):
-        """Line kernels with `lines` per work-group, or (n <= 64, single=True)
+        """Line kernels with `lines` per work-group, or (n <= 128, single=True)
         the single-launch kernel; stats=1: Alg. 1 as a separate read (with
         `chunks` work-groups per slice, 0 = by batch) where the row pass could
         gather it."""

@@ -1,8 +1,8 @@
-"""The single-launch kernel of small slices (n <= 64: Alg. 1, the row and
+"""The single-launch kernel of small slices (n <= 128: Alg. 1, the row and
 column passes and both halves of a round trip in one work-group's LDS)
 against the oracle, bit for bit, and against the line kernels of the same
 plan (same arithmetic, several launches), for every format, operation and
-flag."""
+flag, and at batches that change its work-group size."""
 import numpy as np
 import pytest
 import torch
@@ -164,17 +164,20 @@ def test_tuner_times_the_single_launch():
 
 
 @pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
-@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e2m3", 16), ("fp16", 0), ("e5m2", 64)])
+@pytest.mark.parametrize("fmt,B", [("e4m3", 32), ("e2m3", 16), ("fp16", 0), ("e5m2", 64), ("fp32", 0), ("e2m3", 8)])
 def test_single_launch_at_128(fmt, B, op):
-    """n = 128 (a tuning choice there: 132 KiB of LDS per slice) against the
-    plan's default kernels and the oracle, bit for bit."""
+    """n = 128 (132 KiB of LDS per slice; a tuning choice beside the
+    register-resident passes, the default without them) against the other
+    kernels of the plan and the oracle, bit for bit."""
     N = 128
     x = batch_of(N, 3)
     kw = dict(fmt=fmt) if B == 0 else dict(fmt=fmt, block=B)
     xd = torch.from_numpy(x).cuda()
     print("single-launch case: N=128 %s B=%d %s" % (fmt, B, op), flush=True)
     with mxfft.Plan(N, x.shape[0], **kw) as plan:
-        assert not plan.tuning()["single"]
+        # the default where the plan has no register-resident passes
+        assert plan.tuning()["single"] == (not plan.tuning()["fast"])
+        plan.set_tuning(0, single=False)
         yd, kd, std = run(plan, op, xd)
         plan.set_tuning(0, single=True)
         assert plan.tuning()["single"]
@@ -184,6 +187,42 @@ def test_single_launch_at_128(fmt, B, op):
     if ks is not None:
         np.testing.assert_array_equal(ks, kd)
     so, yo, ko = oracle(x, op, fmt, max(B, 2))
+    if fmt == "fp32":
+        fin = np.isfinite(yo)
+        err = np.linalg.norm(ys[fin] - yo[fin]) / max(np.linalg.norm(yo[fin]), 1e-30)
+        assert err <= 1e-6, err
+        return
     bad = bits(ys) != bits(yo)
     bad &= ~(np.isnan(ys.view(np.float32)) & np.isnan(yo.view(np.float32)))
     assert not bad.any(), "%d words differ from the oracle" % bad.sum()
+
+
+@pytest.mark.parametrize("N,batch,fmt,B", [(16, 4096, "e4m3", 16), (32, 4096, "e5m2", 32), (32, 1024, "fp16", 0),
+                                           (64, 1024, "e4m3", 32), (64, 2048, "e2m3", 16), (64, 4096, "fp32", 0)])
+def test_single_launch_work_group_sizes(N, batch, fmt, B):
+    """Batches that hold several slices per CU give the single launch smaller
+    work-groups (down to one wave per slice, each thread looping over several
+    butterflies of a stage): bit for bit against the line kernels on every
+    slice and against the oracle on sampled slices."""
+    x = synth.random_complex((batch, N, N), seed=N + batch, dist="lognormal")
+    x[batch // 3] *= np.float32(2.0 ** -100)
+    kw = dict(fmt=fmt) if B == 0 else dict(fmt=fmt, block=B)
+    xd = torch.from_numpy(x).cuda()
+    print("single-launch case: %d x %d^2 %s B=%d" % (batch, N, fmt, B), flush=True)
+    with mxfft.Plan(N, batch, **kw) as plan:
+        assert plan.tuning()["single"]
+        ys, ks, sts = run(plan, "roundtrip", xd)
+        plan.set_tuning(0, single=False)
+        yl, kl, stl = run(plan, "roundtrip", xd)
+    assert sts == stl == mxfft.OK
+    np.testing.assert_array_equal(ks, kl)
+    assert np.array_equal(bits(ys), bits(yl)), "single launch and line kernels differ"
+    pick = sorted({0, batch // 3, batch - 1} | set(range(7, batch, batch // 5)))
+    so, yo, ko = oracle(x[pick], "roundtrip", fmt, max(B, 2))
+    assert so == O.OK
+    np.testing.assert_array_equal(ks[pick], ko)
+    if fmt == "fp32":
+        err = np.linalg.norm(ys[pick] - yo) / np.linalg.norm(yo)
+        assert err <= 1e-6, err
+    else:
+        assert np.array_equal(bits(ys[pick]), bits(yo))
