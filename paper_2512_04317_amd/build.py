@@ -19,7 +19,7 @@ SOURCES = ["mxfft_kernels.hip", "mxfft_fast.hip", "fast_e4m3.hip", "fast_e5m2.hi
            "fast_e2m3.hip", "fast_e3m2.hip", "fast_e2m3_128.hip", "fast_e3m2_128.hip", "fast_e2m3_256.hip",
            "fast_e3m2_256.hip", "fast_e2m3_1024.hip", "fast_e3m2_1024.hip",
            "fast_fp16.hip", "fast_bf16.hip", "mxfft_host.cpp", "mxfft_tune.cpp", "mxfft_batch.cpp",
-           "mxfft_serve.cpp", "mxfft_static.hip"]
+           "mxfft_serve.cpp", "mxfft_static.hip", "fast_wide_256.hip", "fast_wide_512.hip", "fast_wide_1024.hip"]
 HEADERS = ["mx_device.hpp", "mxfft_internal.hpp", "mxfft_fast.hpp"]
 
 HIPCC_FLAGS = [

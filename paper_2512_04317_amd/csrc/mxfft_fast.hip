@@ -30,20 +30,32 @@ hipError_t launch_fast_e4m3_256(int cb, bool row, bool inverse, int kind, const 
 hipError_t launch_fast_e5m2_256(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_e4m3_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 hipError_t launch_fast_e5m2_1024(int cb, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_wide_256(int mode, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_wide_512(int mode, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
+hipError_t launch_fast_wide_1024(int mode, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch, hipStream_t s);
 
 bool fast_supported(int mode, int n, int cb)
 {
-    // MXFP6 is instantiated for blocks of 16 and 32 only
+    // MXFP6 is instantiated for blocks of 16 and 32 only; MXFP8 blocks of 64
+    // (32 complex values) at 256^2 and above
+    if (fast_wide(mode, n, cb)) return true;
     const bool mx = ((mode == MODE_E4M3 || mode == MODE_E5M2) && cb >= 2 && cb <= 16) ||
                     ((mode == MODE_E2M3 || mode == MODE_E3M2) && (cb == 8 || cb == 16));
     if (n == 512) return mx || mode == MODE_FP32 || mode == MODE_FP16 || mode == MODE_BF16;
     return (n == 128 || n == 256 || n == 1024) && (mx || mode == MODE_FP16 || mode == MODE_BF16);
 }
 
-bool fast_fused_stats(int mode, int n)
+bool fast_wide(int mode, int n, int cb)
 {
-    // the statistics histogram lives in the exchange planes of the row pass
-    return is_mx_mode(mode) && (n == 512 || n == 1024);
+    return (mode == MODE_E4M3 || mode == MODE_E5M2) && cb == 32 && (n == 256 || n == 512 || n == 1024);
+}
+
+bool fast_fused_stats(int mode, int n, int cb)
+{
+    // the statistics histogram lives in the exchange planes of the row pass;
+    // the window check of the fused statistics needs the column block
+    // exponents, which the row pass of blocks of 64 does not compute
+    return is_mx_mode(mode) && (n == 512 || n == 1024) && !fast_wide(mode, n, cb);
 }
 
 int fast_row_tiles(int n)
@@ -77,6 +89,13 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
     g.slice_off = p.slice_off;
     // the redo pass strides over its list: tiles of at most 64 slices in the grid
     if (row && kind == ROW_FIX && batch > 64) batch = 64;
+    if (fast_wide(mode, n, cb)) {
+        switch (n) {
+        case 256: return launch_fast_wide_256(mode, row, inverse, kind, g, batch, s);
+        case 512: return launch_fast_wide_512(mode, row, inverse, kind, g, batch, s);
+        default: return launch_fast_wide_1024(mode, row, inverse, kind, g, batch, s);
+        }
+    }
     switch (mode * 4096 + n) {
     case MODE_E4M3 * 4096 + 512: return launch_fast_e4m3(cb, row, inverse, kind, g, batch, s);
     case MODE_E5M2 * 4096 + 512: return launch_fast_e5m2(cb, row, inverse, kind, g, batch, s);

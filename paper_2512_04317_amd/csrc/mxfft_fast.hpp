@@ -188,19 +188,45 @@ struct ERange {
     __device__ __forceinline__ void add(int e) { lo = min(lo, e); hi = max(hi, e); }
 };
 
-// max over the groups of G consecutive lanes (G = 1, 2, 4, 8; within a DPP
-// row) of non-negative values given as bits, every lane receiving its
-// group's value: quad_perm swaps of lanes 1 and 2 apart, then the half-row
-// mirror (lane i <-> 7 - i), which after the first two steps meets the other
-// quad of the 8.  Integer max: non-negative floats order like their bits.
+// max over the groups of G consecutive lanes (G = 1 .. 32) of non-negative
+// values given as bits, every lane receiving its group's value: quad_perm
+// swaps of lanes 1 and 2 apart, then the half-row mirror (lane i <-> 7 - i),
+// which after the first two steps meets the other quad of the 8, then the row
+// mirror (lane i <-> 15 - i), which meets the other 8 of the DPP row, then a
+// lane exchange 16 apart.  Integer max: non-negative floats order like their
+// bits.
 template <int G>
 __device__ __forceinline__ uint32_t group_max_bits(uint32_t v)
 {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1..8 lanes");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group of 1..32 lanes");
     if constexpr (G >= 2) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
     if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
     if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+    if constexpr (G >= 16) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
+    if constexpr (G >= 32) v = max(v, (uint32_t)__shfl_xor((int)v, 16, 64));
     return v;
+}
+
+// MX-encode, in place, a block of V values of this lane and the same V of
+// each of the other lanes of its group of G consecutive lanes (one block
+// exponent from the block maximum over all of them).
+template <int F, int V, int G>
+__device__ __forceinline__ void mx_requant_lanes(float2 (&v)[V])
+{
+    const uint32_t a = group_max_bits<G>(__float_as_uint(amax_of<V>(v)));
+    const int E = mxd::block_exp<F>(a);
+    const Blk b = blk<F>(E);
+    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
+    if constexpr (V == 1) {
+        const float2 c = clamp2(mulp<F>(v[0], b.pre), lim);
+        v[0] = mulp<F>(dec2<F, false>(enc2<F, false>(__float_as_uint(c.x), c.x, c.y, s), s), b.post);
+    } else {
+        sfor<V / 2>([&](auto H) {
+            const uint32_t c = enc4<F>(clamp2(mulp<F>(v[2 * H], b.pre), lim), clamp2(mulp<F>(v[2 * H + 1], b.pre), lim), s);
+            v[2 * H] = mulp<F>(dec2<F, false>(c, s), b.post);
+            v[2 * H + 1] = mulp<F>(dec2<F, true>(c, s), b.post);
+        });
+    }
 }
 
 // MX-encode a block of CB consecutive values held two per lane by CB / 2
@@ -558,21 +584,40 @@ constexpr int block_offsets()
     for (int b = 0; b < C; b++) m |= 1 << Lay<LC>::index_of(K, b);
     return m;
 }
-// LC: layout family (Lay<LC>); BC: log2 of butterflies per MX block.  With
-// BC = LC + 1 the layouts after the first hold LC block bits in-lane and the
-// last block bit in lane bit 0 (position bit LC is the lowest lane bit there):
-// each lane then works on half-blocks and the two block maxima (of v and of
-// the products) are completed with one DPP exchange between lanes m, m ^ 1.
+// Block bits (of the BC bits enumerating a block's butterflies) held in-lane
+// in layout K of family LC.  The first layout holds position bits 0..4: a
+// block of 2^5 butterflies with its partner bit reaches position bit 5 there,
+// so 4 of its bits are in-lane.  The later layouts hold a block's low position
+// bits up to the first one that is a lane bit.
+template <int LC, int K, int BC>
+constexpr int block_bits_in_lane()
+{
+    if (K == 0) return BC < 4 ? BC : 4;
+    int c = 0;
+    while (c < BC && Lay<LC>::index_of(K, c) >= 0) c++;
+    return c;
+}
+
+// LC: layout family (Lay<LC>); BC: log2 of butterflies per MX block.  A block
+// whose bits are not all in-lane is split over 2 or 4 lanes: its remaining
+// position bits are the lowest lane bits (lane bits 0 and 1, so DPP quad swaps
+// reach the other lanes).  Each lane then works on its part of the block and
+// the two block maxima (of v and of the products) are completed with one or
+// two DPP exchanges (lanes m ^ 1, then m ^ 2): blocks of 16 butterflies in the
+// later layouts of family 3 (a lane pair), blocks of 32 in its first layout
+// (a lane pair) and in its later ones (four lanes, or a pair where the last
+// layout wraps position bit 3 in-lane).
 // EX (BF16): products below the FP32 normal range computed exactly.
 template <int F, int LC, int BC, int K, int B, bool INV, bool TR, bool EX = false>
 __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange& er)
 {
     using Ly = Lay<LC>;
-    // split: the block's last bit (position bit LC) is a lane bit of layout K
-    constexpr bool SPLIT = (K > 0) && (BC > LC) && (Ly::index_of(K, LC) < 0);
-    static_assert(BC <= LC + 1, "a block spans at most two lanes");
-    static_assert(!SPLIT || Ly::xbit(K, 0) == LC, "last block bit in lane bit 0");
-    constexpr int C = SPLIT ? LC : BC;                 // block bits held in-lane
+    constexpr int C = block_bits_in_lane<LC, K, BC>();   // block bits held in-lane
+    constexpr int NS = (K == 0) ? (BC > 4 ? 1 : 0) : BC - C;   // block bits held by lanes
+    static_assert(NS <= 2, "a block spans at most four lanes");
+    static_assert(NS < 1 || Ly::xbit(K, 0) == (K == 0 ? 5 : C), "next block bit in lane bit 0");
+    static_assert(NS < 2 || Ly::xbit(K, 1) == C + 1, "last block bit in lane bit 1");
+    static_assert(K > 0 || B < 5, "the first layout holds the stages of position bits 0..4");
     constexpr int ob = Ly::index_of(K, B);
     static_assert(ob >= 0, "butterfly bit must be in-lane");
     constexpr int h = 1 << B;
@@ -580,16 +625,16 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
     constexpr int fbb = (B > C) ? B : C;
     constexpr int obb = Ly::index_of(K, fbb);
     static_assert(obb >= 0, "block must be in-lane");
-    static_assert(!SPLIT || B > BC, "split blocks only in the later layouts");
     constexpr int FREE = block_offsets<LC, K, C>() | (1 << obb);   // in-lane bits of one block
     constexpr int BFLY = FREE & ~(1 << ob);            // bits enumerating its butterflies
     constexpr int OTHER = (P - 1) & ~FREE;             // bits enumerating blocks
     constexpr int NBLK = P / (2 * CB);
     const int jm = posM<LC, K>(m) & (h - 1);          // lane part of j
-    // block maximum (bits of a non-negative float): across the lane pair when split
+    // block maximum (bits of a non-negative float): across the lanes of a split block
     auto bmax = [&](float v) -> uint32_t {
         uint32_t u = __float_as_uint(v);
-        if constexpr (SPLIT) u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, true));
+        if constexpr (NS >= 1) u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, true));
+        if constexpr (NS >= 2) u = max(u, (uint32_t)__builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, true));
         return u;
     };
 
@@ -627,9 +672,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
         } else if constexpr (B <= 1) {
             // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
             // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
-            static_assert(!SPLIT, "stages 1 and 2 run in the first layout");
-            const float am = amax_of<CB>(V);
-            const int Ev = mxd::block_exp<F>(__float_as_uint(am));
+            const int Ev = mxd::block_exp<F>(bmax(amax_of<CB>(V)));
             if constexpr (TR) er.add(Ev);
             const Blk bv = blk<F>(Ev);
             const float s = bv.s, lim = mulp1<F>(lim_of<F>(Ev), bv.pre);
@@ -744,11 +787,17 @@ __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, f
     });
 }
 
-// Layout family of a pass with blocks of 2^C butterflies: blocks of 16 use
-// the layouts of blocks of 8 (two layout exchanges instead of four) with each
-// block split over a lane pair.
+// Layout family of a pass with blocks of 2^C butterflies: blocks of 16 and 32
+// use the layouts of blocks of 8 (two layout exchanges instead of four or
+// more) with each block split over a lane pair or four lanes.
 template <int F, int C>
-constexpr int layout_family() { return !is_mx(F) ? 1 : (C == 4 ? 3 : C); }
+constexpr int layout_family() { return !is_mx(F) ? 1 : (C >= 4 ? 3 : C); }
+
+// Blocks of 32 butterflies (B = 64): the row pass stores its FP32 results
+// (no column encode: a column block of 32 rows spans two row tiles) and the
+// column pass MX-encodes its input as it loads it.
+template <int F, int C>
+constexpr bool wide_blocks() { return is_mx(F) && C == 5; }
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -757,7 +806,8 @@ constexpr int layout_family() { return !is_mx(F) ? 1 : (C == 4 ? 3 : C); }
 // Shared memory of the row pass.
 template <int F, int C, int KIND>
 struct alignas(16) RowLds {
-    static constexpr int NSB = !is_mx(F) ? 1 : LINES / (1 << C);   // column blocks (of CB rows) per tile
+    // column blocks (of CB rows) per tile; none with blocks of 32 rows
+    static constexpr int NSB = (!is_mx(F) || wide_blocks<F, C>()) ? 1 : LINES / (1 << C);
     // exchange planes; before them the statistics histogram (row pass with
     // statistics only: 32 copies, bin * 32 + lane % 32, so only lanes l and
     // l + 32 can meet on an address; bin kStatsBins - 1 collects zeros and
@@ -784,6 +834,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr bool ST = (KIND == ROW_STATS);
     static_assert(!ST || is_mx(F), "statistics ride on the MX row pass only");
     static_assert(KIND != ROW_RAW || is_mx(F), "the raw row pass is an MX variant");
+    constexpr bool WIDE = wide_blocks<F, C>();
+    static_assert(!WIDE || KIND == ROW_PLAIN || KIND == ROW_RAW, "blocks of 32: no statistics in the row pass");
     float* s_plane = L.plane;
     float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -937,7 +989,9 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
 
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
-    if constexpr (F == FP32) {
+    if constexpr (F == FP32 || WIDE) {
+        // FP32 results in place of the input rows (the FP32 form; MX blocks of
+        // 32, whose column encode the column pass does)
         float2* y = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + (size_t)row * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
     } else if constexpr (is_16(F)) {
@@ -1155,27 +1209,50 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
     // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
     const uint32_t* c16 = g.codes + (size_t)slice * N * N + (size_t)cb16 * LINES * N;
 
-    if constexpr (F == FP32) {
-        static_assert(LOGN == 9, "the plain FP32 form is built for n = 512");
-        // rows are read whole (128 bytes = the work-group's 16 columns) into an
-        // LDS tile, 256 rows at a time; lanes then take rows 16k + rev4(m)
-        // (layout 0: offset rev5(k)), whose low 4 bits are the lane bits
+    if constexpr (F == FP32 || wide_blocks<F, C>()) {
+        // complex64 input (the FP32 form; MX blocks of 32, whose row pass
+        // stores FP32): rows are read whole (128 bytes = the work-group's 16
+        // columns) into an LDS tile, N/2 rows at a time; lanes then take rows
+        // (k << LOG_LPL) | rev(m) (layout 0: offset rev5(k)), whose low bits are
+        // the lane bits
+        static_assert(F != FP32 || LOGN == 9, "the plain FP32 form is built for n = 512");
+        static_assert(8 * THREADS == N / 2 * 8, "eight 16-byte pieces per thread and half");
+        constexpr int LMR = (1 << LOG_LPL) - 1;
         const float2* xs = g.src + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + cb16 * LINES;
         sfor<2>([&](auto H) {
             if constexpr (H == 1) __syncthreads();
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                const int q = i * 256 + tid, r = q >> 3, pr = q & 7;
-                const float4 v = *(const float4*)&xs[(size_t)(H * 256 + r) * N + 2 * pr];
-                *(float4*)&tile[tslot<0xF>(r, 2 * pr)] = v;
+                const int q = i * THREADS + tid, r = q >> 3, pr = q & 7;
+                const float4 v = *(const float4*)&xs[(size_t)(H * (N / 2) + r) * N + 2 * pr];
+                *(float4*)&tile[tslot<LMR>(r, 2 * pr)] = v;
             }
             __syncthreads();
             sfor<16>([&](auto Kl) {
                 constexpr int Kk = H * 16 + Kl;
-                a[rev(Kk, 5)] = tile[tslot<0xF>(16 * Kl + rm, cl)];
+                a[rev(Kk, 5)] = tile[tslot<LMR>((Kl << LOG_LPL) | rm, cl)];
             });
         });
         __syncthreads();
+        if constexpr (wide_blocks<F, C>()) {
+            // the pass input's MX encode, blocks of 32 consecutive rows: a
+            // block is V = 32 / LPL consecutive k of each of the LPL lanes of
+            // the column
+            constexpr int V = 32 / LPL;
+            static_assert(N / 2 * 16 * 2 <= WAVES * WPL, "input tile fits the planes");
+            sfor<P / V>([&](auto Q) {
+                float2 w[V];
+                sfor<V>([&](auto I) {
+                    constexpr int o = rev(Q * V + I, 5);
+                    w[I] = a[o];
+                });
+                mx_requant_lanes<F, V, LPL>(w);
+                sfor<V>([&](auto I) {
+                    constexpr int o = rev(Q * V + I, 5);
+                    a[o] = w[I];
+                });
+            });
+        }
     } else if constexpr (is_16(F)) {
         // the 512 rows of 64 bytes into LDS, the four 16-byte pieces of row n
         // rotated by XOR ((n >> 1) & 3): the 32-bit reads below (16 rows x 4

@@ -315,7 +315,7 @@ WsCounts ws_counts(const mxfft_plan_s* pl, int batch)
     if (pl->fused) c.parts = std::max(c.parts, b * mxk::fast_row_tiles(pl->n));
     c.kp = b;
     c.status = b;
-    if (pl->fast && mxk::is_mx_mode(pl->mode)) {
+    if (pl->fast && mxk::is_mx_mode(pl->mode) && !mxk::fast_wide(pl->mode, pl->n, pl->cb)) {
         // MX intermediate: codes (2 bytes per complex value) and block exponents
         c.codes = b * n * n / 2;
         c.exps = b * n * (n / (size_t)pl->cb);
@@ -350,7 +350,8 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     LaunchTimer timer(pl, role, s);
     if (pl->fast) {
         // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
-        if (mxk::is_mx_mode(pl->mode) && (!w.codes || !w.exps)) return MXFFT_EHIP;
+        if (mxk::is_mx_mode(pl->mode) && !mxk::fast_wide(pl->mode, pl->n, pl->cb) && (!w.codes || !w.exps))
+            return MXFFT_EHIP;
         mxk::FastPassArgs f{};
         f.src = (const float2*)src;
         f.dst = (float2*)dst;
@@ -571,8 +572,12 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     std::vector<int32_t> tw_exp;
     build_twiddles(pl, tw, tw_exp, pl->tw_exp_off);
 
-    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
-    pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
+    // debug capture of the column pass input needs the MX intermediate: blocks
+    // of 64 (whose register-resident column pass encodes on load) keep the
+    // line kernels then
+    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb) &&
+               !((p->flags & MXFFT_DEBUG_CAPTURE) && mxk::fast_wide(pl->mode, n, pl->cb));
+    pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n, pl->cb);
     pl->single = !pl->fast && n <= mxk::kSmallN;
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
@@ -836,7 +841,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     if ((long)recon * coils > pl->max_batch) return MXFFT_EINVAL;
     // the FP32 form keeps its intermediate in complex64 (the row pass writes
     // it where the column pass reads it): `work` is that buffer
-    const bool plain = pl->mode == mxk::MODE_FP32;
+    const bool plain = pl->mode == mxk::MODE_FP32 || (pl->fast && mxk::fast_wide(pl->mode, pl->n, pl->cb));
     if ((op == 2 || plain || !pl->fast) && !work) return MXFFT_EINVAL;
     if (recon == 0) return MXFFT_OK;
     const mxk::Workspace& w = pl->ws;
