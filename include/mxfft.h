@@ -80,9 +80,7 @@ typedef enum {
  * EncodeBlockMX, element values and shared exponents), which
  * mxfft_plan_capture() returns.  The plan holds 8 + 8/B bytes more per
  * complex value of max_batch slices, and each forward call of up to
- * max_batch slices writes them.  MXFP8 blocks of 64 (whose register-resident
- * column pass encodes its input as it loads it) then run on the line
- * kernels, with the same results. */
+ * max_batch slices writes them. */
 #define MXFFT_DEBUG_CAPTURE 0x10u
 
 typedef struct {
@@ -182,11 +180,10 @@ mxfft_status mxfft_roundtrip(mxfft_plan_t plan, const void* in, void* out, int32
  * rounded square root.  The combine is fused into the last column pass:
  * the per-coil complex results are never written, only the images (1/(2 C)
  * of the plain call's output bytes).  work: complex64 [recon * coils][n][n]
- * scratch for the round trip's forward result, for the complex64
- * intermediate of the FP32 form and of MXFP8 B = 64, and for the per-coil
- * results of plans without the fused epilogue (may be `in`, which is then
- * overwritten); MXFFT_EINVAL when it is needed and NULL; unused (may be NULL)
- * otherwise.  k_out: int32[recon * coils] or NULL.  recon * coils <=
+ * scratch for the round trip's forward result, for the FP32 form's complex64
+ * intermediate, and for the per-coil results of plans without the fused
+ * epilogue (may be `in`, which is then overwritten); MXFFT_EINVAL when it is
+ * needed and NULL; unused (may be NULL) otherwise.  k_out: int32[recon * coils] or NULL.  recon * coils <=
  * max_batch.  Plans on the register-resident passes (n = 128..1024 with MXFP8
  * B = 4..32, MXFP8 B = 64 at n = 256..1024, MXFP6 B = 16 or 32, or FP16/BF16,
  * and FP32 at n = 512) fuse the combine; the others (generic line kernels,

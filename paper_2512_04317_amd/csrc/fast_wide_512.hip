@@ -1,6 +1,6 @@
 // fast_wide_512.hip -- instantiations of the register-resident 512^2 passes for MX blocks of
-// 64 values (32 butterflies) in E4M3 and E5M2: the row pass stores FP32, the column pass encodes
-// its input as it loads it.
+// 64 values (32 butterflies) in E4M3 and E5M2: row tiles of 32 lines, so that a column block's 32
+// rows are encoded inside one work-group.
 #define MXF_LOGN 9
 #define MXF_NS mxf
 #include "mxfft_fast.hpp"
@@ -10,13 +10,16 @@ namespace mxk {
 hipError_t launch_fast_wide_512(int mode, bool row, bool inverse, int kind, const mxf::FastArgs& g, int batch,
                                hipStream_t s)
 {
-    const dim3 grid((mxf::N / mxf::LINES) * batch), block(mxf::THREADS);
-#define MXF_CASE(FF, INV)                                                                                 \
-    if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf::k_col_rss<FF, 5, INV>), grid, block, 0, s, g); \
-    else if (!row) hipLaunchKernelGGL((mxf::k_col<FF, 5, INV>), grid, block, 0, s, g);                  \
-    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf::k_row<FF, 5, INV, ROW_RAW>), grid, block, 0, s, g); \
-    else if (kind != ROW_PLAIN) return hipErrorInvalidValue;                                           \
-    else hipLaunchKernelGGL((mxf::k_row<FF, 5, INV, ROW_PLAIN>), grid, block, 0, s, g);
+    // row tiles of 32 lines (twice the threads of a 16-line tile); column groups of 16
+    const dim3 rgrid((mxf::N / mxf::row_lines<0, 5>()) * batch), rblock(mxf::row_threads<0, 5>());
+    const dim3 cgrid((mxf::N / mxf::LINES) * batch), cblock(mxf::THREADS);
+#define MXF_CASE(FF, INV)                                                                                    \
+    if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf::k_col_rss<FF, 5, INV>), cgrid, cblock, 0, s, g);     \
+    else if (!row) hipLaunchKernelGGL((mxf::k_col<FF, 5, INV>), cgrid, cblock, 0, s, g);                      \
+    else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf::k_row<FF, 5, INV, ROW_RAW>), rgrid, rblock, 0, s, g);     \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf::k_row<FF, 5, INV, ROW_STATS>), rgrid, rblock, 0, s, g); \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf::k_row_fix<FF, 5, INV>), rgrid, rblock, 0, s, g);         \
+    else hipLaunchKernelGGL((mxf::k_row<FF, 5, INV, ROW_PLAIN>), rgrid, rblock, 0, s, g);
     switch ((mode == MODE_E5M2 ? 2 : mode == MODE_E4M3 ? 0 : 4) + (inverse ? 1 : 0)) {
     case 0: MXF_CASE(0, false) break;
     case 1: MXF_CASE(0, true) break;

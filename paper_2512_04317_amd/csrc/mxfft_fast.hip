@@ -50,17 +50,16 @@ bool fast_wide(int mode, int n, int cb)
     return (mode == MODE_E4M3 || mode == MODE_E5M2) && cb == 32 && (n == 256 || n == 512 || n == 1024);
 }
 
-bool fast_fused_stats(int mode, int n, int cb)
+bool fast_fused_stats(int mode, int n)
 {
-    // the statistics histogram lives in the exchange planes of the row pass;
-    // the window check of the fused statistics needs the column block
-    // exponents, which the row pass of blocks of 64 does not compute
-    return is_mx_mode(mode) && (n == 512 || n == 1024) && !fast_wide(mode, n, cb);
+    // the statistics histogram lives in the exchange planes of the row pass
+    return is_mx_mode(mode) && (n == 512 || n == 1024);
 }
 
-int fast_row_tiles(int n)
+int fast_row_tiles(int mode, int n, int cb)
 {
-    return n / 16;   // 16 lines per work-group at every size
+    // 16 lines per work-group at every size; 32 for MXFP8 blocks of 64
+    return fast_wide(mode, n, cb) ? n / 32 : n / 16;
 }
 
 hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind, const FastPassArgs& p,

@@ -188,45 +188,21 @@ struct ERange {
     __device__ __forceinline__ void add(int e) { lo = min(lo, e); hi = max(hi, e); }
 };
 
-// max over the groups of G consecutive lanes (G = 1 .. 32) of non-negative
-// values given as bits, every lane receiving its group's value: quad_perm
-// swaps of lanes 1 and 2 apart, then the half-row mirror (lane i <-> 7 - i),
-// which after the first two steps meets the other quad of the 8, then the row
-// mirror (lane i <-> 15 - i), which meets the other 8 of the DPP row, then a
-// lane exchange 16 apart.  Integer max: non-negative floats order like their
-// bits.
+// max over the groups of G consecutive lanes (G = 1 .. 16, within a DPP row)
+// of non-negative values given as bits, every lane receiving its group's
+// value: quad_perm swaps of lanes 1 and 2 apart, then the half-row mirror
+// (lane i <-> 7 - i), which after the first two steps meets the other quad of
+// the 8, then the row mirror (lane i <-> 15 - i), which meets the other 8.
+// Integer max: non-negative floats order like their bits.
 template <int G>
 __device__ __forceinline__ uint32_t group_max_bits(uint32_t v)
 {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group of 1..32 lanes");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
     if constexpr (G >= 2) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
     if constexpr (G >= 4) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
     if constexpr (G >= 8) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
     if constexpr (G >= 16) v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
-    if constexpr (G >= 32) v = max(v, (uint32_t)__shfl_xor((int)v, 16, 64));
     return v;
-}
-
-// MX-encode, in place, a block of V values of this lane and the same V of
-// each of the other lanes of its group of G consecutive lanes (one block
-// exponent from the block maximum over all of them).
-template <int F, int V, int G>
-__device__ __forceinline__ void mx_requant_lanes(float2 (&v)[V])
-{
-    const uint32_t a = group_max_bits<G>(__float_as_uint(amax_of<V>(v)));
-    const int E = mxd::block_exp<F>(a);
-    const Blk b = blk<F>(E);
-    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
-    if constexpr (V == 1) {
-        const float2 c = clamp2(mulp<F>(v[0], b.pre), lim);
-        v[0] = mulp<F>(dec2<F, false>(enc2<F, false>(__float_as_uint(c.x), c.x, c.y, s), s), b.post);
-    } else {
-        sfor<V / 2>([&](auto H) {
-            const uint32_t c = enc4<F>(clamp2(mulp<F>(v[2 * H], b.pre), lim), clamp2(mulp<F>(v[2 * H + 1], b.pre), lim), s);
-            v[2 * H] = mulp<F>(dec2<F, false>(c, s), b.post);
-            v[2 * H + 1] = mulp<F>(dec2<F, true>(c, s), b.post);
-        });
-    }
 }
 
 // MX-encode a block of CB consecutive values held two per lane by CB / 2
@@ -793,11 +769,15 @@ __device__ __forceinline__ void all_stages(float2 (&a)[P], int m, const Tw& t, f
 template <int F, int C>
 constexpr int layout_family() { return !is_mx(F) ? 1 : (C >= 4 ? 3 : C); }
 
-// Blocks of 32 butterflies (B = 64): the row pass stores its FP32 results
-// (no column encode: a column block of 32 rows spans two row tiles) and the
-// column pass MX-encodes its input as it loads it.
+// Blocks of 32 butterflies (B = 64): a column block holds 32 rows, so the
+// row pass takes tiles of 32 lines (twice the waves and LDS of a work-group)
+// to encode the column pass's input inside one work-group.
 template <int F, int C>
 constexpr bool wide_blocks() { return is_mx(F) && C == 5; }
+template <int F, int C>
+constexpr int row_lines() { return wide_blocks<F, C>() ? 2 * LINES : LINES; }
+template <int F, int C>
+constexpr int row_threads() { return 64 * (row_lines<F, C>() / LPW); }
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -806,17 +786,18 @@ constexpr bool wide_blocks() { return is_mx(F) && C == 5; }
 // Shared memory of the row pass.
 template <int F, int C, int KIND>
 struct alignas(16) RowLds {
-    // column blocks (of CB rows) per tile; none with blocks of 32 rows
-    static constexpr int NSB = (!is_mx(F) || wide_blocks<F, C>()) ? 1 : LINES / (1 << C);
+    static constexpr int RL = row_lines<F, C>();      // lines of a row tile
+    static constexpr int RW = RL / LPW;                // waves of its work-group
+    static constexpr int NSB = !is_mx(F) ? 1 : RL / (1 << C);   // column blocks (of CB rows) per tile
     // exchange planes; before them the statistics histogram (row pass with
     // statistics only: 32 copies, bin * 32 + lane % 32, so only lanes l and
     // l + 32 can meet on an address; bin kStatsBins - 1 collects zeros and
     // non-finite values); after them the column maxima
-    float plane[WAVES * WPL];
+    float plane[RW * WPL];
     float sc[NSB * N];                 // column block scales 2^E (MX)
-    double m2[WAVES];
-    uint32_t mc[WAVES];
-    int nf[WAVES], elo[WAVES], ehi[WAVES];
+    double m2[RW];
+    uint32_t mc[RW];
+    int nf[RW], elo[RW], ehi[RW];
 };
 
 // One 16-row tile of the row pass. F: 0 E4M3, 1 E5M2, 2 FP16, 3 BF16, 4 FP32.
@@ -834,14 +815,13 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr bool ST = (KIND == ROW_STATS);
     static_assert(!ST || is_mx(F), "statistics ride on the MX row pass only");
     static_assert(KIND != ROW_RAW || is_mx(F), "the raw row pass is an MX variant");
-    constexpr bool WIDE = wide_blocks<F, C>();
-    static_assert(!WIDE || KIND == ROW_PLAIN || KIND == ROW_RAW, "blocks of 32: no statistics in the row pass");
+    constexpr int RL = RowLds<F, C, KIND>::RL, RW = RowLds<F, C, KIND>::RW, RT = 64 * RW;
     float* s_plane = L.plane;
     float* s_sc = L.sc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int line = lane >> LOG_LPL, m = lane & (LPL - 1);
     const int rl = wave * LPW + line;                     // row within the tile
-    const int row = rb * LINES + rl;
+    const int row = rb * RL + rl;
     const int kp = slice_k(g, slice);
     const int kin = ST ? 0 : g.kin_mul * kp;
     if (KIND == ROW_PLAIN && g.k_out && rb == 0 && tid == 0) g.k_out[slice] = g.kp ? g.kp[slice] : 0;
@@ -899,8 +879,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // the squares is finite iff every part is), and the binade histogram
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
-            static_assert(kStatsBins * 32 <= WAVES * WPL, "histogram fits the planes");
-            for (int i = tid; i < kStatsBins * 32 / 4; i += THREADS) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
+            static_assert(kStatsBins * 32 <= RW * WPL, "histogram fits the planes");
+            for (int i = tid; i < kStatsBins * 32 / 4; i += RT) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
             double m2max = 0.0, m2sum = 0.0;
@@ -948,8 +928,8 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // sum the 32 copies of bin i, copy order skewed by i so a wave's
             // reads fall in 32 different banks
             __syncthreads();
-            StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
-            for (int i = tid; i < kStatsBins; i += THREADS) {
+            StatPart* pt = g.parts + (size_t)slice * (N / RL) + rb;
+            for (int i = tid; i < kStatsBins; i += RT) {
                 uint32_t h = 0;
 #pragma unroll 8
                 for (int c = 0; c < 32; c++) h += hist[i * 32 + ((c + i) & 31)];
@@ -989,9 +969,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
 
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
-    if constexpr (F == FP32 || WIDE) {
-        // FP32 results in place of the input rows (the FP32 form; MX blocks of
-        // 32, whose column encode the column pass does)
+    if constexpr (F == FP32) {
         float2* y = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + (size_t)row * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
     } else if constexpr (is_16(F)) {
@@ -1013,7 +991,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         //    VW consecutive columns per lane are in-lane offset bits 0..log2(VW)-1
         constexpr int VW = (CL >= 2) ? 4 : 2;
         float* s_m = s_plane;
-        static_assert(LINES * N <= WAVES * WPL, "column maxima fit the planes");
+        static_assert(RL * N <= RW * WPL, "column maxima fit the planes");
         __syncthreads();                                   // every wave is done with its planes
         sfor<P / VW>([&](auto G) {
             constexpr int o0 = deposit(G, (P - 1) & ~(VW - 1));
@@ -1026,8 +1004,10 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         });
         __syncthreads();
         // 2. one thread per column pair: block exponents -> E8M0 bytes (global,
-        //    [slice][row block][column]) and scales 2^E (LDS)
-        {
+        //    [slice][row block][column]) and scales 2^E (LDS); tiles of 32
+        //    lines have twice the threads
+        static_assert(RT >= N / 2, "a thread per column pair");
+        if (2 * tid < N) {
             const int c2 = 2 * tid;
             uint8_t* ex = g.exps + (size_t)slice * (N / CB) * N + (size_t)rb * NSB * N;
             sfor<NSB>([&](auto B) {
@@ -1115,13 +1095,13 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             const int lo = wave_reduce_min(er.lo), hi = wave_reduce_max(er.hi);
             if (lane == 0) { L.elo[wave] = lo; L.ehi[wave] = hi; }
             __syncthreads();
-            StatPart* pt = g.parts + (size_t)slice * (N / LINES) + rb;
+            StatPart* pt = g.parts + (size_t)slice * (N / RL) + rb;
             if (tid == 0) {
                 double m2 = L.m2[0];
                 uint32_t mcw = L.mc[0];
                 int nf = L.nf[0], elo = L.elo[0], ehi = L.ehi[0];
 #pragma unroll
-                for (int w = 1; w < WAVES; w++) {
+                for (int w = 1; w < RW; w++) {
                     m2 = fmax(m2, L.m2[w]);
                     mcw = max(mcw, L.mc[w]);
                     nf |= L.nf[w];
@@ -1142,21 +1122,22 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
 // Row pass over every tile of the batch (ROW_PLAIN, ROW_STATS).  Above 128
 // VGPRs at 1024^2: the statistics form of blocks of 16 and 32, and BF16.
 template <int F, int C, bool INV, int KIND>
-__global__ __launch_bounds__(THREADS)
+__global__ __launch_bounds__((row_threads<F, C>()))
 __attribute__((amdgpu_waves_per_eu(waves_target((KIND == ROW_STATS && C >= 3) || F == BF16), 8))) void k_row(FastArgs g)
 {
     __shared__ RowLds<F, C, KIND> L;
-    row_tile<F, C, INV, KIND>(g, blockIdx.x / (N / LINES), blockIdx.x % (N / LINES), L);
+    constexpr int TILES = N / row_lines<F, C>();
+    row_tile<F, C, INV, KIND>(g, blockIdx.x / TILES, blockIdx.x % TILES, L);
 }
 
 // Row pass over the slices in fix_list only: the work-groups stride over the
 // (list entry, tile) pairs, so a grid of a few slices' tiles serves any list
 // length and an empty list costs one read per work-group.
 template <int F, int C, bool INV>
-__global__ __launch_bounds__(THREADS) void k_row_fix(FastArgs g)
+__global__ __launch_bounds__((row_threads<F, C>())) void k_row_fix(FastArgs g)
 {
     __shared__ RowLds<F, C, ROW_FIX> L;
-    constexpr int TILES = N / LINES;
+    constexpr int TILES = N / row_lines<F, C>();
     const int total = *g.fix_count * TILES;            // the same for every thread
     for (int e = blockIdx.x; e < total; e += gridDim.x) {
         if (e != (int)blockIdx.x) __syncthreads();     // the previous tile is done with the LDS
@@ -1209,13 +1190,11 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
     // 16-bit forms: this work-group's part of the intermediate, [row][16 words]
     const uint32_t* c16 = g.codes + (size_t)slice * N * N + (size_t)cb16 * LINES * N;
 
-    if constexpr (F == FP32 || wide_blocks<F, C>()) {
-        // complex64 input (the FP32 form; MX blocks of 32, whose row pass
-        // stores FP32): rows are read whole (128 bytes = the work-group's 16
-        // columns) into an LDS tile, N/2 rows at a time; lanes then take rows
-        // (k << LOG_LPL) | rev(m) (layout 0: offset rev5(k)), whose low bits are
-        // the lane bits
-        static_assert(F != FP32 || LOGN == 9, "the plain FP32 form is built for n = 512");
+    if constexpr (F == FP32) {
+        // rows are read whole (128 bytes = the work-group's 16 columns) into an
+        // LDS tile, N/2 rows at a time; lanes then take rows (k << LOG_LPL) |
+        // rev(m) (layout 0: offset rev5(k)), whose low bits are the lane bits
+        static_assert(LOGN == 9, "the plain FP32 form is built for n = 512");
         static_assert(8 * THREADS == N / 2 * 8, "eight 16-byte pieces per thread and half");
         constexpr int LMR = (1 << LOG_LPL) - 1;
         const float2* xs = g.src + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + cb16 * LINES;
@@ -1234,25 +1213,6 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
             });
         });
         __syncthreads();
-        if constexpr (wide_blocks<F, C>()) {
-            // the pass input's MX encode, blocks of 32 consecutive rows: a
-            // block is V = 32 / LPL consecutive k of each of the LPL lanes of
-            // the column
-            constexpr int V = 32 / LPL;
-            static_assert(N / 2 * 16 * 2 <= WAVES * WPL, "input tile fits the planes");
-            sfor<P / V>([&](auto Q) {
-                float2 w[V];
-                sfor<V>([&](auto I) {
-                    constexpr int o = rev(Q * V + I, 5);
-                    w[I] = a[o];
-                });
-                mx_requant_lanes<F, V, LPL>(w);
-                sfor<V>([&](auto I) {
-                    constexpr int o = rev(Q * V + I, 5);
-                    a[o] = w[I];
-                });
-            });
-        }
     } else if constexpr (is_16(F)) {
         // the 512 rows of 64 bytes into LDS, the four 16-byte pieces of row n
         // rotated by XOR ((n >> 1) & 3): the 32-bit reads below (16 rows x 4

@@ -312,10 +312,10 @@ WsCounts ws_counts(const mxfft_plan_s* pl, int batch)
     WsCounts c{};
     // chunk statistics: the literal statistics pass, or one part per row tile
     c.parts = mxk::stats_parts(pl->n, batch);
-    if (pl->fused) c.parts = std::max(c.parts, b * mxk::fast_row_tiles(pl->n));
+    if (pl->fused) c.parts = std::max(c.parts, b * mxk::fast_row_tiles(pl->mode, pl->n, pl->cb));
     c.kp = b;
     c.status = b;
-    if (pl->fast && mxk::is_mx_mode(pl->mode) && !mxk::fast_wide(pl->mode, pl->n, pl->cb)) {
+    if (pl->fast && mxk::is_mx_mode(pl->mode)) {
         // MX intermediate: codes (2 bytes per complex value) and block exponents
         c.codes = b * n * n / 2;
         c.exps = b * n * (n / (size_t)pl->cb);
@@ -350,8 +350,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     LaunchTimer timer(pl, role, s);
     if (pl->fast) {
         // rows: complex64 src -> MX intermediate (or FP32 dst); columns: intermediate -> dst
-        if (mxk::is_mx_mode(pl->mode) && !mxk::fast_wide(pl->mode, pl->n, pl->cb) && (!w.codes || !w.exps))
-            return MXFFT_EHIP;
+        if (mxk::is_mx_mode(pl->mode) && (!w.codes || !w.exps)) return MXFFT_EHIP;
         mxk::FastPassArgs f{};
         f.src = (const float2*)src;
         f.dst = (float2*)dst;
@@ -484,8 +483,9 @@ mxfft_status row_with_stats(mxfft_plan_s* pl, const mxk::Workspace& w, const voi
     {
         const mxk::PrescaleArgs pa = prescale_args(pl);
         LaunchTimer timer(pl, ROLE_STATS, s);
-        if (mxk::launch_stats_final((const float2*)in, pl->n, batch, mxk::fast_row_tiles(pl->n), w.parts, w.kp,
-                                    w.status, pa, w.kadd, w.fix_list, w.fix_count, k_out, w.slice_off, s) != hipSuccess)
+        const int tiles = mxk::fast_row_tiles(pl->mode, pl->n, pl->cb);
+        if (mxk::launch_stats_final((const float2*)in, pl->n, batch, tiles, w.parts, w.kp, w.status, pa, w.kadd,
+                                    w.fix_list, w.fix_count, k_out, w.slice_off, s) != hipSuccess)
             return MXFFT_EHIP;
     }
     return pass(pl, w, in, nullptr, w.kp, nullptr, 1, 0, 0, 0, inverse, batch, s, mxk::ROW_FIX);
@@ -572,12 +572,8 @@ mxfft_status plan_create(mxfft_plan_t* out, int32_t n, int32_t max_batch, const 
     std::vector<int32_t> tw_exp;
     build_twiddles(pl, tw, tw_exp, pl->tw_exp_off);
 
-    // debug capture of the column pass input needs the MX intermediate: blocks
-    // of 64 (whose register-resident column pass encodes on load) keep the
-    // line kernels then
-    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb) &&
-               !((p->flags & MXFFT_DEBUG_CAPTURE) && mxk::fast_wide(pl->mode, n, pl->cb));
-    pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n, pl->cb);
+    pl->fast = mxk::fast_supported(pl->mode, n, pl->cb);
+    pl->fused = pl->fast && mxk::fast_fused_stats(pl->mode, n);
     pl->single = !pl->fast && n <= mxk::kSmallN;
     mxfft_status st = MXFFT_OK;
     if (st == MXFFT_OK) st = dev_alloc(pl, &pl->d_tw, tw.size());
@@ -841,7 +837,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
     if ((long)recon * coils > pl->max_batch) return MXFFT_EINVAL;
     // the FP32 form keeps its intermediate in complex64 (the row pass writes
     // it where the column pass reads it): `work` is that buffer
-    const bool plain = pl->mode == mxk::MODE_FP32 || (pl->fast && mxk::fast_wide(pl->mode, pl->n, pl->cb));
+    const bool plain = pl->mode == mxk::MODE_FP32;
     if ((op == 2 || plain || !pl->fast) && !work) return MXFFT_EINVAL;
     if (recon == 0) return MXFFT_OK;
     const mxk::Workspace& w = pl->ws;

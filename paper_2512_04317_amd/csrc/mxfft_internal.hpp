@@ -128,17 +128,16 @@ struct FastPassArgs {
 enum RowKind { ROW_PLAIN = 0, ROW_STATS = 1, ROW_FIX = 2, COL_RSS = 3, ROW_RAW = 4 };
 
 bool fast_supported(int mode, int n, int cb);
-// MXFP8 blocks of 64 values (cb = 32) on the register-resident passes: the
-// row pass writes FP32 results to the output (the intermediate), as the FP32
-// form does, and the column pass encodes its input as it loads it
+// MXFP8 blocks of 64 values (cb = 32) on the register-resident passes: row
+// tiles of 32 lines, so that a column block's 32 rows share a work-group
 bool fast_wide(int mode, int n, int cb);
 // whether the row pass can gather the Alg. 1 statistics (register-resident MX passes)
-bool fast_fused_stats(int mode, int n, int cb);
+bool fast_fused_stats(int mode, int n);
 // row: kind is one of RowKind; columns ignore it
 hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind, const FastPassArgs& p,
                        int batch, hipStream_t s);
 // Tiles (row chunks) per slice of the row pass with statistics.
-int fast_row_tiles(int n);
+int fast_row_tiles(int mode, int n, int cb);
 
 // chunks: work-groups per slice (a power of two dividing n * n), 0 = by batch
 hipError_t launch_stats(const float2* x, int n, int batch, StatPart* parts, int32_t* kp,

@@ -276,12 +276,7 @@ class Plan:
             out = torch.empty((recon, self.n, self.n), dtype=torch.float32, device=x.device)
         if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.shape == (recon, self.n, self.n)):
             raise ValueError("out must be a contiguous float32 CUDA tensor [recon, n, n]")
-        # the scratch buffer: the round trip's forward result, the complex64
-        # intermediate (FP32 form, MXFP8 blocks of 64), or the per-coil results
-        # of plans without the fused combine
-        fast = self.tuning()["fast"]
-        wide = fast and self.params.format in (E4M3, E5M2) and self.params.block == 64
-        if work is None and (op == ROUNDTRIP or self.params.format == FP32 or wide or not fast):
+        if work is None and (op == ROUNDTRIP or self.params.format == FP32 or not self.tuning()["fast"]):
             work = torch.empty_like(x)
         k_out = self._kbuf(x.shape[0], k_out, x.device)
         st = lib().mxfft_rss(self.handle, int(op), _ptr(x), _ptr(work), _ptr(out), recon, int(coils), _ptr(k_out),
