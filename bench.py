@@ -32,11 +32,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 ALG_BYTES_PER_ELEM = 16.0      # complex64 read once + complex64 written once per transform
 # VALU issue rate: 256 compute units x 64 lanes, one lane operation per lane
 # and cycle (non-packed FP32 and integer VALU), at the published 2.4 GHz peak
-# clock and at the clock the counters measure under this load
-# (GRBM_GUI_ACTIVE over the kernel time: about 2.1 GHz,
-# profiles/pmc_kspace512x1024_e4m3_b32.md)
+# clock, and at the clock the counters measured for the kernel under this
+# load (GRBM_GUI_ACTIVE over its duration, recorded beside the HBM traffic in
+# profiles/traffic_<workload>_<format>.json; 2.1 to 2.36 GHz on different
+# boxes)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-MEASURED_CLOCK_GHZ = 2.1
 # algorithmic operations per radix-2 butterfly of the MX path: one complex
 # product and two complex sums (10 flops) plus the four quantise/dequantise
 # operations of Alg. 2 (encode v, encode the product, decode both)
@@ -513,15 +513,16 @@ def main():
     alg_bytes = {"row_pass": 8.0 * elems, "column_pass": 8.0 * elems, "prescale_stats": 0.0}
     n_dom, t_dom = ktimes[dom]
     avg_s = t_dom / n_dom * 1e-3
-    traffic = None
+    traffic, clock_ghz = None, None
     tfile = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (args.workload, args.fmt))
     if os.path.exists(tfile):
         t = json.load(open(tfile))
         if t.get("source_sha") == kernel_source_sha() and dom in t.get("kernels", {}):
             traffic = t["kernels"][dom]["hbm_bytes_per_launch"]
+            clock_ghz = t["kernels"][dom].get("clock_GHz")
     achieved_ops = alg_ops.get(dom, 0.0) / avg_s / 1e12
     achieved_gbs = alg_bytes.get(dom, 0.0) / avg_s / 1e9
-    clock_peak = 256 * 64 * MEASURED_CLOCK_GHZ * 1e9 / 1e12
+    clock_peak = 256 * 64 * clock_ghz * 1e9 / 1e12 if clock_ghz else None
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_avg_ms": round(avg_s * 1e3, 4), "launches_timed": n_dom,
@@ -530,8 +531,9 @@ def main():
                 "valu": {"achieved": round(achieved_ops, 3), "unit": "Tops/s",
                          "alg_ops_per_launch": alg_ops.get(dom, 0.0),
                          "peak_2.4GHz": round(ALU_PEAK_TOPS, 3), "frac_2.4GHz": round(achieved_ops / ALU_PEAK_TOPS, 4),
-                         "clock_GHz_measured": MEASURED_CLOCK_GHZ, "peak_measured_clock": round(clock_peak, 3),
-                         "frac_measured_clock": round(achieved_ops / clock_peak, 4)}}
+                         "clock_GHz_measured": clock_ghz,
+                         "peak_measured_clock": round(clock_peak, 3) if clock_peak else None,
+                         "frac_measured_clock": round(achieved_ops / clock_peak, 4) if clock_peak else None}}
     kern = {k: {"launches": n, "avg_ms": t / n} for k, (n, t) in pre.items()}
     step_frac = slices_per_s * N * N * ALG_BYTES_PER_ELEM / (HBM_PEAK_GBS * 1e9)
 
