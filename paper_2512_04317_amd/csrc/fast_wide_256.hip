@@ -17,7 +17,8 @@ hipError_t launch_fast_wide_256(int mode, bool row, bool inverse, int kind, cons
     if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf256::k_col_rss<FF, 5, INV>), cgrid, cblock, 0, s, g);     \
     else if (!row) hipLaunchKernelGGL((mxf256::k_col<FF, 5, INV>), cgrid, cblock, 0, s, g);                      \
     else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf256::k_row<FF, 5, INV, ROW_RAW>), rgrid, rblock, 0, s, g);     \
-    else if (kind != ROW_PLAIN) return hipErrorInvalidValue;                                                   \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf256::k_row<FF, 5, INV, ROW_STATS>), rgrid, rblock, 0, s, g); \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf256::k_row_fix<FF, 5, INV>), rgrid, rblock, 0, s, g);         \
     else hipLaunchKernelGGL((mxf256::k_row<FF, 5, INV, ROW_PLAIN>), rgrid, rblock, 0, s, g);
     switch ((mode == MODE_E5M2 ? 2 : mode == MODE_E4M3 ? 0 : 4) + (inverse ? 1 : 0)) {
     case 0: MXF_CASE(0, false) break;

@@ -789,9 +789,12 @@ struct alignas(16) RowLds {
     static constexpr int RL = row_lines<F, C>();      // lines of a row tile
     static constexpr int RW = RL / LPW;                // waves of its work-group
     static constexpr int NSB = !is_mx(F) ? 1 : RL / (1 << C);   // column blocks (of CB rows) per tile
+    // copies of the statistics histogram: as many as the planes hold, up to 32
+    static constexpr int HC_FIT = RW * WPL / kStatsBins;
+    static constexpr int HC = HC_FIT >= 32 ? 32 : HC_FIT >= 16 ? 16 : HC_FIT >= 8 ? 8 : 4;
     // exchange planes; before them the statistics histogram (row pass with
-    // statistics only: 32 copies, bin * 32 + lane % 32, so only lanes l and
-    // l + 32 can meet on an address; bin kStatsBins - 1 collects zeros and
+    // statistics only: HC copies, bin * HC + lane % HC, so only lanes HC
+    // apart can meet on an address; bin kStatsBins - 1 collects zeros and
     // non-finite values); after them the column maxima
     float plane[RW * WPL];
     float sc[NSB * N];                 // column block scales 2^E (MX)
@@ -879,8 +882,9 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // the squares is finite iff every part is), and the binade histogram
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
-            static_assert(kStatsBins * 32 <= RW * WPL, "histogram fits the planes");
-            for (int i = tid; i < kStatsBins * 32 / 4; i += RT) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
+            constexpr int HC = RowLds<F, C, KIND>::HC;
+            static_assert(kStatsBins * HC <= RW * WPL && HC >= 16, "histogram copies fit the planes");
+            for (int i = tid; i < kStatsBins * HC / 4; i += RT) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
             double m2max = 0.0, m2sum = 0.0;
@@ -892,7 +896,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
                 // zero (e = 0) and non-finite (e = 2047) land in the last bin
                 const uint32_t hi = (uint32_t)((unsigned long long)__double_as_longlong(m2) >> 32);
                 const uint32_t bin = min(((hi >> 20) - 725u) >> 1, (uint32_t)(kStatsBins - 1));
-                atomicAdd(&hist[bin * 32 + (lane & 31)], 1u);
+                atomicAdd(&hist[bin * HC + (lane & (HC - 1))], 1u);
             });
             m2max = wave_reduce_max(m2max);
             const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
@@ -925,14 +929,15 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
             // the tile's histogram to its part (the planes are needed next):
-            // sum the 32 copies of bin i, copy order skewed by i so a wave's
-            // reads fall in 32 different banks
+            // sum the HC copies of bin i, copy order skewed by i so a wave's
+            // reads fall in different banks
             __syncthreads();
+            constexpr int HC = RowLds<F, C, KIND>::HC;
             StatPart* pt = g.parts + (size_t)slice * (N / RL) + rb;
             for (int i = tid; i < kStatsBins; i += RT) {
                 uint32_t h = 0;
 #pragma unroll 8
-                for (int c = 0; c < 32; c++) h += hist[i * 32 + ((c + i) & 31)];
+                for (int c = 0; c < HC; c++) h += hist[i * HC + ((c + i) & (HC - 1))];
                 pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
             }
             __syncthreads();
