@@ -363,16 +363,22 @@ mxfft_status mxfft_batch_destroy(mxfft_batch_t b);
  * requests in arrival order (no overtaking) while a stream slot is free and
  * the device memory of the plans it holds stays within the budget: plans
  * (tables and workspace) are pooled by (n, parameters, batch capacity: the
- * coil count rounded up to a power of two) and reused; idle plans are evicted,
- * least recently used first, when a new one would exceed the budget.  A
- * planner thread creates and frees the plans, so admission of later requests
- * and completion of running ones never wait on an allocation or a free.  Up to
- * `slots` requests run at once, each on its own stream, so transfers of
- * results and the kernels of different requests overlap.  A request's input
- * and output stay caller-owned (pre-staged device buffers); each request is
- * computed exactly as a single mxfft_forward / mxfft_inverse / mxfft_roundtrip
- * call on its coils would be, so its result does not depend on what else
- * runs. */
+ * coil count rounded up to a power of two, at least 32) and reused; idle plans
+ * are evicted, least recently used first, when a new one would exceed the
+ * budget.  A planner thread creates and frees the plans, so admission of later
+ * requests and completion of running ones never wait on an allocation or a
+ * free.  When a slot frees, the request at the head of the queue takes it
+ * together with the queued requests behind it (up to 64 looked at) that have
+ * the same n, parameters and operation and fit its plan's capacity (at most
+ * 1024 slices): one launch sequence over all their slices, each request's
+ * buffers addressed through per-slice offset tables.  Up to `slots` launches
+ * run at once, each on its own stream, so transfers of results and the
+ * kernels of different requests overlap.  A request's input and output stay
+ * caller-owned (pre-staged device buffers; complex64, so 8-byte aligned for
+ * a shared launch); each request is computed exactly as a single
+ * mxfft_forward / mxfft_inverse / mxfft_roundtrip call on its coils would be
+ * (every slice is transformed independently), so its result does not depend
+ * on what else runs or shares its launch. */
 typedef struct mxfft_server_s* mxfft_server_t;
 
 typedef struct {
@@ -406,6 +412,8 @@ typedef struct {
     uint64_t plan_bytes, peak_plan_bytes; /* device bytes of the pooled plans: now, highest */
     uint64_t plans_created, plans_evicted;
     uint64_t budget;
+    uint64_t coalesced_launches;          /* launches that served several requests */
+    uint64_t coalesced_requests;          /* requests served by them */
 } mxfft_serve_counters;
 
 /* Create a server with `slots` concurrent requests (1..16; each its own
@@ -429,6 +437,12 @@ mxfft_status mxfft_serve_wait(mxfft_server_t srv, uint64_t ticket, mxfft_result*
 
 /* As mxfft_serve_wait without blocking: MXFFT_EBUSY while it is not done. */
 mxfft_status mxfft_serve_poll(mxfft_server_t srv, uint64_t ticket, mxfft_result* res);
+
+/* Hold (hold = 1) or resume (0) admissions: while held, submitted requests
+ * queue and running ones finish, but nothing new is admitted (maintenance,
+ * or filling the queue to measure the sustainable rate).  Destroying a held
+ * server still runs its queued requests.  MXFFT_EINVAL for another value. */
+mxfft_status mxfft_serve_hold(mxfft_server_t srv, int32_t hold);
 
 /* Counters (a consistent snapshot). */
 mxfft_status mxfft_serve_stats(mxfft_server_t srv, mxfft_serve_counters* out);

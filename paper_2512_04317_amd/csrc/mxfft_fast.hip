@@ -87,6 +87,7 @@ hipError_t launch_fast(int mode, int n, int cb, bool row, bool inverse, int kind
     g.rss = p.rss;
     g.coils = p.coils;
     g.slice_off = p.slice_off;
+    g.slice_off_out = p.slice_off_out;
     // the redo pass strides over its list: tiles of at most 64 slices in the grid
     if (row && kind == ROW_FIX && batch > 64) batch = 64;
     if (fast_wide(mode, n, cb)) {

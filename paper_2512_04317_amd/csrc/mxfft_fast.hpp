@@ -362,7 +362,8 @@ struct FastArgs {
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves, [2^b + j]
     float* rss;              // column pass with the coil combine: [reconstruction][N][N] FP32
     int32_t coils;           // coil slices per reconstruction (consecutive slices)
-    const unsigned long long* slice_off;  // element offset of each slice in src / dst, or nullptr
+    const unsigned long long* slice_off;      // element offset of each slice in src, or nullptr
+    const unsigned long long* slice_off_out;  // element offset of each slice in dst, or nullptr
 };
 
 using mxk::kStatsBins;
@@ -975,7 +976,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     constexpr int KL = Lay<CL>::NL - 1;
     const int pmL = posM<CL, KL>(m);
     if constexpr (F == FP32) {
-        float2* y = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + (size_t)row * N;
+        float2* y = g.dst + mxd::slice_base(g.slice_off_out, slice, (size_t)N * N) + (size_t)row * N;
         sfor<P>([&](auto O) { y[Lay<CL>::posF(KL, O) | pmL] = a[O]; });
     } else if constexpr (is_16(F)) {
         // 16-bit intermediate [slice][16-column group][row][16 words]: in-lane
@@ -1325,7 +1326,7 @@ __attribute__((amdgpu_waves_per_eu(waves_target(F == BF16), 8))) void k_col(Fast
     constexpr int LM = lane_mask<CL, KL>();
     static_assert(HB >= 0 && (LM & 1) == 0 && (LM >> (LOGN - 1)) == 0, "top row bit and bit 0 in-lane");
     const int pmL = posM<CL, KL>(m);
-    float2* ys = g.dst + mxd::slice_base(g.slice_off, slice, (size_t)N * N) + cb16 * LINES;
+    float2* ys = g.dst + mxd::slice_base(g.slice_off_out, slice, (size_t)N * N) + cb16 * LINES;
     sfor<2>([&](auto H) {
         __syncthreads();
         sfor<P>([&](auto O) {

@@ -372,6 +372,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
         f.fix_list = w.fix_list;
         f.fix_count = w.fix_count;
         f.slice_off = w.slice_off;
+        f.slice_off_out = w.slice_off_out ? w.slice_off_out : w.slice_off;
         return mxk::launch_fast(pl->mode, pl->n, pl->cb, axis == 0, inverse != 0, kind, f, batch, s) == hipSuccess
                    ? MXFFT_OK
                    : MXFFT_EHIP;
@@ -399,6 +400,7 @@ mxfft_status pass(mxfft_plan_s* pl, const mxk::Workspace& w, const void* src, vo
     a.cap_exp = capture ? pl->d_cap_exp : nullptr;
     a.cap_trace = capture ? pl->d_cap_trace : nullptr;
     a.slice_off = w.slice_off;
+    a.slice_off_out = w.slice_off_out ? w.slice_off_out : w.slice_off;
     return mxk::launch_lines(pl->mode, a, batch, s) == hipSuccess ? MXFFT_OK : MXFFT_EHIP;
 }
 
@@ -440,6 +442,7 @@ mxfft_status small(mxfft_plan_s* pl, const mxk::Workspace& w, const void* in, vo
     g.a.cap_exp = capture ? pl->d_cap_exp : nullptr;
     g.a.cap_trace = capture ? pl->d_cap_trace : nullptr;
     g.a.slice_off = w.slice_off;
+    g.a.slice_off_out = w.slice_off_out ? w.slice_off_out : w.slice_off;
     g.pa = prescale_args(pl);
     g.op = op;
     g.stats = stats ? 1 : 0;
@@ -712,6 +715,15 @@ mxfft_status mxfft_forward(mxfft_plan_t pl, const void* in, void* out, int32_t b
 
 namespace mxk {
 
+// The workspace as the passes after the first see it: they read the output
+// buffer, so the output's offset table addresses their input too.
+Workspace output_side(const Workspace& w)
+{
+    Workspace o = w;
+    if (w.slice_off_out) o.slice_off = w.slice_off_out;
+    return o;
+}
+
 mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
                              int32_t* k_out, void* stream)
 {
@@ -720,15 +732,16 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
     const int32_t* kp = pre ? w.kp : nullptr;
     const int kout_mul = (pl->p.flags & MXFFT_KEEP_SCALE) ? 0 : -1;
     const bool cap = pl->d_cap_mant != nullptr && batch <= pl->max_batch;   // capture buffers hold max_batch
+    const Workspace wo = output_side(w);
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 0, pre, nullptr, k_out, 1, kout_mul, 0, cap, batch, s));
     } else if (pre && fused_stats(pl)) {
         MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
         if (pre) MX_TRY(stats(pl, w, in, batch, s));
         MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr, 0, cap));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr,
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr,
                     0, cap));
     }
     if (cap && pl->fast && !pl->single) {
@@ -784,15 +797,16 @@ mxfft_status plan_inverse_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
         kp = w.kp;
         kin_mul = 1;
     }
+    const Workspace wo = output_side(w);
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 1, pre, pre ? nullptr : k_in, nullptr, kin_mul, -1, kout_add, false, batch, s));
     } else if (pre && fused_stats(pl)) {
         MX_TRY(row_with_stats(pl, w, in, nullptr, 1, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, w.kadd));
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s, mxk::ROW_PLAIN, w.kadd));
     } else {
         if (pre) MX_TRY(stats(pl, w, in, batch, s));
         MX_TRY(pass(pl, w, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
     }
     pl->last_batch = batch;
     pl->last_has_stats = pre;
@@ -806,19 +820,20 @@ mxfft_status plan_roundtrip_ws(mxfft_plan_s* pl, const Workspace& w, const void*
     hipStream_t s = (hipStream_t)stream;
     const bool pre = !(pl->p.flags & MXFFT_NO_PRESCALE);
     const int32_t* kp = pre ? w.kp : nullptr;
+    const Workspace wo = output_side(w);
     if (pl->single) {
         MX_TRY(small(pl, w, in, out, 2, pre, nullptr, k_out, 1, -1, -2 * pl->logn, false, batch, s));
     } else {
         if (pre && fused_stats(pl)) {
             MX_TRY(row_with_stats(pl, w, in, k_out, 0, batch, s));
-            MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
+            MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s, mxk::ROW_PLAIN, w.kadd));
         } else {
             if (pre) MX_TRY(stats(pl, w, in, batch, s));
             MX_TRY(pass(pl, w, in, out, kp, k_out, 1, 0, 0, 0, 0, batch, s));
-            MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
+            MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, 0, 0, 1, 0, batch, s));
         }
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
-        MX_TRY(pass(pl, w, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
+        MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     }
     pl->last_batch = batch;
     pl->last_has_stats = pre;

@@ -50,9 +50,12 @@ struct Workspace {
     int32_t* kadd = nullptr;      // fused statistics: exponent offset per slice
     int32_t* fix_list = nullptr;  // fused statistics: slices whose row pass is redone
     int32_t* fix_count = nullptr; // length of fix_list (cleared by the row pass)
-    // element offset of each slice in the caller's input and output pools, or
-    // nullptr for [batch][n][n] (uneven batches: slices anywhere in the pool)
+    // element offset of each slice in the caller's input pool, or nullptr for
+    // [batch][n][n] (uneven batches: slices anywhere in the pool); and in the
+    // output pool, or nullptr for the same offsets as the input (coalesced
+    // serving requests: slices of unrelated buffers)
     const unsigned long long* slice_off = nullptr;
+    const unsigned long long* slice_off_out = nullptr;
 };
 
 // Chunks per slice for a batch: enough work-groups to fill the chip, at
@@ -90,7 +93,8 @@ struct LineArgs {
     int32_t encode;          // MX-encode the pass input
     float2* cap_mant;        // column pass: its encoded input's element values, or nullptr
     int32_t* cap_exp;        // column pass: its input block exponents [slice][column][row block]
-    const unsigned long long* slice_off;  // slice offsets in src / dst, or nullptr (contiguous)
+    const unsigned long long* slice_off;      // slice offsets in src, or nullptr (contiguous)
+    const unsigned long long* slice_off_out;  // slice offsets in dst, or nullptr (contiguous)
     int32_t* cap_trace;      // row pass, debug capture: (E_v, k_r, E_out) per stage and block of line 0,
                              // [slice][log2 n][n / B][3], or nullptr
 };
@@ -119,7 +123,8 @@ struct FastPassArgs {
     const uint32_t* tw16;    // FP16 form: twiddles as packed halves at [h + j]
     float* rss;              // COL_RSS: [reconstruction][n][n] root-sum-of-squares image
     int32_t coils;           // COL_RSS: coil slices per reconstruction
-    const unsigned long long* slice_off;  // slice offsets in src / dst, or nullptr (contiguous)
+    const unsigned long long* slice_off;      // slice offsets in src, or nullptr (contiguous)
+    const unsigned long long* slice_off_out;  // slice offsets in dst, or nullptr (contiguous)
 };
 
 // Row pass kinds of the register-resident passes.

@@ -508,7 +508,8 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     extern __shared__ float2 lds[];
     const int N = a.n, logn = a.logn, R = a.lines, tid = threadIdx.x;
     const int slice = blockIdx.y;
-    const size_t sbase = mxd::slice_base(a.slice_off, slice, (size_t)N * N);   // slice in src / dst
+    const size_t sbase = mxd::slice_base(a.slice_off, slice, (size_t)N * N);       // slice in src
+    const size_t dbase = mxd::slice_base(a.slice_off_out, slice, (size_t)N * N);   // slice in dst
     const size_t cbase = (size_t)slice * N * N;                               // slice in the capture
     const int line0 = blockIdx.x * R;
     int kp = a.kp ? a.kp[slice] : 0;
@@ -607,11 +608,11 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
         if (a.axis == 0) {
             r = idx >> logn;
             e = idx & (N - 1);
-            g = sbase + (size_t)(line0 + r) * N + e;
+            g = dbase + (size_t)(line0 + r) * N + e;
         } else {
             e = idx / R;
             r = idx & (R - 1);
-            g = sbase + (size_t)e * N + line0 + r;
+            g = dbase + (size_t)e * N + line0 + r;
         }
         float2 v = lds[r * N + e];
         if constexpr (MODE == MODE_FP16 || MODE == MODE_BF16) {
@@ -840,7 +841,7 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
         small_pass<MODE>(a, buf, true, MX, nullptr, nullptr, nullptr, slice);
     }
     const int kout = g.kout_mul * k + g.kout_add;
-    float2* ys = g.a.dst + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
+    float2* ys = g.a.dst + mxd::slice_base(g.a.slice_off_out, slice, (size_t)nn);
     for (int i = tid; i < nn; i += blockDim.x) {
         const float2 v = buf[(i >> logn) * pitch + (i & (N - 1))];
         ys[i] = make_float2(ldexpf(v.x, kout), ldexpf(v.y, kout));

@@ -5,6 +5,7 @@
 // on an allocation or a free: it keeps polling completions meanwhile.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -22,6 +23,12 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr int kMaxSlots = 16;
 constexpr int kMaxCoils = 65535;
+// Pooled plans hold at least this many slices, so that small requests queued
+// together can share one launch sequence; a shared launch takes at most
+// kMaxGroup slices and looks at most kGroupScan queued requests ahead.
+constexpr int kMinCap = 32;
+constexpr int kMaxGroup = 1024;
+constexpr int kGroupScan = 64;
 
 static_assert((int)MXFFT_E4M3 == (int)mxk::MODE_E4M3 && (int)MXFFT_E5M2 == (int)mxk::MODE_E5M2 &&
                   (int)MXFFT_E2M3 == (int)mxk::MODE_E2M3 && (int)MXFFT_E3M2 == (int)mxk::MODE_E3M2,
@@ -47,11 +54,21 @@ struct Request {
     mxfft_result res{};
 };
 
+// A request of a launch and its first slice in it.
+struct Member {
+    uint64_t ticket;
+    int first;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    int32_t* h_status = nullptr;   // pinned copy of the request's status words
-    uint64_t ticket = 0;           // 0: free
+    int32_t* h_status = nullptr;   // pinned copy of the launch's status words
+    unsigned long long* h_off = nullptr;   // pinned: input then output slice offsets of a shared launch
+    unsigned long long* d_off = nullptr;   // their device copy
+    int32_t* d_k = nullptr;        // k of a shared launch, before its copy to each request
+    uint64_t ticket = 0;           // 0: free; else the (first) request
+    std::vector<Member> members;   // every request of the launch
     PooledPlan* plan = nullptr;
     bool has_status = false;
 };
@@ -67,9 +84,20 @@ bool same_params(const mxfft_params& a, const mxfft_params& b)
 
 int capacity_of(int coils)
 {
-    int c = 1;
+    int c = kMinCap;
     while (c < coils) c <<= 1;
     return c > kMaxCoils ? kMaxCoils : c;
+}
+
+// Requests that one launch sequence can serve together: the same size,
+// parameters and operation, and complex64 buffers (8-byte aligned, so that
+// their slices are element offsets from the lowest address).
+bool can_share(const mxfft_request& a, const mxfft_request& b)
+{
+    auto aligned = [](const mxfft_request& r) {
+        return ((uintptr_t)r.in % 8) == 0 && ((uintptr_t)r.out % 8) == 0;
+    };
+    return a.n == b.n && a.op == b.op && same_params(a.params, b.params) && aligned(a) && aligned(b);
 }
 
 struct PlanJob {
@@ -93,6 +121,7 @@ struct mxfft_server_s {
     std::condition_variable cv_work, cv_done, cv_plan;
     std::thread th, planner;
     bool stop = false, planner_stop = false;
+    bool held = false;             // admissions paused (mxfft_serve_hold)
     uint64_t next_ticket = 1, use_clock = 0;
     uint64_t events = 0;           // submissions and finished plan jobs (wakes the idle scheduler)
     uint64_t freeing = 0;          // bytes of evicted plans the planner has yet to free
@@ -246,8 +275,124 @@ struct mxfft_server_s {
             return;
         }
         s.ticket = ticket;
+        s.members.assign(1, Member{ticket, 0});
         s.plan = pp;
         c.in_flight++;
+    }
+
+    // Enqueue the requests `group` (the first one q, whose plan pp has room
+    // for all of them) on slot si as one launch sequence over their slices:
+    // per-slice offset tables address each request's input and output
+    // buffers from the lowest of them; k goes to the slot's array and then to
+    // each request's k_out.  Each request's result is the one it would have
+    // alone: every slice is transformed independently.  When an enqueue
+    // fails every request of the group is finished with that status.
+    void launch_group(const std::vector<uint64_t>& group, PooledPlan* pp, int si)
+    {
+        if (group.size() == 1) {
+            launch(group[0], reqs[group[0]], pp, si);
+            return;
+        }
+        Slot& s = slots[si];
+        pp->last_use = ++use_clock;
+        const double t = now_ms();
+        const size_t nn = (size_t)pp->n * pp->n;
+        uintptr_t in0 = UINTPTR_MAX, out0 = UINTPTR_MAX;
+        int total = 0;
+        bool want_k = false;
+        for (uint64_t tk : group) {
+            const mxfft_request& r = reqs[tk].r;
+            in0 = std::min(in0, (uintptr_t)r.in);
+            out0 = std::min(out0, (uintptr_t)r.out);
+            total += r.coils;
+            want_k |= r.k_out != nullptr;
+        }
+        s.members.clear();
+        int first = 0;
+        for (uint64_t tk : group) {
+            Request& q = reqs[tk];
+            q.state = 1;
+            q.res.slot = si;
+            q.res.t_start_ms = t;
+            const unsigned long long bi = ((uintptr_t)q.r.in - in0) / 8, bo = ((uintptr_t)q.r.out - out0) / 8;
+            for (int j = 0; j < q.r.coils; j++) {
+                s.h_off[first + j] = bi + (unsigned long long)j * nn;
+                s.h_off[total + first + j] = bo + (unsigned long long)j * nn;
+            }
+            s.members.push_back(Member{tk, first});
+            first += q.r.coils;
+        }
+        mxfft_status st = MXFFT_OK;
+        for (uint64_t tk : group) {
+            const mxfft_request& r = reqs[tk].r;
+            if (st == MXFFT_OK && r.ready && hipStreamWaitEvent(s.stream, (hipEvent_t)r.ready, 0) != hipSuccess)
+                st = MXFFT_EHIP;
+        }
+        if (st == MXFFT_OK && hipMemcpyAsync(s.d_off, s.h_off, sizeof(unsigned long long) * 2 * (size_t)total,
+                                             hipMemcpyHostToDevice, s.stream) != hipSuccess)
+            st = MXFFT_EHIP;
+        if (st == MXFFT_OK) {
+            mxk::Workspace w = mxk::plan_workspace(pp->plan);
+            w.slice_off = s.d_off;
+            w.slice_off_out = s.d_off + total;
+            int32_t* kb = want_k ? s.d_k : nullptr;
+            const mxfft_request& r0 = reqs[group[0]].r;
+            switch (r0.op) {
+            case 0: st = mxk::plan_forward_ws(pp->plan, w, (const void*)in0, (void*)out0, total, kb, s.stream); break;
+            case 1: st = mxk::plan_inverse_ws(pp->plan, w, (const void*)in0, (void*)out0, total, nullptr, s.stream); break;
+            default: st = mxk::plan_roundtrip_ws(pp->plan, w, (const void*)in0, (void*)out0, total, kb, s.stream); break;
+            }
+            for (const Member& m : s.members) {
+                const mxfft_request& r = reqs[m.ticket].r;
+                if (st == MXFFT_OK && kb && r.k_out && r.op != 1 &&
+                    hipMemcpyAsync(r.k_out, kb + m.first, sizeof(int32_t) * (size_t)r.coils, hipMemcpyDeviceToDevice,
+                                   s.stream) != hipSuccess)
+                    st = MXFFT_EHIP;
+            }
+        }
+        s.has_status = mxk::plan_has_status(pp->plan);
+        if (st == MXFFT_OK && s.has_status &&
+            hipMemcpyAsync(s.h_status, mxk::plan_status_words(pp->plan), sizeof(int32_t) * (size_t)total,
+                           hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+            st = MXFFT_EHIP;
+        if (st == MXFFT_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = MXFFT_EHIP;
+        c.admitted += group.size();
+        if (st != MXFFT_OK) {
+            pp->busy = false;
+            for (uint64_t tk : group) finish(reqs[tk], st);
+            s.members.clear();
+            return;
+        }
+        c.coalesced_launches++;
+        c.coalesced_requests += group.size();
+        s.ticket = group[0];
+        s.plan = pp;
+        c.in_flight += group.size();
+    }
+
+    // The head-of-queue request and the queued requests after it that can
+    // share its launch (its plan has room; they wait on no plan of their own),
+    // taken out of the queue in arrival order.
+    std::vector<uint64_t> take_group(PooledPlan* pp)
+    {
+        std::vector<uint64_t> g{queue.front()};
+        const Request& q = reqs[queue.front()];
+        int total = q.r.coils;
+        const int room = std::min(pp->cap, kMaxGroup);
+        auto it = queue.begin() + 1;
+        for (int looked = 0; it != queue.end() && looked < kGroupScan && total < room; looked++) {
+            const Request& o = reqs[*it];
+            if (!o.building && total + o.r.coils <= room && can_share(q.r, o.r)) {
+                total += o.r.coils;
+                g.push_back(*it);
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        queue.pop_front();
+        c.queued -= g.size();
+        return g;
     }
 
     void loop()
@@ -266,23 +411,26 @@ struct mxfft_server_s {
                     busy = true;
                     continue;
                 }
-                Request& q = reqs[s.ticket];
-                int32_t status = (e == hipSuccess) ? MXFFT_OK : MXFFT_EHIP;
-                if (e == hipSuccess && s.has_status)
-                    for (int i = 0; i < q.r.coils; i++)
-                        if (s.h_status[i] != 0) {
-                            status = s.h_status[i];
-                            break;
-                        }
+                for (const Member& m : s.members) {
+                    Request& q = reqs[m.ticket];
+                    int32_t status = (e == hipSuccess) ? MXFFT_OK : MXFFT_EHIP;
+                    if (e == hipSuccess && s.has_status)
+                        for (int i = 0; i < q.r.coils; i++)
+                            if (s.h_status[m.first + i] != 0) {
+                                status = s.h_status[m.first + i];
+                                break;
+                            }
+                    c.in_flight--;
+                    finish(q, status);
+                }
                 s.plan->busy = false;
                 s.plan->last_use = ++use_clock;
                 s.ticket = 0;
+                s.members.clear();
                 s.plan = nullptr;
-                c.in_flight--;
-                finish(q, status);
             }
             // admissions, in arrival order
-            while (!queue.empty()) {
+            while (!queue.empty() && !held) {
                 int si = -1;
                 for (int i = 0; i < (int)slots.size(); i++)
                     if (!slots[i].ticket) {
@@ -295,17 +443,21 @@ struct mxfft_server_s {
                 mxfft_status err;
                 PooledPlan* pp = acquire(q, &err);
                 if (!pp && err == MXFFT_OK) break;   // wait for a plan or for budget
-                queue.pop_front();
-                c.queued--;
                 if (!pp) {
+                    queue.pop_front();
+                    c.queued--;
                     c.admitted++;
                     finish(q, err);
                     continue;
                 }
-                launch(t, q, pp, si);
+                launch_group(take_group(pp), pp, si);
                 if (slots[si].ticket) busy = true;
             }
-            if (stop && queue.empty() && !busy) break;
+            if (stop && (queue.empty() || held) && !busy) {
+                if (!held) break;
+                held = false;      // stopping: the queued requests still run
+                continue;
+            }
             if (busy) {
                 lk.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -335,10 +487,17 @@ mxfft_status mxfft_serve_create(mxfft_server_t* out, uint64_t hbm_budget_bytes, 
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc((void**)&sl.h_status, sizeof(int32_t) * kMaxCoils, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&sl.h_off, sizeof(unsigned long long) * 2 * kMaxGroup, hipHostMallocDefault) ==
+                       hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.d_off, sizeof(unsigned long long) * 2 * kMaxGroup) == hipSuccess;
+        ok = ok && hipMalloc((void**)&sl.d_k, sizeof(int32_t) * kMaxGroup) == hipSuccess;
     }
     if (!ok) {
         for (Slot& sl : s->slots) {
             if (sl.h_status) (void)hipHostFree(sl.h_status);
+            if (sl.h_off) (void)hipHostFree(sl.h_off);
+            (void)hipFree(sl.d_off);
+            (void)hipFree(sl.d_k);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
@@ -406,6 +565,16 @@ mxfft_status mxfft_serve_poll(mxfft_server_t srv, uint64_t ticket, mxfft_result*
     return MXFFT_OK;
 }
 
+mxfft_status mxfft_serve_hold(mxfft_server_t srv, int32_t hold)
+{
+    if (!srv || (hold != 0 && hold != 1)) return MXFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->held = hold != 0;
+    srv->events++;
+    srv->cv_work.notify_one();
+    return MXFFT_OK;
+}
+
 mxfft_status mxfft_serve_stats(mxfft_server_t srv, mxfft_serve_counters* out)
 {
     if (!srv || !out) return MXFFT_EINVAL;
@@ -435,6 +604,9 @@ mxfft_status mxfft_serve_destroy(mxfft_server_t srv)
     }
     for (Slot& sl : srv->slots) {
         (void)hipHostFree(sl.h_status);
+        (void)hipHostFree(sl.h_off);
+        (void)hipFree(sl.d_off);
+        (void)hipFree(sl.d_k);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }

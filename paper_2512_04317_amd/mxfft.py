@@ -27,7 +27,8 @@ EXPORTS = ("mxfft_params_default", "mxfft_plan", "mxfft_plan_destroy", "mxfft_fo
            "mxfft_plan_set_tuning", "mxfft_plan_get_tuning", "mxfft_tune", "mxfft_tune_cache_lookup",
            "mxfft_batch_create", "mxfft_batch_execute", "mxfft_batch_last_status", "mxfft_batch_group_tuning",
            "mxfft_batch_destroy", "mxfft_plan_bytes", "mxfft_serve_create", "mxfft_serve_submit",
-           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_stats", "mxfft_serve_destroy", "mxfft_rss",
+           "mxfft_serve_wait", "mxfft_serve_poll", "mxfft_serve_hold", "mxfft_serve_stats", "mxfft_serve_destroy",
+           "mxfft_rss",
            "mxfft_ssim", "mxfft_plan_capture")
 TUNE_FORCE = 0x1
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
@@ -66,7 +67,7 @@ class Result(ctypes.Structure):
 class ServeCounters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "submitted", "admitted", "completed", "rejected", "queued", "in_flight", "plan_bytes", "peak_plan_bytes",
-        "plans_created", "plans_evicted", "budget")]
+        "plans_created", "plans_evicted", "budget", "coalesced_launches", "coalesced_requests")]
 
 
 class KernelTime(ctypes.Structure):
@@ -151,6 +152,8 @@ def lib():
             getattr(L, name).argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
         L.mxfft_serve_stats.restype = i32
         L.mxfft_serve_stats.argtypes = [P, ctypes.POINTER(ServeCounters)]
+        L.mxfft_serve_hold.restype = i32
+        L.mxfft_serve_hold.argtypes = [P, i32]
         L.mxfft_serve_destroy.restype = i32
         L.mxfft_serve_destroy.argtypes = [P]
         _lib = L
@@ -549,6 +552,12 @@ class Server:
             raise MxfftError(st, "mxfft_serve_poll")
         self._release(ticket)
         return self._res(r)
+
+    def hold(self, on=True):
+        """Pause (on) or resume admissions; queued requests wait meanwhile."""
+        st = lib().mxfft_serve_hold(self.handle, 1 if on else 0)
+        if st != OK:
+            raise MxfftError(st, "mxfft_serve_hold")
 
     def stats(self):
         c = ServeCounters()

@@ -1,8 +1,8 @@
 """Serving on the GPU, through the C ABI: results bit-identical to the oracle
-and to a single plan, alone and in a mixed stream of requests; plans never
-shared across block sizes (MXFP8 and MXFP6); admission under a device-memory
-budget; a request with non-finite input failing alone (its neighbours
-unaffected)."""
+and to a single plan, alone, in a mixed stream of requests and when queued
+requests share one launch; plans never shared across block sizes (MXFP8 and
+MXFP6); admission under a device-memory budget; a request with non-finite
+input failing alone (its neighbours unaffected)."""
 import os
 import threading
 
@@ -111,13 +111,13 @@ def test_serve_budget_admission():
     plan alone exceeds the budget is rejected at submission."""
     kinds = [dict(fmt="fp16"), dict(fmt="bf16"), dict(fmt="fp16", target=64.0), dict(fmt="bf16", target=64.0),
              dict(fmt="fp16", target=32.0)]
-    need = max(mxfft.plan_bytes(512, 4, **p) for p in kinds)
+    need = max(mxfft.plan_bytes(512, 32, **p) for p in kinds)     # pooled plans hold at least 32 slices
     budget = need + need // 2
     srv = mxfft.Server(budget, slots=3)
     xs = [torch.from_numpy(synth.random_complex((3, 512, 512), seed=i, dist="lognormal")).cuda() for i in range(5)]
     outs = [torch.empty_like(x) for x in xs]
     tickets = [srv.submit(x, o, op=mxfft.FORWARD, **p) for x, o, p in zip(xs, outs, kinds)]
-    big = torch.empty((64, 512, 512), dtype=torch.complex64, device="cuda")
+    big = torch.empty((128, 512, 512), dtype=torch.complex64, device="cuda")
     with pytest.raises(mxfft.MxfftError) as e:
         srv.submit(big, big, fmt="fp16")          # its workspace alone is above the budget
     assert e.value.status == mxfft.EBUDGET
@@ -191,3 +191,65 @@ def test_serve_waits_for_input_written_on_the_submitting_stream():
     yo, _ = oracle_of(x0, mxfft.FORWARD)
     assert np.array_equal(bits(out.cpu().numpy()), bits(yo))
     srv.close()
+
+
+def test_serve_coalesces_queued_requests():
+    """Requests queued while admissions are held, then released onto one
+    slot: those of the same size, parameters and operation share launches
+    (counted), the others run on their own; interleaved, with an in-place
+    request, one without k_out and one with a non-finite slice.  Nothing is
+    admitted while held.  Every result bit for bit as the request alone and
+    as the oracle, k included; the non-finite request fails alone."""
+    import time
+    srv = mxfft.Server(8 * GiB, slots=1)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(14):
+        coils = int(rng.integers(1, 5))
+        x = torch.from_numpy(synth.random_complex((coils, 128, 128), seed=200 + i, dist="lognormal")).cuda()
+        op, params = mxfft.FORWARD, dict(fmt="e4m3", block=32)
+        if i % 5 == 3:
+            op = mxfft.ROUNDTRIP
+        if i % 7 == 6:
+            params = dict(fmt="e5m2", block=16)
+        if i == 9:
+            x[coils - 1, 3, 4] = complex(float("inf"), 0.0)
+        reqs.append((x, op, params))
+    x_ref = [x.clone() for x, _, _ in reqs]
+    outs = [x if i == 4 else torch.empty_like(x) for i, (x, _, _) in enumerate(reqs)]   # request 4 in place
+    ks = [None if i == 2 else torch.full((x.shape[0],), 777, dtype=torch.int32, device="cuda")
+          for i, (x, _, _) in enumerate(reqs)]
+    torch.cuda.synchronize()
+    print("serve coalescing: %d requests queued while held" % len(reqs), flush=True)
+    srv.hold(True)
+    tickets = [srv.submit(x, o, k, op=op, **p) for (x, op, p), o, k in zip(reqs, outs, ks)]
+    time.sleep(0.05)
+    st = srv.stats()
+    assert st["admitted"] == 0 and st["queued"] == len(reqs), st
+    srv.hold(False)
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["in_flight"] == 0 and st["queued"] == 0
+    # forward e4m3 (10 requests) and round trip e4m3 (2) share launches
+    assert st["coalesced_launches"] >= 2 and st["coalesced_requests"] >= 5, st
+    for i, ((_, op, params), r) in enumerate(zip(reqs, res)):
+        x0 = x_ref[i]
+        if i == 9:
+            assert r["status"] == mxfft.ENONFINITE, r
+            continue
+        assert r["status"] == mxfft.OK, (i, r)
+        got = bits(outs[i].cpu().numpy())
+        y, k = alone(x0, op, **params)
+        assert np.array_equal(got, bits(y)), "request %d" % i
+        yo, ko = oracle_of(x0, op, **params)
+        assert np.array_equal(got, bits(yo)), "request %d vs oracle" % i
+        if ks[i] is not None:
+            assert np.array_equal(ks[i].cpu().numpy(), ko), "request %d k" % i
+    # a server destroyed while held still runs what it has queued
+    srv.hold(True)
+    x, op, params = reqs[0]
+    out = torch.empty_like(x)
+    srv.submit(x_ref[0], out, op=op, **params)
+    srv.close()
+    y, _ = alone(x_ref[0], op, **params)
+    assert np.array_equal(bits(out.cpu().numpy()), bits(y))
