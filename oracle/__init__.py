@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "libmxfft_oracle.so")
 E4M3, E5M2, FP16, BF16, E6M23, E2M3, E3M2 = 0, 1, 2, 3, 4, 5, 6
 MODE_MX, MODE_FP32, MODE_FP16, MODE_BF16 = 0, 1, 2, 3
 OK, EINVAL, ENONFINITE, ERANGE = 0, -1, -4, -5
-NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_RT = 1, 2, 4, 8
+NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_RT, QUANTIZE_OUT = 1, 2, 4, 8, 32
 FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
 INT32_MIN = -(2 ** 31)
 INT32_MAX = 2 ** 31 - 1

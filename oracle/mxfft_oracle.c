@@ -30,7 +30,11 @@
  *   - one prescale exponent per N x N slice (Alg. 1); the forward output is
  *     de-scaled by 2^-k; the round trip keeps k and applies 2^(-k - 2 log2 N);
  *   - percentile: linear interpolation between order statistics,
- *     pos = ((n-1)*tau)/100 in FP64, p = S[i] + f*(S[i+1]-S[i]) in FP64.
+ *     pos = ((n-1)*tau)/100 in FP64, p = S[i] + f*(S[i+1]-S[i]) in FP64;
+ *   - quantised output (flag, MX formats; the 16-bit control's "quantized
+ *     outputs", Sec. 2.2, carried over to MX): EncodeBlockMX of the final
+ *     de-scaled output in blocks of B/2 consecutive rows of one column (the
+ *     last pass's axis), each value element * 2^E rounded once to FP32.
  */
 #include <math.h>
 #include <stdint.h>
@@ -567,7 +571,40 @@ typedef struct {
     pthread_mutex_t mu;
 } job;
 
+/* The flag's output quantisation: every column of an N x N slice MX-encoded
+ * in blocks of B/2 consecutive rows (EncodeBlockMX), each value replaced by
+ * element * 2^E rounded once to FP32. */
+static void quantize_columns(int fmt, int B, int N, float* a)
+{
+    const int cb = B / 2;
+    double vals[2 * 4096], m[2 * 4096];
+    for (int col = 0; col < N; col++)
+        for (int rb = 0; rb < N / cb; rb++) {
+            for (int k = 0; k < cb; k++) {
+                const long idx = (long)(rb * cb + k) * N + col;
+                vals[2 * k] = a[2 * idx];
+                vals[2 * k + 1] = a[2 * idx + 1];
+            }
+            const int e = orc_mx_encode(fmt, vals, 2 * cb, m);
+            for (int k = 0; k < cb; k++) {
+                const long idx = (long)(rb * cb + k) * N + col;
+                a[2 * idx] = (float)ldexp(m[2 * k], e);
+                a[2 * idx + 1] = (float)ldexp(m[2 * k + 1], e);
+            }
+        }
+}
+
+static int run_slice_body(job* jb, long s, double* scratch, float* line);
+
 static int run_slice(job* jb, long s, double* scratch, float* line)
+{
+    const int st = run_slice_body(jb, s, scratch, line);
+    if (st == ORC_OK && (jb->flags & ORC_QUANTIZE_OUT) && jb->mode == ORC_MODE_MX)
+        quantize_columns(jb->fmt, jb->B, jb->N, jb->out + 2 * (long)jb->N * jb->N * s);
+    return st;
+}
+
+static int run_slice_body(job* jb, long s, double* scratch, float* line)
 {
     const int N = jb->N, L = ilog2i(N);
     const long NN = (long)N * N;

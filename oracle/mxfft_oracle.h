@@ -16,7 +16,7 @@
 enum { ORC_E4M3 = 0, ORC_E5M2 = 1, ORC_FP16 = 2, ORC_BF16 = 3, ORC_E6M23 = 4, ORC_E2M3 = 5, ORC_E3M2 = 6, ORC_NFMT = 7 };
 enum { ORC_MODE_MX = 0, ORC_MODE_FP32 = 1, ORC_MODE_FP16 = 2, ORC_MODE_BF16 = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONFINITE = -4, ORC_ERANGE = -5 };
-enum { ORC_NO_PRESCALE = 1u, ORC_KEEP_SCALE = 2u, ORC_NORMALIZE = 4u, ORC_FUSED_RT = 8u };
+enum { ORC_NO_PRESCALE = 1u, ORC_KEEP_SCALE = 2u, ORC_NORMALIZE = 4u, ORC_FUSED_RT = 8u, ORC_QUANTIZE_OUT = 32u };
 
 int orc_fmt_info(int f, int* ebits, int* mbits, int* emin, int* emax, double* maxval);
 double orc_quantize(int f, double x);

@@ -50,8 +50,9 @@ int main(void)
         for (int fi = 0; fi < 5; fi++)
             for (int B = 2; B <= N && B <= 64; B *= 2)
                 for (int op = 0; op < 3; op++)
-                    for (int fi2 = 0; fi2 < 4; fi2++) {
-                        const unsigned flv[4] = {0u, ORC_NO_PRESCALE | ORC_KEEP_SCALE, ORC_NORMALIZE, ORC_FUSED_RT};
+                    for (int fi2 = 0; fi2 < 5; fi2++) {
+                        const unsigned flv[5] = {0u, ORC_NO_PRESCALE | ORC_KEEP_SCALE, ORC_NORMALIZE, ORC_FUSED_RT,
+                                                 ORC_QUANTIZE_OUT | ORC_FUSED_RT};
                         const unsigned fl = flv[fi2];
                         if (fmts[fi] == ORC_E6M23 && B > 8) continue;
                         const int st = orc_transform(op, ORC_MODE_MX, fmts[fi], B, N, batch, x, y, k, 0, 128.0, 5.0,
