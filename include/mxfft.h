@@ -82,6 +82,16 @@ typedef enum {
  * complex value of max_batch slices, and each forward call of up to
  * max_batch slices writes them. */
 #define MXFFT_DEBUG_CAPTURE 0x10u
+/* MX formats: the output is stored quantised, as the paper's 16-bit control
+ * stores its output in its format (Sec. 2.2): after the last pass and the
+ * de-scale, every column is MX-encoded in blocks of B/2 consecutive rows
+ * (Alg. 2's EncodeBlockMX: shared exponent E from the block maximum, elements
+ * rounded to nearest even and saturated) and each value becomes element *
+ * 2^E, rounded once to FP32.  Forward, inverse and round trip; one more read
+ * and write of the output.  The 16-bit forms always round their output to the
+ * format; FP32 ignores the flag.  mxfft_rss refuses such plans
+ * (MXFFT_EUNSUPPORTED): it never stores the per-coil results. */
+#define MXFFT_QUANTIZE_OUTPUT 0x20u
 
 typedef struct {
     uint32_t struct_size;  /* sizeof(mxfft_params); checked for ABI versioning */

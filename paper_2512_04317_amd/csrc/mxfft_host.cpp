@@ -15,7 +15,8 @@
 namespace {
 
 constexpr uint32_t kKnownFlags =
-    MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE | MXFFT_FUSED_ROUNDTRIP | MXFFT_DEBUG_CAPTURE;
+    MXFFT_NO_PRESCALE | MXFFT_KEEP_SCALE | MXFFT_NORMALIZE | MXFFT_FUSED_ROUNDTRIP | MXFFT_DEBUG_CAPTURE |
+    MXFFT_QUANTIZE_OUTPUT;
 
 // Element formats for twiddle pre-quantisation (OCP E4M3 / E5M2) and the
 // 16-bit forms (IEEE half, bfloat16; twiddles never reach their overflow).
@@ -724,6 +725,15 @@ Workspace output_side(const Workspace& w)
     return o;
 }
 
+// MXFFT_QUANTIZE_OUTPUT (MX formats): the finished output MX-encoded in place.
+mxfft_status quantize_output(const mxfft_plan_s* pl, const Workspace& w, void* out, int batch, hipStream_t s)
+{
+    if (!(pl->p.flags & MXFFT_QUANTIZE_OUTPUT) || !is_mx_mode(pl->mode)) return MXFFT_OK;
+    const unsigned long long* off = w.slice_off_out ? w.slice_off_out : w.slice_off;
+    return launch_quantize_out(pl->mode, (float2*)out, off, pl->n, pl->logcb, batch, s) == hipSuccess ? MXFFT_OK
+                                                                                                     : MXFFT_EHIP;
+}
+
 mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* in, void* out, int32_t batch,
                              int32_t* k_out, void* stream)
 {
@@ -744,6 +754,7 @@ mxfft_status plan_forward_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
         MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, kout_mul, 0, 1, 0, batch, s, mxk::ROW_PLAIN, nullptr, nullptr,
                     0, cap));
     }
+    MX_TRY(quantize_output(pl, w, out, batch, s));
     if (cap && pl->fast && !pl->single) {
         // the register-resident intermediate holds the column pass input
         if (mxk::launch_capture_mx(pl->mode, pl->n, pl->cb, w.codes, w.exps, (pre && fused_stats(pl)) ? w.kadd : nullptr,
@@ -808,6 +819,7 @@ mxfft_status plan_inverse_ws(mxfft_plan_s* pl, const Workspace& w, const void* i
         MX_TRY(pass(pl, w, in, out, kp, nullptr, kin_mul, 0, 0, 0, 1, batch, s));
         MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, -1, kout_add, 1, 1, batch, s));
     }
+    MX_TRY(quantize_output(pl, w, out, batch, s));
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     pl->last_status = w.status;
@@ -835,6 +847,7 @@ mxfft_status plan_roundtrip_ws(mxfft_plan_s* pl, const Workspace& w, const void*
         MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, 0, 0, 0, 1, batch, s, inverse_row_kind(pl)));
         MX_TRY(pass(pl, wo, out, out, kp, nullptr, 0, -1, -2 * pl->logn, 1, 1, batch, s));
     }
+    MX_TRY(quantize_output(pl, w, out, batch, s));
     pl->last_batch = batch;
     pl->last_has_stats = pre;
     pl->last_status = w.status;
@@ -849,6 +862,7 @@ mxfft_status mxfft_rss(mxfft_plan_t pl, int32_t op, const void* in, void* work, 
                        int32_t coils, int32_t* k_out, void* stream)
 {
     if (!pl || !in || !rss || recon < 0 || coils < 1 || (op != 0 && op != 2)) return MXFFT_EINVAL;
+    if ((pl->p.flags & MXFFT_QUANTIZE_OUTPUT) && mxk::is_mx_mode(pl->mode)) return MXFFT_EUNSUPPORTED;
     if ((long)recon * coils > pl->max_batch) return MXFFT_EINVAL;
     // the FP32 form keeps its intermediate in complex64 (the row pass writes
     // it where the column pass reads it): `work` is that buffer

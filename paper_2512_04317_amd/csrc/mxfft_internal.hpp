@@ -177,6 +177,10 @@ struct SmallArgs {
 // cus, lds_per_cu: the device's compute units and LDS bytes per CU (they
 // set the work-group size; see small_block)
 hipError_t launch_small(int mode, const SmallArgs& g, int batch, int cus, int lds_per_cu, hipStream_t s);
+// The output of batch n x n slices (slice offsets off, or nullptr) MX-encoded
+// in place in blocks of 2^logcb consecutive rows of one column.
+hipError_t launch_quantize_out(int mode, float2* out, const unsigned long long* off, int n, int logcb, int batch,
+                               hipStream_t s);
 int small_block(int n, int batch, int cus, int lds_per_cu);
 int line_lines_per_group(int n);
 // Debug capture from the register-resident MX intermediate: element values

@@ -885,6 +885,50 @@ hipError_t launch_small(int mode, const SmallArgs& g, int batch, int cus, int ld
     return hipGetLastError();
 }
 
+// Output quantisation (MXFFT_QUANTIZE_OUTPUT): one thread per (slice, row
+// block, column), consecutive threads on consecutive columns, so every row of
+// a block is read and written as whole row segments.  The block's exponent
+// from its maximum, then each value re-encoded with it (the same encode as
+// the passes' input encode).
+template <int MODE>
+__global__ void k_quantize_out(float2* __restrict__ out, const unsigned long long* __restrict__ off, int n,
+                               int logcb, long total)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int cb = 1 << logcb, nb = n >> logcb;
+    const long per_slice = (long)nb * n;
+    const long slice = i / per_slice;
+    const int rem = (int)(i - slice * per_slice), rb = rem / n, col = rem - rb * n;
+    float2* y = out + mxd::slice_base(off, slice, (size_t)n * n) + (size_t)rb * cb * n + col;
+    uint32_t am = 0;
+    for (int r = 0; r < cb; r++) {
+        const float2 v = y[(size_t)r * n];
+        am = max(am, max(mxd::abs_key(v.x), mxd::abs_key(v.y)));
+    }
+    const int E = mxd::block_exp<MODE>(am);
+    for (int r = 0; r < cb; r++) {
+        float qx, qy;
+        mx_encode_value<MODE>(y[(size_t)r * n], E, qx, qy);
+        y[(size_t)r * n] = make_float2(ldexpf(qx, E), ldexpf(qy, E));
+    }
+}
+
+hipError_t launch_quantize_out(int mode, float2* out, const unsigned long long* off, int n, int logcb, int batch,
+                               hipStream_t s)
+{
+    const long total = (long)batch * (n >> logcb) * n;
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    switch (mode) {
+    case MODE_E4M3: hipLaunchKernelGGL(k_quantize_out<MODE_E4M3>, grid, block, 0, s, out, off, n, logcb, total); break;
+    case MODE_E5M2: hipLaunchKernelGGL(k_quantize_out<MODE_E5M2>, grid, block, 0, s, out, off, n, logcb, total); break;
+    case MODE_E2M3: hipLaunchKernelGGL(k_quantize_out<MODE_E2M3>, grid, block, 0, s, out, off, n, logcb, total); break;
+    case MODE_E3M2: hipLaunchKernelGGL(k_quantize_out<MODE_E3M2>, grid, block, 0, s, out, off, n, logcb, total); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 __global__ void k_scatter_k(const int32_t* __restrict__ src, const int32_t* __restrict__ idx,
                             int32_t* __restrict__ dst, int count)
 {

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libmxfft.so")
 
 E4M3, E5M2, FP16, BF16, FP32, E2M3, E3M2 = 0, 1, 2, 3, 4, 5, 6
 FORMATS = {"e4m3": E4M3, "e5m2": E5M2, "fp16": FP16, "bf16": BF16, "fp32": FP32, "e2m3": E2M3, "e3m2": E3M2}
-NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_ROUNDTRIP, DEBUG_CAPTURE = 0x1, 0x2, 0x4, 0x8, 0x10
+NO_PRESCALE, KEEP_SCALE, NORMALIZE, FUSED_ROUNDTRIP, DEBUG_CAPTURE, QUANTIZE_OUTPUT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ERANGE, EBUDGET, EBUSY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 INT32_MIN, INT32_MAX = -(2 ** 31), 2 ** 31 - 1
 

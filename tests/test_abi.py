@@ -62,6 +62,7 @@ def plan_status(n, max_batch, **kw):
     (64, 1, dict(tau_min=float("inf")), mxfft.EINVAL),
     (64, 1, dict(k_min=3, k_max=2), mxfft.EINVAL),
     (64, 1, dict(flags=0x80), mxfft.EINVAL),
+    (64, 1, dict(flags=0x40), mxfft.EINVAL),
     (64, 1, dict(fmt="fp16", flags=mxfft.DEBUG_CAPTURE), mxfft.EINVAL),   # capture: MX formats only
 ])
 def test_plan_argument_checks(n, mb, kw, st):
@@ -156,6 +157,12 @@ def test_plan_bytes_host():
         n, mb = bad.pop("n"), bad.pop("max_batch", 1)
         with pytest.raises(mxfft.MxfftError):
             mxfft.plan_bytes(n, mb, **bad)
+
+
+def test_quantize_output_flag_is_known():
+    """MXFFT_QUANTIZE_OUTPUT is accepted for every format (host check, no GPU)."""
+    for fmt in ("e4m3", "e2m3", "fp16", "fp32"):
+        assert mxfft.plan_bytes(256, 2, fmt=fmt, flags=mxfft.QUANTIZE_OUTPUT) > 0
 
 
 def test_any_positive_tau_min_is_accepted():

@@ -624,3 +624,34 @@ def test_block_64_paths(N, fmt, fast):
     rg, _, st = gpu_run(x, op="roundtrip", fmt=fmt, block=64, flags=mxfft.FUSED_ROUNDTRIP)
     so, ro, _ = orc_run(x, op="roundtrip", fmt=fmt, block=64, flags=O.FUSED_RT)
     assert_bitexact(rg, ro, "%d^2 %s B=64 fused round trip" % (N, fmt))
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("N,fmt,B", [(64, "e4m3", 32), (256, "e5m2", 16), (512, "e4m3", 64), (512, "e2m3", 8),
+                                     (1024, "e3m2", 32), (128, "e5m2", 128)])
+def test_quantized_output(N, fmt, B, op):
+    """MXFFT_QUANTIZE_OUTPUT: the output MX-encoded in blocks of B/2 rows of
+    each column after the last pass, on the single launch (64^2, 128^2 with
+    B = 128), the register-resident passes (256^2 .. 1024^2, fused
+    statistics and blocks of 64 included) and the line kernels (MXFP6 B = 8):
+    bit for bit against the oracle's quantised output."""
+    x = synth.kspace_batch(N, 3, 1, 2)
+    yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B, flags=mxfft.QUANTIZE_OUTPUT)
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B, flags=O.QUANTIZE_OUT)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 %s %s B=%d quantised output" % (N, op, fmt, B))
+
+
+def test_quantized_output_flag_elsewhere():
+    """No effect on the 16-bit forms (their output is rounded to the format
+    anyway); RSS refuses an MX plan with the flag."""
+    x = synth.kspace_batch(128, 3, 1, 2)
+    a, _, _ = gpu_run(x, fmt="fp16")
+    b, _, _ = gpu_run(x, fmt="fp16", flags=mxfft.QUANTIZE_OUTPUT)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    with mxfft.Plan(128, 2, fmt="e4m3", block=32, flags=mxfft.QUANTIZE_OUTPUT) as pl:
+        with pytest.raises(mxfft.MxfftError) as e:
+            pl.rss(torch.from_numpy(x).cuda(), 2)
+        assert e.value.status == mxfft.EUNSUPPORTED
