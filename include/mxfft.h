@@ -97,8 +97,9 @@ typedef struct {
     uint32_t struct_size;  /* sizeof(mxfft_params); checked for ABI versioning */
     int32_t format;        /* mxfft_format */
     int32_t block;         /* B: real scalars per MX block, a power of two with
-                              2 <= B <= n and B <= 128 (B/2 complex values per
-                              block; Sec. 2.2 and Sec. 4.2).  Ignored for FP32. */
+                              2 <= B <= n (B/2 complex values per block; Sec.
+                              2.2 and Sec. 4.2); blocks above 128 run on the
+                              line kernels.  Ignored for FP16, BF16, FP32. */
     int32_t k_min, k_max;  /* clip bounds of the prescale exponent (Alg. 1);
                               INT32_MIN / INT32_MAX mean no bound */
     uint32_t flags;        /* MXFFT_* flags above */

@@ -201,7 +201,6 @@ mxfft_status check_params(const mxfft_params* p, int n)
     case MXFFT_E2M3:
     case MXFFT_E3M2:
         if (!is_pow2(p->block) || p->block < 2 || p->block > n) return MXFFT_EINVAL;
-        if (p->block > 128) return MXFFT_EUNSUPPORTED;
         break;
     case MXFFT_FP32:
     case MXFFT_FP16:

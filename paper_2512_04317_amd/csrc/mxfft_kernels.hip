@@ -440,6 +440,33 @@ __device__ __forceinline__ void mx_encode_value(float2 v, int E, float& qx, floa
     qy = q.y;
 }
 
+// Alg. 2's product of one butterfly in mantissa space: v encoded with its
+// block's exponent Ev (clamped first: the scaled conversions do not
+// saturate), its element values times the twiddle's (products of 8-bit and
+// 6-bit elements are exact in FP32).
+template <int F>
+__device__ __forceinline__ float2 mx_mant_product(float2 w, float2 v, int Ev)
+{
+    const mxd::Blk bv = mxd::blk<F>(Ev);
+    const float2 vc = mxd::clamp2(mxd::mulp<F>(v, bv.pre), mxd::mulp1<F>(mxd::lim_of<F>(Ev), bv.pre));
+    const float2 y = mxd::dec2<F, false>(mxd::enc2<F, false>(0u, vc.x, vc.y, bv.s), mxd::unit_scale<F>());
+    return make_float2(w.x * y.x - w.y * y.y, w.x * y.y + w.y * y.x);
+}
+
+// The renormalised product block's value: the mantissa-space product q
+// encoded with 2^kr (no clamp needed) and decoded with its scale 2^Eo, or (a
+// scale outside the E8M0 range) decoded and then ldexp.
+template <int F>
+__device__ __forceinline__ float2 mx_product_value(float2 q, int kr, int Eo)
+{
+    constexpr int OFF = mxd::Hw<F>::OFF;
+    const uint32_t cp = mxd::enc2<F, false>(0u, q.x, q.y, mxd::e8(kr + OFF));
+    if ((OFF == 0) ? (Eo >= -127) : (Eo + OFF >= -127 && Eo + OFF <= 127))
+        return mxd::dec2<F, false>(cp, mxd::e8(Eo + OFF));
+    const float2 d = mxd::dec2<F, false>(cp, mxd::unit_scale<F>());
+    return make_float2(ldexpf(d.x, Eo), ldexpf(d.y, Eo));
+}
+
 // tr (MX, nullable): receives the block's (E_v, k_r, E_out) of Alg. 2.
 template <int MODE>
 __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float2 u, float2 v,
@@ -469,14 +496,9 @@ __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float
         // they do not saturate)
         const uint32_t av = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
         const int Ev = mxd::block_exp<F>(av);
-        const mxd::Blk bv = mxd::blk<F>(Ev);
-        const float2 vc = mxd::clamp2(mxd::mulp<F>(v, bv.pre), mxd::mulp1<F>(mxd::lim_of<F>(Ev), bv.pre));
-        const float2 y = mxd::dec2<F, false>(mxd::enc2<F, false>(0u, vc.x, vc.y, bv.s), mxd::unit_scale<F>());
-        // mantissa-space product: products of 8-bit elements are exact in FP32
-        const float qr = w.x * y.x - w.y * y.y;
-        const float qi = w.x * y.y + w.y * y.x;
+        const float2 q = mx_mant_product<F>(w, v, Ev);
         // renormalise the product block when it exceeds the element range
-        const uint32_t ap = mxd::group_max(max(mxd::abs_key(qr), mxd::abs_key(qi)), a.cb);
+        const uint32_t ap = mxd::group_max(max(mxd::abs_key(q.x), mxd::abs_key(q.y)), a.cb);
         const int kr = mxd::renorm_exp<F>(ap);
         const int Eo = Ew + Ev + kr;
         if (tr) {
@@ -484,28 +506,90 @@ __device__ __forceinline__ void butterfly(const LineArgs& a, int s, int j, float
             tr[1] = kr;
             tr[2] = Eo;
         }
-        // the renormalised product needs no clamp; decoded with its scale
-        // 2^Eo, or (a scale outside the E8M0 range) decoded and then ldexp
-        constexpr int OFF = mxd::Hw<F>::OFF;
-        const uint32_t cp = mxd::enc2<F, false>(0u, qr, qi, mxd::e8(kr + OFF));
-        if ((OFF == 0) ? (Eo >= -127) : (Eo + OFF >= -127 && Eo + OFF <= 127)) {
-            const float2 p = mxd::dec2<F, false>(cp, mxd::e8(Eo + OFF));
-            pr = p.x;
-            pi = p.y;
-        } else {
-            const float2 q = mxd::dec2<F, false>(cp, mxd::unit_scale<F>());
-            pr = ldexpf(q.x, Eo);
-            pi = ldexpf(q.y, Eo);
-        }
+        const float2 p = mx_product_value<F>(q, kr, Eo);
+        pr = p.x;
+        pi = p.y;
     }
     y0 = make_float2(u.x + pr, u.y + pi);
     y1 = make_float2(u.x - pr, u.y - pi);
+}
+
+// Blocks of more than 64 butterflies (B > 128): a block spans several waves
+// (or several steps of a thread's loop), so its maxima go through LDS.  At
+// most R N / 128 <= 64 blocks per work-group (R N <= 8192).
+constexpr int kBigBlocks = 64;
+
+// The stages of a pass with blocks of more than 64 butterflies: per stage,
+// (1) the v maxima of every block by LDS atomics, (2) each butterfly's
+// mantissa-space product, stored over its v, and the product maxima, (3) the
+// renormalised products and u +/- p.  The same arithmetic as butterfly();
+// every barrier is outside the per-thread loops.
+template <int MODE>
+__device__ void big_block_stages(const LineArgs& a, float2* lds, uint32_t (*s_bm)[kBigBlocks], int slice, int line0,
+                                 int R)
+{
+    constexpr int F = MODE;
+    const int N = a.n, logn = a.logn, tid = threadIdx.x, half = N >> 1, nbf = (R * N) >> 1;
+    const int nblk = nbf >> a.logcb;
+    for (int s = 1; s <= logn; s++) {
+        const int h = 1 << (s - 1);
+        auto where = [&](int b, int& iu, int& iv, int& j, int& t, int& r) {
+            r = b >> (logn - 1);
+            t = b & (half - 1);
+            const int g = t >> (s - 1);
+            j = t & (h - 1);
+            iu = r * N + (g << s) + j;
+            iv = iu + h;
+        };
+        for (int i = tid; i < nblk; i += blockDim.x) {
+            s_bm[0][i] = 0u;
+            s_bm[1][i] = 0u;
+        }
+        __syncthreads();
+        for (int b = tid; b < nbf; b += blockDim.x) {
+            int iu, iv, j, t, r;
+            where(b, iu, iv, j, t, r);
+            const float2 v = lds[iv];
+            atomicMax(&s_bm[0][b >> a.logcb], max(mxd::abs_key(v.x), mxd::abs_key(v.y)));
+        }
+        __syncthreads();
+        for (int b = tid; b < nbf; b += blockDim.x) {
+            int iu, iv, j, t, r;
+            where(b, iu, iv, j, t, r);
+            float2 w = a.tw[h - 1 + j];
+            if (a.inverse) w.y = -w.y;
+            const float2 q = mx_mant_product<F>(w, lds[iv], mxd::block_exp<F>(s_bm[0][b >> a.logcb]));
+            lds[iv] = q;
+            atomicMax(&s_bm[1][b >> a.logcb], max(mxd::abs_key(q.x), mxd::abs_key(q.y)));
+        }
+        __syncthreads();
+        for (int b = tid; b < nbf; b += blockDim.x) {
+            int iu, iv, j, t, r;
+            where(b, iu, iv, j, t, r);
+            const int Ew = a.tw_exp[a.tw_exp_off[s] + (a.cb <= h ? (j >> a.logcb) : 0)];
+            const int Ev = mxd::block_exp<F>(s_bm[0][b >> a.logcb]);
+            const int kr = mxd::renorm_exp<F>(s_bm[1][b >> a.logcb]);
+            const int Eo = Ew + Ev + kr;
+            if (a.cap_trace && a.axis == 0 && line0 + r == 0 && (t & (a.cb - 1)) == 0) {
+                int32_t* tr = a.cap_trace + ((size_t)slice * logn + (s - 1)) * 3 * (half >> a.logcb) + 3 * (t >> a.logcb);
+                tr[0] = Ev;
+                tr[1] = kr;
+                tr[2] = Eo;
+            }
+            const float2 p = mx_product_value<F>(lds[iv], kr, Eo);
+            const float2 u = lds[iu];
+            lds[iu] = make_float2(u.x + p.x, u.y + p.y);
+            lds[iv] = make_float2(u.x - p.x, u.y - p.y);
+        }
+        __syncthreads();
+    }
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_lines(LineArgs a)
 {
     extern __shared__ float2 lds[];
+    __shared__ uint32_t s_bm[2][kBigBlocks];   // block maxima of v and of the products (B > 128)
     const int N = a.n, logn = a.logn, R = a.lines, tid = threadIdx.x;
     const int slice = blockIdx.y;
     const size_t sbase = mxd::slice_base(a.slice_off, slice, (size_t)N * N);       // slice in src
@@ -548,9 +632,20 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     } else if constexpr (MODE != MODE_FP32) {
         if (a.encode) {
             // pass input: blocks of cb consecutive values along the line
+            const bool big = a.cb > 64;
+            if (big) {
+                for (int i = tid; i < (total >> a.logcb); i += blockDim.x) s_bm[0][i] = 0u;
+                __syncthreads();
+                for (int idx = tid; idx < total; idx += blockDim.x) {
+                    const float2 v = lds[idx];
+                    atomicMax(&s_bm[0][idx >> a.logcb], max(mxd::abs_key(v.x), mxd::abs_key(v.y)));
+                }
+                __syncthreads();
+            }
             for (int idx = tid; idx < total; idx += blockDim.x) {
                 float2 v = lds[idx];
-                const uint32_t am = mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
+                const uint32_t am = big ? s_bm[0][idx >> a.logcb]
+                                        : mxd::group_max(max(mxd::abs_key(v.x), mxd::abs_key(v.y)), a.cb);
                 const int E = mxd::block_exp<MODE>(am);
                 float qx, qy;
                 mx_encode_value<MODE>(v, E, qx, qy);
@@ -583,23 +678,30 @@ __global__ __launch_bounds__(256) void k_lines(LineArgs a)
     __syncthreads();
 
     const int half = N >> 1, nbf = total >> 1;
-    for (int s = 1; s <= logn; s++) {
-        const int h = 1 << (s - 1);
-        for (int b = tid; b < nbf; b += blockDim.x) {
-            const int r = b >> (logn - 1);
-            const int t = b & (half - 1);
-            const int g = t >> (s - 1), j = t & (h - 1);
-            const int iu = r * N + (g << s) + j, iv = iu + h;
-            float2 y0, y1;
-            // debug capture: the block exponents of line 0 of the row pass
-            int32_t* tr = nullptr;
-            if (a.cap_trace && a.axis == 0 && line0 + r == 0 && (t & (a.cb - 1)) == 0)
-                tr = a.cap_trace + ((size_t)slice * logn + (s - 1)) * 3 * (half >> a.logcb) + 3 * (t >> a.logcb);
-            butterfly<MODE>(a, s, j, lds[iu], lds[iv], y0, y1, tr);
-            lds[iu] = y0;
-            lds[iv] = y1;
+    bool big = false;
+    if constexpr (MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16) big = a.cb > 64;
+    if (big) {
+        if constexpr (MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16)
+            big_block_stages<MODE>(a, lds, s_bm, slice, line0, R);
+    } else {
+        for (int s = 1; s <= logn; s++) {
+            const int h = 1 << (s - 1);
+            for (int b = tid; b < nbf; b += blockDim.x) {
+                const int r = b >> (logn - 1);
+                const int t = b & (half - 1);
+                const int g = t >> (s - 1), j = t & (h - 1);
+                const int iu = r * N + (g << s) + j, iv = iu + h;
+                float2 y0, y1;
+                // debug capture: the block exponents of line 0 of the row pass
+                int32_t* tr = nullptr;
+                if (a.cap_trace && a.axis == 0 && line0 + r == 0 && (t & (a.cb - 1)) == 0)
+                    tr = a.cap_trace + ((size_t)slice * logn + (s - 1)) * 3 * (half >> a.logcb) + 3 * (t >> a.logcb);
+                butterfly<MODE>(a, s, j, lds[iu], lds[iv], y0, y1, tr);
+                lds[iu] = y0;
+                lds[iv] = y1;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     for (int idx = tid; idx < total; idx += blockDim.x) {

@@ -50,7 +50,7 @@ def plan_status(n, max_batch, **kw):
     (64, 1, dict(block=48), mxfft.EINVAL),
     (64, 1, dict(block=1), mxfft.EINVAL),
     (16, 1, dict(block=32), mxfft.EINVAL),           # B > n
-    (512, 1, dict(block=256), mxfft.EUNSUPPORTED),   # B > 128 not built
+    (512, 1, dict(block=1024), mxfft.EINVAL),        # B > n
     (64, 1, dict(fmt="fp16", tau=-1.0), mxfft.EINVAL),
     (64, 1, dict(fmt=9), mxfft.EINVAL),
     (64, 1, dict(fmt="e2m3", block=48), mxfft.EINVAL),   # MXFP6 blocks follow the MX rules
@@ -157,6 +157,12 @@ def test_plan_bytes_host():
         n, mb = bad.pop("n"), bad.pop("max_batch", 1)
         with pytest.raises(mxfft.MxfftError):
             mxfft.plan_bytes(n, mb, **bad)
+
+
+def test_blocks_up_to_n_are_accepted():
+    """Any power-of-two B from 2 to n (host check, no GPU)."""
+    for n, b in ((256, 256), (512, 512), (1024, 1024), (4096, 4096), (2048, 256)):
+        assert mxfft.plan_bytes(n, 1, block=b) > 0
 
 
 def test_quantize_output_flag_is_known():

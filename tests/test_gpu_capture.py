@@ -41,6 +41,7 @@ def oracle_column_input(x, fmt, B):
     (128, "e4m3", 32), (256, "e5m2", 16), (256, "e3m2", 32),                # register-resident, literal statistics
     (512, "e4m3", 32), (512, "e2m3", 16), (1024, "e5m2", 8),                # fused statistics
     (256, "e5m2", 64), (512, "e4m3", 64),                                   # blocks of 64: 32-line row tiles
+    (256, "e4m3", 256),                                                     # blocks above 128: line kernels
 ])
 def test_column_pass_input_matches_oracle_encode(N, fmt, B):
     batch = 3
@@ -64,7 +65,8 @@ def test_column_pass_input_matches_oracle_encode(N, fmt, B):
 
 
 @pytest.mark.parametrize("N,fmt,B,single", [(8, "e4m3", 4, True), (64, "e5m2", 16, True), (64, "e4m3", 32, False),
-                                            (128, "e2m3", 16, True), (256, "e3m2", 8, False)])
+                                            (128, "e2m3", 16, True), (256, "e3m2", 8, False),
+                                            (256, "e4m3", 256, False)])
 def test_stage_exponents_match_oracle_trace(N, fmt, B, single):
     """Alg. 2's block exponents at every stage (E_v, k_r, E_out) of row 0's
     row pass, recorded by the single-launch kernel and the line kernels, bit

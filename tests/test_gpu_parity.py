@@ -655,3 +655,34 @@ def test_quantized_output_flag_elsewhere():
         with pytest.raises(mxfft.MxfftError) as e:
             pl.rss(torch.from_numpy(x).cuda(), 2)
         assert e.value.status == mxfft.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("op", ["forward", "inverse", "roundtrip"])
+@pytest.mark.parametrize("N,fmt,B,lines", [(256, "e4m3", 256, 0), (256, "e5m2", 256, 1), (512, "e5m2", 512, 0),
+                                           (512, "e2m3", 256, 2), (1024, "e4m3", 1024, 0), (1024, "e3m2", 512, 4)])
+def test_blocks_above_128(N, fmt, B, lines, op):
+    """MX blocks of more than 64 butterflies (B = 256 .. n) on the line
+    kernels, whose block maxima then go through LDS (a block spans several
+    waves, or several steps of a thread's loop), with the default and with
+    small line counts per work-group: bit for bit against the oracle."""
+    x = synth.kspace_batch(N, 3, 1, 2)
+    print("big-block case: N=%d %s B=%d lines=%d %s" % (N, fmt, B, lines, op), flush=True)
+    with mxfft.Plan(N, 2, fmt=fmt, block=B) as pl:
+        assert not pl.tuning()["fast"]
+        if lines:
+            pl.set_tuning(lines)
+        xd = torch.from_numpy(x).cuda()
+        if op == "forward":
+            y, k = pl.forward(xd)
+        elif op == "inverse":
+            y, k = pl.inverse(xd), None
+        else:
+            y, k = pl.roundtrip(xd)
+        st = pl.last_status()
+        torch.cuda.synchronize()
+        yg, kg = y.cpu().numpy(), None if k is None else k.cpu().numpy()
+    so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
+    assert st == mxfft.OK and so == O.OK
+    if kg is not None:
+        np.testing.assert_array_equal(kg, ko)
+    assert_bitexact(yg, yo, "%d^2 %s %s B=%d lines=%d" % (N, op, fmt, B, lines))
