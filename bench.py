@@ -114,8 +114,9 @@ def uneven_batch(args, torch, mxfft, synth):
     branches side by side.  Also timed: each size's branch alone (the same
     slices, in a batch of that size only) and the same slices grouped by size
     in the pool, to show what the concurrent branches gain and what the
-    per-reconstruction layout costs.  The data repeats 8 distinct synthetic
-    coil slices per size (the time does not depend on the values)."""
+    per-reconstruction layout costs.  The data: 16 synthetic phantom coil
+    slices per size, each use times its own random complex factor (uniform
+    phase, amplitude 2^U(-3, 3)), so every slice of the list is distinct."""
     recon = uneven_workload()
     groups, off = [], 0
     for n, c in recon:
@@ -123,10 +124,14 @@ def uneven_batch(args, torch, mxfft, synth):
         off += c * n * n
     b = mxfft.Batch(groups, fmt=args.fmt, block=args.block)
     pool = torch.empty(b.pool_elems, dtype=torch.complex64, device="cuda")
-    distinct = {n: torch.from_numpy(synth.kspace_batch(n, 4, 1, 8)).cuda() for n in (128, 256, 512, 1024)}
+    D = 16
+    distinct = {n: torch.from_numpy(synth.kspace_batch(n, 4, 1, D)).cuda() for n in (128, 256, 512, 1024)}
+    rng = np.random.default_rng([20251205, 4])
     for i, (n, c, o) in enumerate(b.groups):
-        src = distinct[n].repeat((c + 7) // 8 + 1, 1, 1)
-        pool[o:o + c * n * n].view(c, n, n).copy_(src[i % 8:i % 8 + c])
+        idx = torch.tensor([(i + j) % D for j in range(c)], device="cuda")
+        f = np.exp(1j * rng.uniform(0, 2 * np.pi, c)) * 2.0 ** rng.uniform(-3, 3, c)
+        fac = torch.from_numpy(f.astype(np.complex64)).cuda().view(c, 1, 1)
+        pool[o:o + c * n * n].view(c, n, n).copy_(distinct[n].index_select(0, idx) * fac)
     out = torch.empty_like(pool)
     k = torch.empty(b.slices, dtype=torch.int32, device="cuda")
     wall, per = timed_steps(lambda: b.forward(pool, out, k), args.steps, args.warmup, torch)
@@ -151,8 +156,13 @@ def uneven_batch(args, torch, mxfft, synth):
         off += c * n * n
     with mxfft.Batch(grouped, fmt=args.fmt, block=args.block) as bg:
         pg = torch.empty(bg.pool_elems, dtype=torch.complex64, device="cuda")
-        for n, c, o in bg.groups:
-            pg[o:o + c * n * n].view(c, n, n).copy_(distinct[n].repeat((c + 7) // 8, 1, 1)[:c])
+        for n, c, o in bg.groups:             # the same slices, in size order
+            dst = pg[o:o + c * n * n].view(c, n, n)
+            at = 0
+            for nn, cc, oo in groups:
+                if nn == n:
+                    dst[at:at + cc].copy_(pool[oo:oo + cc * n * n].view(cc, n, n))
+                    at += cc
         og = torch.empty_like(pg)
         kg = torch.empty(bg.slices, dtype=torch.int32, device="cuda")
         w_g, _ = timed_steps(lambda: bg.forward(pg, og, kg), args.steps, args.warmup, torch)
@@ -170,7 +180,8 @@ def uneven_batch(args, torch, mxfft, synth):
             "concurrency_gain": round(sum_alone / ms, 3),
             "grouped_by_size_ms": round(1e3 * w_g / args.steps, 4),
             "format": args.fmt, "block": args.block, "direction": "forward",
-            "data": "synthetic: 8 distinct coil slices per size, repeated"}
+            "data": "synthetic: 16 phantom coil slices per size, each use with its own random complex factor "
+                    "(every slice distinct)"}
 
 
 def nrmse_psnr(y, ref):
