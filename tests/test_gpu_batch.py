@@ -83,6 +83,43 @@ def test_uneven_batch_matches_single_plans(fmt, block):
     b.close()
 
 
+@pytest.mark.parametrize("fmt,block,flags", [("e4m3", 64, 0), ("e5m2", 64, mxfft.QUANTIZE_OUTPUT),
+                                             ("e4m3", 256, 0)])
+def test_uneven_batch_large_blocks(fmt, block, flags):
+    """Work lists with MXFP8 blocks of 64 (single launch at 128^2, 32-line row
+    tiles at 256^2 .. 1024^2, fused statistics from 256^2), of 256 (line
+    kernels with LDS block maxima; sizes from 256^2) and with the quantised output: every
+    group bit for bit as a single-plan call, forward and round trip; one
+    group against the oracle."""
+    sizes = [(512, 2), (128, 3), (1024, 1), (256, 4)] if block <= 128 else [(512, 2), (256, 3), (1024, 1)]   # B <= n
+    groups = layout(sizes)
+    print("uneven batch %s B=%d flags=%d" % (fmt, block, flags), flush=True)
+    b = mxfft.Batch(groups, fmt=fmt, block=block, flags=flags)
+    xs = [synth.kspace_batch(n, 3, 1, c) for n, c, _ in groups]
+    pool = torch.from_numpy(pool_of(b, xs)).cuda()
+    for op in (mxfft.FORWARD, mxfft.ROUNDTRIP):
+        out, k = b.execute(op, pool)
+        assert b.last_status() == mxfft.OK
+        yb = b.views(out.cpu())
+        kb = k.cpu().numpy()
+        kbase = 0
+        for gi, ((n, c, _), x) in enumerate(zip(groups, xs)):
+            with mxfft.Plan(n, c, fmt=fmt, block=block, flags=flags) as pl:
+                xd = torch.from_numpy(x).cuda()
+                y, ks = pl.forward(xd) if op == mxfft.FORWARD else pl.roundtrip(xd)
+                torch.cuda.synchronize()
+                assert np.array_equal(bits(yb[gi].numpy()), bits(y.cpu().numpy())), "group %d op %d" % (gi, op)
+                assert np.array_equal(kb[kbase:kbase + c], ks.cpu().numpy())
+            kbase += c
+        fo = O.E4M3 if fmt == "e4m3" else O.E5M2
+        oflags = O.QUANTIZE_OUT if flags else 0
+        st, yo, ko = O.transform(xs[1], op=O.FORWARD if op == mxfft.FORWARD else O.ROUNDTRIP, fmt=fo, B=block,
+                                 flags=oflags, nthreads=NTHREADS)
+        assert st == O.OK
+        assert np.array_equal(bits(yb[1].numpy()), bits(yo)), "group 1 vs oracle"
+    b.close()
+
+
 def test_uneven_batch_against_oracle():
     groups = [(64, 3), (256, 2), (512, 1)]
     b = mxfft.Batch(groups, fmt="e4m3", block=32)

@@ -253,3 +253,28 @@ def test_serve_coalesces_queued_requests():
     srv.close()
     y, _ = alone(x_ref[0], op, **params)
     assert np.array_equal(bits(out.cpu().numpy()), bits(y))
+
+
+def test_serve_quantized_output_requests_share_launches():
+    """Requests with the quantised output (MX) queued while held share a
+    launch with each other but not with plain requests of the same size:
+    each result bit for bit as the oracle's."""
+    srv = mxfft.Server(4 * GiB, slots=1)
+    xs = [torch.from_numpy(synth.random_complex((c, 256, 256), seed=300 + c, dist="lognormal")).cuda()
+          for c in (2, 3, 1, 2)]
+    flags = [mxfft.QUANTIZE_OUTPUT, 0, mxfft.QUANTIZE_OUTPUT, 0]
+    outs = [torch.empty_like(x) for x in xs]
+    srv.hold(True)
+    tickets = [srv.submit(x, o, op=mxfft.FORWARD, fmt="e4m3", block=32, flags=f) for x, o, f in zip(xs, outs, flags)]
+    srv.hold(False)
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    assert st["coalesced_launches"] == 2 and st["coalesced_requests"] == 4, st
+    for x, o, f, r in zip(xs, outs, flags, res):
+        assert r["status"] == mxfft.OK
+        mode, fo = ORC_FMT["e4m3"]
+        s2, yo, _ = O.transform(x.cpu().numpy(), mode=mode, fmt=fo, B=32, flags=O.QUANTIZE_OUT if f else 0,
+                                nthreads=NTHREADS)
+        assert s2 == O.OK
+        assert np.array_equal(bits(o.cpu().numpy()), bits(yo))
+    srv.close()

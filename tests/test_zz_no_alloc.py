@@ -21,8 +21,11 @@ CASES = [
     (512, 5, 2, dict(fmt="fp16")),                          # 16-bit intermediate
     (512, 5, 2, dict(fmt="bf16")),
     (512, 4, 2, dict(fmt="fp32", flags=mxfft.NO_PRESCALE)),  # FP32 form, no statistics
-    (64, 16, 7, dict(fmt="e4m3", block=32)),                # generic line kernels
-    (256, 6, 3, dict(fmt="e5m2", block=64)),                # generic line kernels, B = 64
+    (64, 16, 7, dict(fmt="e4m3", block=32)),                # single launch
+    (256, 6, 3, dict(fmt="e5m2", block=64)),                # B = 64: 32-line row tiles
+    (512, 4, 2, dict(fmt="e4m3", block=64)),                # B = 64 with the statistics on the row pass
+    (256, 4, 2, dict(fmt="e4m3", block=256)),               # line kernels, blocks above 128 (LDS maxima)
+    (128, 6, 2, dict(fmt="e5m2", block=16, flags=mxfft.QUANTIZE_OUTPUT)),   # quantised output
 ]
 
 
