@@ -284,8 +284,8 @@ typedef struct {
                         0 = the line kernels with `lines` or the
                         register-resident passes; must be 0 for n > 128 */
     int32_t stats;   /* Alg. 1 with the prescale: 0 = gathered by the row pass
-                        where the plan can (register-resident MX passes at
-                        n = 256, 512 and 1024), 1 = a separate statistics read of
+                        where the plan can (register-resident MX passes,
+                        n = 128 .. 1024), 1 = a separate statistics read of
                         the input before the row pass (the only way elsewhere) */
     int32_t chunks;  /* work-groups per slice of that separate read: 0 = by the
                         batch (enough to fill the GPU), else a power of two

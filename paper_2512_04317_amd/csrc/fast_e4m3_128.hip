@@ -13,7 +13,8 @@ hipError_t launch_fast_e4m3_128(int cb, bool row, bool inverse, int kind, const 
     if (!row && kind == COL_RSS) hipLaunchKernelGGL((mxf128::k_col_rss<0, CC, INV>), grid, block, 0, s, g); \
     else if (!row) hipLaunchKernelGGL((mxf128::k_col<0, CC, INV>), grid, block, 0, s, g);                  \
     else if (kind == ROW_RAW) hipLaunchKernelGGL((mxf128::k_row<0, CC, INV, ROW_RAW>), grid, block, 0, s, g); \
-    else if (kind != ROW_PLAIN) return hipErrorInvalidValue;                                          \
+    else if (kind == ROW_STATS) hipLaunchKernelGGL((mxf128::k_row<0, CC, INV, ROW_STATS>), grid, block, 0, s, g); \
+    else if (kind == ROW_FIX) hipLaunchKernelGGL((mxf128::k_row_fix<0, CC, INV>), grid, block, 0, s, g);         \
     else hipLaunchKernelGGL((mxf128::k_row<0, CC, INV, ROW_PLAIN>), grid, block, 0, s, g);
     switch (cb * 2 + (inverse ? 1 : 0)) {
     case 4: MXF_CASE(1, false) break;

@@ -53,8 +53,8 @@ bool fast_wide(int mode, int n, int cb)
 bool fast_fused_stats(int mode, int n)
 {
     // the statistics histogram lives in the exchange planes of the row pass
-    // (16 copies at 256^2, 32 above; too few fit at 128^2)
-    return is_mx_mode(mode) && (n == 256 || n == 512 || n == 1024);
+    // (4 copies at 128^2, 16 at 256^2, 32 above)
+    return is_mx_mode(mode) && (n == 128 || n == 256 || n == 512 || n == 1024);
 }
 
 int fast_row_tiles(int mode, int n, int cb)

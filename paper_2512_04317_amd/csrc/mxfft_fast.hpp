@@ -884,7 +884,7 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
             // monotone and correctly rounded)
             constexpr int HC = RowLds<F, C, KIND>::HC;
-            static_assert(kStatsBins * HC <= RW * WPL && HC >= 16, "histogram copies fit the planes");
+            static_assert(kStatsBins * HC <= RW * WPL && HC >= 4, "histogram copies fit the planes");
             for (int i = tid; i < kStatsBins * HC / 4; i += RT) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();

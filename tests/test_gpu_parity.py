@@ -281,9 +281,9 @@ def test_n512_all_blocks(op, fmt, B):
 @pytest.mark.parametrize("N", [128, 256, 1024])
 def test_fast_sizes_all_blocks(N, op, fmt, B):
     """128^2, 256^2 and 1024^2 slices take the register-resident kernels of
-    their size for 4 <= B <= 32 and, at 256^2 and 1024^2, B = 64 (256^2 and
-    1024^2 with the statistics on the row pass, 128^2 with the two-kernel
-    statistics), the single launch or the generic kernels otherwise."""
+    their size for 4 <= B <= 32 and, at 256^2 and 1024^2, B = 64 (all with the
+    statistics on the row pass), the single launch or the generic kernels
+    otherwise."""
     x = synth.kspace_batch(N, 3, 1, 2)
     yg, kg, st = gpu_run(x, op=op, fmt=fmt, block=B)
     so, yo, ko = orc_run(x, op=op, fmt=fmt, block=B)
@@ -344,10 +344,9 @@ def mixed_512_batch(N=512):
 @pytest.mark.parametrize("op", ["forward", "roundtrip"])
 @pytest.mark.parametrize("N,B", [(128, 32), (256, 32), (1024, 32), (256, 64), (1024, 64)])
 def test_fast_sizes_prescale_paths(N, B, op):
-    """The mixed batch at 128^2 (two-kernel statistics), 256^2 (statistics on
-    the row pass, 16 histogram copies) and 1024^2 (statistics on the row
-    pass, 32 copies), out-of-window slices redone literally, for blocks of 32
-    and of 64 (32-line row tiles)."""
+    """The mixed batch at 128^2, 256^2 and 1024^2 (statistics on the row
+    pass: 4, 16 and 32 histogram copies), out-of-window slices redone
+    literally, for blocks of 32 and of 64 (32-line row tiles)."""
     x = mixed_512_batch(N)
     yg, kg, st = gpu_run(x, op=op, fmt="e4m3", block=B)
     so, yo, ko = orc_run(x, op=op, fmt="e4m3", block=B)
