@@ -879,29 +879,29 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
         };
         if constexpr (ST) {
             // Alg. 1 statistics of the unscaled input: |x|^2 in FP64 (both squares
-            // exact, one rounding), its maximum, a non-finite check (the sum of
-            // the squares is finite iff every part is), and the binade histogram
+            // exact, one rounding), its maximum, and the binade histogram
             // floor(log2 |x|) = floor(floor(log2 |x|^2) / 2) (the square root is
-            // monotone and correctly rounded)
+            // monotone and correctly rounded).  The local histogram's bins are
+            // one above the part's: from the high word of |x|^2 (biased exponent
+            // e), the saturating (hi - 723 * 2^20) / 2^21 is 0 for zero, (e - 723) / 2
+            // = floor(log2 |x|) + 150 for finite nonzero |x| (1 .. 278), and 662 for
+            // Inf/NaN (e = 2047), clamped to the last bin, which so counts the
+            // non-finite elements
             constexpr int HC = RowLds<F, C, KIND>::HC;
             static_assert(kStatsBins * HC <= RW * WPL && HC >= 4, "histogram copies fit the planes");
             for (int i = tid; i < kStatsBins * HC / 4; i += RT) ((uint4*)hist)[i] = make_uint4(0, 0, 0, 0);
             if (blockIdx.x == 0 && tid == 0) *g.fix_count = 0;
             __syncthreads();
-            double m2max = 0.0, m2sum = 0.0;
+            double m2max = 0.0;
             sfor<P>([&](auto I) {
                 const double m2 = (double)v[I].x * (double)v[I].x + (double)v[I].y * (double)v[I].y;
                 m2max = fmax(m2max, m2);
-                m2sum += m2;
-                // biased exponent e of |x|^2 -> bin (e - 725) / 2 = floor(log2 |x|) + 149;
-                // zero (e = 0) and non-finite (e = 2047) land in the last bin
                 const uint32_t hi = (uint32_t)((unsigned long long)__double_as_longlong(m2) >> 32);
-                const uint32_t bin = min(((hi >> 20) - 725u) >> 1, (uint32_t)(kStatsBins - 1));
+                const uint32_t bin = min(__builtin_elementwise_sub_sat(hi, 723u << 20) >> 21, (uint32_t)(kStatsBins - 1));
                 atomicAdd(&hist[bin * HC + (lane & (HC - 1))], 1u);
             });
             m2max = wave_reduce_max(m2max);
-            const int nf = wave_reduce_max((int)!__builtin_isfinite(m2sum));
-            if (lane == 0) { L.m2[wave] = m2max; L.nf[wave] = nf; }
+            if (lane == 0) L.m2[wave] = m2max;
         }
         // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive
         // lanes, or (lines of 4 lanes, blocks of 16) in two loads of every lane;
@@ -929,17 +929,30 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             if (zblk) er.add(0);
             mcb = wave_reduce_max(mcb);
             if (lane == 0) L.mc[wave] = mcb;
-            // the tile's histogram to its part (the planes are needed next):
-            // sum the HC copies of bin i, copy order skewed by i so a wave's
-            // reads fall in different banks
+            // the tile's histogram to its part (the planes are needed next): part
+            // bin i sums the HC copies of local bin i + 1, four at a time, the
+            // quads in the order q ^ (i + 1) so a wave's reads fall in different
+            // banks (one address operation per read); the last local bin gives
+            // the non-finite flag
             __syncthreads();
-            constexpr int HC = RowLds<F, C, KIND>::HC;
+            constexpr int HC = RowLds<F, C, KIND>::HC, NQ = HC / 4;
             StatPart* pt = g.parts + (size_t)slice * (N / RL) + rb;
             for (int i = tid; i < kStatsBins; i += RT) {
+                const int j = i + 1;
                 uint32_t h = 0;
-#pragma unroll 8
-                for (int c = 0; c < HC; c++) h += hist[i * HC + ((c + i) & (HC - 1))];
-                pt->hist[i] = (i == kStatsBins - 1) ? 0u : h;
+                if (j < kStatsBins) {
+                    const uint32_t a0 = (uint32_t)(j * HC * 4) | ((uint32_t)(j & (NQ - 1)) << 4);
+#pragma unroll
+                    for (int q = 0; q < NQ; q++) {
+                        const uint4 u = *(const uint4*)((const char*)hist + (a0 ^ ((uint32_t)q << 4)));
+                        h += u.x + u.y + u.z + u.w;
+                    }
+                }
+                if (j == kStatsBins - 1) {
+                    L.nf[0] = h != 0;
+                    h = 0;
+                }
+                pt->hist[i] = h;
             }
             __syncthreads();
         }
@@ -1105,12 +1118,12 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             if (tid == 0) {
                 double m2 = L.m2[0];
                 uint32_t mcw = L.mc[0];
-                int nf = L.nf[0], elo = L.elo[0], ehi = L.ehi[0];
+                const int nf = L.nf[0];
+                int elo = L.elo[0], ehi = L.ehi[0];
 #pragma unroll
                 for (int w = 1; w < RW; w++) {
                     m2 = fmax(m2, L.m2[w]);
                     mcw = max(mcw, L.mc[w]);
-                    nf |= L.nf[w];
                     elo = min(elo, L.elo[w]);
                     ehi = max(ehi, L.ehi[w]);
                 }
