@@ -127,14 +127,34 @@ __device__ __forceinline__ float amax2(float a, float2 v)
 }
 
 // largest |component| of CNT complex values: chains of v_max3_f32, four per
-// asm statement (the compiler separates asm statements with wait states)
-template <int CNT>
+// asm statement (the compiler separates asm statements with wait states).
+// SEED: the first three parts start the chain, one instruction fewer than
+// from a zero register (which can cost registers where they are scarce)
+template <int CNT, bool SEED = true>
 __device__ __forceinline__ float amax_of(const float2* v)
 {
     float a = 0.f;
-    if constexpr (CNT % 4 == 0) {
+    if constexpr (CNT % 4 == 0 && !SEED) {
 #pragma unroll
         for (int g = 0; g < CNT / 4; g++) {
+            const float2 p = v[4 * g], q = v[4 * g + 1], r = v[4 * g + 2], t = v[4 * g + 3];
+            asm("v_max3_f32 %0, %0, |%1|, |%2|\n\t"
+                "v_max3_f32 %0, %0, |%3|, |%4|\n\t"
+                "v_max3_f32 %0, %0, |%5|, |%6|\n\t"
+                "v_max3_f32 %0, %0, |%7|, |%8|"
+                : "+v"(a)
+                : "v"(p.x), "v"(p.y), "v"(q.x), "v"(q.y), "v"(r.x), "v"(r.y), "v"(t.x), "v"(t.y));
+        }
+    } else if constexpr (CNT % 4 == 0) {
+        // the first three parts seed the chain (no zero register)
+        asm("v_max3_f32 %0, |%1|, |%2|, |%3|" : "=v"(a) : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x));
+        asm("v_max3_f32 %0, %0, |%1|, |%2|\n\t"
+            "v_max3_f32 %0, %0, |%3|, |%4|\n\t"
+            "v_max_f32_e64 %0, %0, |%5|"
+            : "+v"(a)
+            : "v"(v[1].y), "v"(v[2].x), "v"(v[2].y), "v"(v[3].x), "v"(v[3].y));
+#pragma unroll
+        for (int g = 1; g < CNT / 4; g++) {
             const float2 p = v[4 * g], q = v[4 * g + 1], r = v[4 * g + 2], t = v[4 * g + 3];
             asm("v_max3_f32 %0, %0, |%1|, |%2|\n\t"
                 "v_max3_f32 %0, %0, |%3|, |%4|\n\t"
@@ -147,6 +167,31 @@ __device__ __forceinline__ float amax_of(const float2* v)
         sfor<CNT>([&](auto T) { a = amax2(a, v[T]); });
     }
     return a;
+}
+
+// Block exponent E, block scale and saturation bound MAXV * 2^E of a block
+// whose largest magnitude has bits ab (mxd::block_exp, blk, lim_of).  For the
+// 8-bit formats 2^E comes straight from the exponent field: E + 127 =
+// max(field - EMAX, 0), which also gives E = -127 for a subnormal maximum; an
+// all-zero block keeps E = 0.
+struct BlkE {
+    int E;
+    Blk b;
+    float lim;
+};
+template <int F>
+__device__ __forceinline__ BlkE block_of(uint32_t ab)
+{
+    if constexpr (Hw<F>::OFF == 0) {
+        constexpr uint32_t LIMADD = ((uint32_t)mxd::Elem<F>::EMAX << 23) | maxv_frac<F>();
+        const uint32_t sb0 = __builtin_elementwise_sub_sat(ab & 0x7F800000u, (uint32_t)mxd::Elem<F>::EMAX << 23);
+        const uint32_t sb = ab ? sb0 : 0x3F800000u;
+        return BlkE{(int)(sb >> 23) - 127, Blk{__uint_as_float(sb), 1.0f, 1.0f}, __uint_as_float(sb + LIMADD)};
+    } else {
+        const int E = mxd::block_exp<F>(ab);
+        const Blk b = blk<F>(E);
+        return BlkE{E, b, mulp1<F>(lim_of<F>(E), b.pre)};
+    }
 }
 
 // Codes of two complex values (each re, im) in the low and high halves of one
@@ -649,10 +694,11 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
         } else if constexpr (B <= 1) {
             // stages 1 and 2: twiddles 1 and -i with exponent -EMAX; the product
             // is the MX-encoded v itself (renormalisation by exactly 2^EMAX)
-            const int Ev = mxd::block_exp<F>(bmax(amax_of<CB>(V)));
+            const BlkE qv = block_of<F>(bmax(amax_of<CB, !TR>(V)));
+            const int Ev = qv.E;
             if constexpr (TR) er.add(Ev);
-            const Blk bv = blk<F>(Ev);
-            const float s = bv.s, lim = mulp1<F>(lim_of<F>(Ev), bv.pre);
+            const Blk bv = qv.b;
+            const float s = bv.s, lim = qv.lim;
             uint32_t c[CB / 2];
             sfor<CB / 2>([&](auto H) {
                 c[H] = enc4<F>(clamp2(mulp<F>(V[2 * H], bv.pre), lim), clamp2(mulp<F>(V[2 * H + 1], bv.pre), lim), s);
@@ -669,10 +715,11 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
             constexpr int jc0 = Ly::posF(K, base) & (h - 1);
             const int Ew = t.ex[t.off[B + 1] + (((1 << BC) <= h) ? ((jm | jc0) >> BC) : 0)];
             // operand v: EncodeBlockMX, element values as FP32 mantissas
-            const int Ev = mxd::block_exp<F>(bmax(amax_of<CB>(V)));
+            const BlkE qv = block_of<F>(bmax(amax_of<CB, !TR>(V)));
+            const int Ev = qv.E;
             if constexpr (TR) er.add(Ev);
-            const Blk bv = blk<F>(Ev);
-            const float s = bv.s, lim = mulp1<F>(lim_of<F>(Ev), bv.pre);
+            const Blk bv = qv.b;
+            const float s = bv.s, lim = qv.lim;
             float2 Pp[CB];
             uint32_t cv[CB / 2];
             sfor<CB / 2>([&](auto H) {
@@ -688,7 +735,7 @@ __device__ __forceinline__ void stage(float2 (&a)[P], int m, const Tw& t, ERange
                 Pp[T].x = x.x * y.x - xi * y.y;
                 Pp[T].y = x.x * y.y + xi * y.x;
             });
-            const int kr = mxd::renorm_exp<F>(bmax(amax_of<CB>(Pp)));
+            const int kr = mxd::renorm_exp<F>(bmax(amax_of<CB, !TR>(Pp)));
             constexpr int OFF = Hw<F>::OFF;
             const float sp = e8(kr + OFF);
             const int Eo = Ew + Ev + kr;
