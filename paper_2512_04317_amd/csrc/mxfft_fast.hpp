@@ -1314,31 +1314,49 @@ __device__ __forceinline__ void col_lines(const FastArgs& g, int slice, int cb16
         const uint4 q0 = cd[tid], q1 = cd[THREADS + tid], q2 = cd[2 * THREADS + tid], q3 = cd[3 * THREADS + tid];
         // exponents [slice][row block][column]: 16 bytes per row block
         const uint8_t* ex = g.exps + (size_t)slice * NRB * N + cb16 * LINES;
-        for (int i = tid; i < NRB; i += THREADS) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
         // stored exponents of a row pass that ran unscaled are offset by kadd
         const int eadd = g.kadd ? g.kadd[slice] : 0;
+        // MXFP8: the tile's block scales 2^(E + kadd) as FP32 words [row block][16
+        // columns], after the code tile in the planes, so a decode reads its
+        // scale operand directly; MXFP6 keeps the bytes (its scale has two forms)
+        float* s_scf = s_plane + LINES * N / 2;
+        static_assert(LINES * N / 2 + NRB * 16 <= WAVES * WPL, "block scales fit after the code tile");
+        if constexpr (Hw<F>::OFF == 0) {
+            for (int i = tid; i < NRB * 4; i += THREADS) {
+                const uint32_t w = *(const uint32_t*)&ex[(size_t)(i >> 2) * N + 4 * (i & 3)];
+                *(float4*)&s_scf[4 * i] = make_float4(__uint_as_float((uint32_t)((int)(w & 0xffu) + eadd) << 23),
+                                                      __uint_as_float((uint32_t)((int)((w >> 8) & 0xffu) + eadd) << 23),
+                                                      __uint_as_float((uint32_t)((int)((w >> 16) & 0xffu) + eadd) << 23),
+                                                      __uint_as_float((uint32_t)((int)(w >> 24) + eadd) << 23));
+            }
+        } else {
+            for (int i = tid; i < NRB; i += THREADS) *(uint4*)&s_ex[i * 16] = *(const uint4*)&ex[(size_t)i * N];
+        }
         ((uint4*)ctile)[tid] = q0;
         ((uint4*)ctile)[THREADS + tid] = q1;
         ((uint4*)ctile)[2 * THREADS + tid] = q2;
         ((uint4*)ctile)[3 * THREADS + tid] = q3;
         __syncthreads();
-        // exponent bytes of this wave's 4 columns come as one dword per row
-        // block (every lane of the wave reads the same dword: a broadcast;
+        // MXFP6: exponent bytes of this wave's 4 columns come as one dword per
+        // row block (every lane of the wave reads the same dword: a broadcast;
         // byte reads of one dword by many lanes serialise)
         const uint32_t* s_ex4 = (const uint32_t*)s_ex + (cl >> 2);
         const int exsh = 8 * (cl & 3);
         const int cdsh = 16 * (cl & 1);                     // this column's code pair within the word
+        const uint16_t* ctile16 = (const uint16_t*)ctile + (cl & 1);
         sfor<P>([&](auto O) {
             const int n = (rev(O, 5) << LOG_LPL) | rm;    // row of position 32m + O
-            const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
-            const int eb = (int)((s_ex4[(n / CB) * 4] >> exsh) & 0xffu);
             if constexpr (Hw<F>::OFF == 0) {
-                const float s = __uint_as_float((uint32_t)(eb + eadd) << 23);
-                a[O] = dec2<F, false>(wd >> cdsh, s);
+                // this column's code pair (a 16-bit read) and its block's scale
+                // (one word, the same for the lanes of a line)
+                const uint32_t cp = ctile16[2 * (n * 8 + ((cl >> 1) ^ cswz(n)))];
+                a[O] = dec2<F, false>(cp, s_scf[(n / CB) * 16 + cl]);
             } else {
                 // MXFP6: scale operand 2^(E + OFF), or 2^E and a factor 2^OFF
                 // after decoding when E + OFF is above the scale range
                 constexpr int OFF = Hw<F>::OFF;
+                const uint32_t wd = ctile[n * 8 + ((cl >> 1) ^ cswz(n))];
+                const int eb = (int)((s_ex4[(n / CB) * 4] >> exsh) & 0xffu);
                 const int ebits = eb + eadd;
                 const bool hi = ebits > 254 - OFF;
                 const float s = __uint_as_float((uint32_t)(hi ? ebits : ebits + OFF) << 23);
