@@ -263,9 +263,10 @@ __device__ __forceinline__ int mx_requant_pair(float2& v0, float2& v1, float& am
         : "v"(v0.x), "v"(v0.y), "v"(v1.x), "v"(v1.y));
     a = group_max_bits<CB / 2>(a);
     am = __uint_as_float(a);
-    const int E = mxd::block_exp<F>(a);
-    const Blk b = blk<F>(E);
-    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
+    const BlkE q = block_of<F>(a);
+    const int E = q.E;
+    const Blk b = q.b;
+    const float s = b.s, lim = q.lim;
     const uint32_t c = enc4<F>(clamp2(mulp<F>(v0, b.pre), lim), clamp2(mulp<F>(v1, b.pre), lim), s);
     v0 = mulp<F>(dec2<F, false>(c, s), b.post);
     v1 = mulp<F>(dec2<F, true>(c, s), b.post);
@@ -286,9 +287,10 @@ __device__ __forceinline__ int mx_requant_quad(float2& v0, float2& v1, float2& v
         : "v"(v0.x), "v"(v0.y), "v"(v1.x), "v"(v1.y), "v"(v2.x), "v"(v2.y), "v"(v3.x), "v"(v3.y));
     a = group_max_bits<G>(a);
     am = __uint_as_float(a);
-    const int E = mxd::block_exp<F>(a);
-    const Blk b = blk<F>(E);
-    const float s = b.s, lim = mulp1<F>(lim_of<F>(E), b.pre);
+    const BlkE q = block_of<F>(a);
+    const int E = q.E;
+    const Blk b = q.b;
+    const float s = b.s, lim = q.lim;
     const uint32_t c0 = enc4<F>(clamp2(mulp<F>(v0, b.pre), lim), clamp2(mulp<F>(v1, b.pre), lim), s);
     const uint32_t c1 = enc4<F>(clamp2(mulp<F>(v2, b.pre), lim), clamp2(mulp<F>(v3, b.pre), lim), s);
     v0 = mulp<F>(dec2<F, false>(c0, s), b.post);
