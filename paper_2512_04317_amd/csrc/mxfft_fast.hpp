@@ -899,12 +899,19 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
     if constexpr (!is_mx(F)) {
         load_plain();
     } else {
-        // coalesced loads: lane m of a line holds naturals 2 LPL I + 2 m + e
-        // (e = 0, 1) as v[2 I + e]
+        // IN4: loads of 32 consecutive bytes per lane, lane m of a line holding
+        // naturals 4 LPL I + 4 m + e (e = 0 .. 3) as v[4 I + e] (two 16-byte
+        // loads whose pair covers whole cache lines), so a block's part in a
+        // lane is four values.  Otherwise coalesced 16-byte loads, lane m
+        // holding naturals 2 LPL I + 2 m + e (e = 0, 1) as v[2 I + e].  IN4
+        // takes fewer instructions; the statistics passes at 1024^2 and of
+        // blocks of 32 at 512^2 keep the second form, which the register
+        // allocation fits better there (no spills, four waves per SIMD)
+        constexpr bool IN4 = !(ST && ((LOGN == 10 && C <= 4) || (LOGN == 9 && C == 5)));
         float2 v[P];
         const float4* x4 = (const float4*)x;
         sfor<P / 2>([&](auto I) {
-            const float4 q = x4[LPL * I + m];
+            const float4 q = IN4 ? x4[2 * (LPL * (I / 2) + m) + (I % 2)] : x4[LPL * I + m];
             if constexpr (ST) {
                 v[2 * I] = make_float2(q.x, q.y);
                 v[2 * I + 1] = make_float2(q.z, q.w);
@@ -952,21 +959,24 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             m2max = wave_reduce_max(m2max);
             if (lane == 0) L.m2[wave] = m2max;
         }
-        // MX encode: a block of CB consecutive naturals sits in CB / 2 consecutive
-        // lanes, or (lines of 4 lanes, blocks of 16) in two loads of every lane;
-        // ROW_RAW leaves the input as it is
+        // MX encode: a block of CB consecutive naturals sits in CB / 4
+        // consecutive lanes, four values each (blocks of 2: two blocks per
+        // four values), or without IN4 in CB / 2 consecutive lanes, or (lines of
+        // 4 lanes, blocks of 16) in two loads of every lane; ROW_RAW leaves the
+        // input as it is
         if constexpr (KIND == ROW_RAW) {
-        } else if constexpr (CB / 2 <= LPL) {
+        } else if constexpr ((IN4 && CB == 2) || (!IN4 && CB / 2 <= LPL)) {
             sfor<P / 2>([&](auto I) {
                 float am;
                 const int E = mx_requant_pair<F, CB>(v[2 * I], v[2 * I + 1], am);
                 if constexpr (ST) { (void)E; track(__float_as_uint(am)); }
             });
         } else {
-            static_assert(CB == 4 * LPL, "a block spans two loads of every lane of its line");
+            constexpr int G = IN4 ? CB / 4 : LPL;
+            static_assert(IN4 ? CB / 4 <= LPL : CB == 4 * LPL, "a block spans at most the lanes of its line");
             sfor<P / 4>([&](auto H) {
                 float am;
-                const int E = mx_requant_quad<F, LPL>(v[4 * H], v[4 * H + 1], v[4 * H + 2], v[4 * H + 3], am);
+                const int E = mx_requant_quad<F, G>(v[4 * H], v[4 * H + 1], v[4 * H + 2], v[4 * H + 3], am);
                 if constexpr (ST) { (void)E; track(__float_as_uint(am)); }
             });
         }
@@ -1006,14 +1016,16 @@ __device__ __forceinline__ void row_tile(const FastArgs& g, int slice, int rb, R
             __syncthreads();
         }
         // bit reversal into layout 0 through the LDS plane
-        float* wb = plane + slot(rm << 4);
+        float* wb = plane + slot(rm << (IN4 ? 3 : 4));
         const float* rbp = plane + slot(P * m);
         sfor<2>([&](auto R) {
             wave_sync();
-            // natural 2 LPL I + 2 m + e sits at position e N/2 + rm 16 + rev4(I)
+            // IN4: natural 4 LPL I + 4 m + e sits at position rev2(e) N/4 + rm 8 +
+            // rev3(I); otherwise natural 2 LPL I + 2 m + e at e N/2 + rm 16 + rev4(I)
             sfor<P>([&](auto J) {
-                constexpr int I = J / 2, e = J % 2;
-                wb[slot((e << (LOGN - 1)) | rev(I, 4))] = R ? v[J].y : v[J].x;
+                constexpr int off = IN4 ? ((rev(J % 4, 2) << (LOGN - 2)) | rev(J / 4, 3))
+                                        : (((J % 2) << (LOGN - 1)) | rev(J / 2, 4));
+                wb[slot(off)] = R ? v[J].y : v[J].x;
             });
             wave_sync();
             sfor<P / 2>([&](auto I) {
