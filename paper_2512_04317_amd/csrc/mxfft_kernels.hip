@@ -874,8 +874,21 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
 {
     extern __shared__ float2 buf[];     // n x (n + 1) complex values
     __shared__ Alg1Smem S;
+    // the plan's twiddles (n - 1 values) and MX twiddle block exponents, read
+    // by every stage: staged in LDS once
+    __shared__ float2 s_tw[kSmallMaxN];
+    __shared__ int32_t s_twe[kSmallMaxN];
     const int tid = threadIdx.x, slice = blockIdx.x, N = g.a.n, logn = g.a.logn, nn = N * N, pitch = N + 1;
     const float2* xs = g.a.src + mxd::slice_base(g.a.slice_off, slice, (size_t)nn);
+    constexpr bool MXM = MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16;
+    if (N >= 2) {
+        for (int i = tid; i < N - 1; i += blockDim.x) s_tw[i] = g.a.tw[i];
+        if constexpr (MXM) {
+            // stage s holds (n/2 of the last stage) / min(cb, h) exponents from tw_exp_off[s]
+            const int h = N >> 1, ne = g.a.tw_exp_off[logn] + h / min(g.a.cb, h);
+            for (int i = tid; i < ne; i += blockDim.x) s_twe[i] = g.a.tw_exp[i];
+        }
+    }
     if (g.stats) {
         alg1_init(S);
         __syncthreads();
@@ -932,9 +945,13 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
         }
         __syncthreads();
     }
-    constexpr bool MX = MODE != MODE_FP32 && MODE != MODE_FP16 && MODE != MODE_BF16;
+    constexpr bool MX = MXM;
     LineArgs a = g.a;
     a.inverse = g.op == 1;
+    if (N >= 2) {
+        a.tw = s_tw;
+        if constexpr (MX) a.tw_exp = s_twe;
+    }
     small_pass<MODE>(a, buf, false, MX, nullptr, nullptr, g.op == 0 ? g.a.cap_trace : nullptr, slice);
     small_pass<MODE>(a, buf, true, MX, g.op == 0 ? g.a.cap_mant : nullptr, g.a.cap_exp, nullptr, slice);
     if (g.op == 2) {
