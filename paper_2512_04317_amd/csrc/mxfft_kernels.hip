@@ -101,18 +101,34 @@ __global__ __launch_bounds__(256) void k_stats_part(const float2* __restrict__ x
     } else {
         for (int i = beg + tid; i < end; i += blockDim.x) elem(xs[i].x, xs[i].y);
     }
-    atomicMax(&s_m2, mm);
-    atomicAdd(&s_count, cnt);
-    atomicMax(&s_maxc, mc);
-    atomicOr(&s_nonfin, nf);
+    // reduced over the wave first: one LDS atomic per wave and value instead
+    // of 64 on one address
+    for (int o = 32; o; o >>= 1) {
+        mm = max(mm, (unsigned long long)__shfl_xor((long long)mm, o, 64));
+        cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+        mc = max(mc, (uint32_t)__shfl_xor((int)mc, o, 64));
+        nf |= (uint32_t)__shfl_xor((int)nf, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        atomicMax(&s_m2, mm);
+        atomicAdd(&s_count, cnt);
+        atomicMax(&s_maxc, mc);
+        atomicOr(&s_nonfin, nf);
+    }
     __syncthreads();
 
     StatPart* pt = parts + (size_t)slice * chunks + blockIdx.x;
-    // sum the copies of bin i; thread i starts at copy i % 32 so a wave's
-    // reads fall in 32 different banks
+    // sum the copies of bin i four at a time, the quads in the order q ^ i so
+    // a wave's reads fall in different banks (one address operation per read)
+    constexpr int NQ = kHistCopies / 4;
     for (int i = tid; i < kStatsBins; i += blockDim.x) {
+        const uint32_t a0 = (uint32_t)(i * kHistCopies * 4) | ((uint32_t)(i & (NQ - 1)) << 4);
         uint32_t h = 0;
-        for (int j = 0; j < kHistCopies; j++) h += hist[i * kHistCopies + ((i + j) & (kHistCopies - 1))];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const uint4 u = *(const uint4*)((const char*)hist + (a0 ^ ((uint32_t)q << 4)));
+            h += u.x + u.y + u.z + u.w;
+        }
         pt->hist[i] = h;
     }
     if (tid == 0) {
@@ -352,7 +368,8 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
             if (h) atomicAdd(&S.hist[i], h);
             cnt += h;
         }
-        atomicAdd(&S.count, cnt);
+        for (int o = 32; o; o >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+        if ((tid & 63) == 0) atomicAdd(&S.count, cnt);
     }
     for (int c = tid; c < chunks; c += blockDim.x) {
         atomicMax(&S.m2, pt[c].max_m2);
@@ -916,10 +933,20 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
             }
         }
         if (g.stats) {
-            atomicMax(&S.m2, mm);
-            atomicAdd(&S.count, cnt);
-            atomicMax(&S.maxc, mc);
-            atomicOr(&S.nonfin, nf);
+            // reduced over the wave first: one LDS atomic per wave and value
+            // instead of 64 on one address
+            for (int o = 32; o; o >>= 1) {
+                mm = max(mm, (unsigned long long)__shfl_xor((long long)mm, o, 64));
+                cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+                mc = max(mc, (uint32_t)__shfl_xor((int)mc, o, 64));
+                nf |= (uint32_t)__shfl_xor((int)nf, o, 64);
+            }
+            if ((tid & 63) == 0) {
+                atomicMax(&S.m2, mm);
+                atomicAdd(&S.count, cnt);
+                atomicMax(&S.maxc, mc);
+                atomicOr(&S.nonfin, nf);
+            }
         }
     }
     __syncthreads();
