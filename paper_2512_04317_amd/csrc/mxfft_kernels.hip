@@ -995,11 +995,11 @@ __global__ __launch_bounds__(1024) void k_small(SmallArgs g)
 }
 
 // Threads per work-group of the single-launch kernel (results do not depend
-// on it).  While the batch gives a CU at most one slice, 8 waves per slice
-// (16 where only one slice fits the CU's LDS); with more slices per CU, 16
-// waves shared among the slices a CU holds at once, so that each thread runs
-// several butterflies of a stage and a barrier spans fewer waves.  Never more
-// than one thread per butterfly, never less than one wave.
+// on it).  While the batch gives a CU at most one slice, 16 waves per slice;
+// with more slices per CU, 16 waves shared among the slices a CU holds at
+// once (at most 8 per slice), so that each thread runs several butterflies of
+// a stage and a barrier spans fewer waves.  Never more than one thread per
+// butterfly, never less than one wave.
 int small_block(int n, int batch, int cus, int lds_per_cu)
 {
     const int bf = n * n / 2;
@@ -1007,7 +1007,7 @@ int small_block(int n, int batch, int cus, int lds_per_cu)
     const int fit = std::max(1, (int)(lds_per_cu / lds));
     const int per_cu = (batch + std::max(cus, 1) - 1) / std::max(cus, 1);
     int waves = 16 / std::min(std::min(fit, per_cu), 16);
-    if (fit > 1) waves = std::min(waves, 8);
+    if (fit > 1 && per_cu > 1) waves = std::min(waves, 8);
     waves = std::max(1, std::min(waves, bf / 64));
     return 64 * waves;
 }
