@@ -685,3 +685,33 @@ def test_blocks_above_128(N, fmt, B, lines, op):
     if kg is not None:
         np.testing.assert_array_equal(kg, ko)
     assert_bitexact(yg, yo, "%d^2 %s %s B=%d lines=%d" % (N, op, fmt, B, lines))
+
+
+@pytest.mark.parametrize("N,fmt,B", [(128, "e4m3", 32), (256, "e5m2", 16), (256, "e4m3", 64), (1024, "e4m3", 32),
+                                     (512, "e2m3", 32)])
+def test_fused_statistics_nonfinite(N, fmt, B):
+    """The row pass that gathers Alg. 1's statistics finds non-finite parts
+    through its histogram (Inf/NaN land in their own bin, zeros in another):
+    a NaN real part, a -Inf imaginary part and a NaN beside zeros each fail
+    their own slice with ENONFINITE and k = INT32_MIN, and the finite slices
+    around them (one of them mostly zeros) keep their k and output, bit for
+    bit against the oracle."""
+    ks = synth.kspace_batch(N, 2, 1, 5)
+    sparse = np.zeros((N, N), np.complex64)
+    sparse[3, 5] = 1.5 - 2.0j
+    sparse[N - 2, N // 3] = 0.25j
+    x = np.stack([ks[0], ks[1], sparse, ks[0], sparse]).astype(np.complex64)
+    x[1, N // 2, 7] = np.complex64(complex(np.nan, 1.0))
+    x[3, 1, N - 1] = np.complex64(complex(2.0, -np.inf))
+    x[4, 0, 0] = np.complex64(complex(np.nan, 0.0))
+    yg, kg, st = gpu_run(x, fmt=fmt, block=B)
+    assert st == mxfft.ENONFINITE
+    bad = [1, 3, 4]
+    assert all(kg[i] == mxfft.INT32_MIN for i in bad)
+    good = [0, 2]
+    so, yo, ko = orc_run(x[good], fmt=fmt, block=B)
+    assert so == O.OK
+    np.testing.assert_array_equal(kg[good], ko)
+    assert_bitexact(np.asarray(yg)[good], yo, "%d^2 %s B=%d finite slices beside non-finite ones" % (N, fmt, B))
+    for i in bad:
+        assert O.prescale(x[i])[0] == O.ENONFINITE
