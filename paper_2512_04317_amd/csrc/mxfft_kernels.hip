@@ -356,17 +356,22 @@ __global__ __launch_bounds__(256) void k_stats_final(const float2* __restrict__ 
     const StatPart* pt = parts + (size_t)slice * chunks;
     alg1_init(S);
     __syncthreads();
-    // histograms of all chunks, read as one coalesced sweep (many loads in
-    // flight per thread) and summed per bin in LDS
+    // histograms of all chunks, read as one coalesced sweep of 16-byte loads
+    // (several in flight per thread) and summed per bin in LDS
     {
-        const int total = chunks * kStatsBins;
+        static_assert(kStatsBins % 4 == 0 && sizeof(StatPart) % 16 == 0, "histograms in 16-byte quads");
+        constexpr int QB = kStatsBins / 4;
+        const int total = chunks * QB;
         uint32_t cnt = 0;
-#pragma unroll 8
+#pragma unroll 4
         for (int w = tid; w < total; w += blockDim.x) {
-            const int c = w / kStatsBins, i = w - c * kStatsBins;
-            const uint32_t h = pt[c].hist[i];
-            if (h) atomicAdd(&S.hist[i], h);
-            cnt += h;
+            const int c = w / QB, q = w - c * QB;
+            const uint4 h = *(const uint4*)&pt[c].hist[4 * q];
+            if (h.x) atomicAdd(&S.hist[4 * q], h.x);
+            if (h.y) atomicAdd(&S.hist[4 * q + 1], h.y);
+            if (h.z) atomicAdd(&S.hist[4 * q + 2], h.z);
+            if (h.w) atomicAdd(&S.hist[4 * q + 3], h.w);
+            cnt += h.x + h.y + h.z + h.w;
         }
         for (int o = 32; o; o >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
         if ((tid & 63) == 0) atomicAdd(&S.count, cnt);
