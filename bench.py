@@ -35,7 +35,7 @@ ALG_BYTES_PER_ELEM = 16.0      # complex64 read once + complex64 written once pe
 # clock, and at the clock the counters measured for the kernel under this
 # load (GRBM_GUI_ACTIVE over its duration, recorded beside the HBM traffic in
 # profiles/traffic_<workload>_<format>.json; 2.1 to 2.36 GHz on different
-# boxes)
+# machines)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic operations per radix-2 butterfly of the MX path: one complex
 # product and two complex sums (10 flops) plus the four quantise/dequantise
@@ -447,7 +447,7 @@ def cpu_baseline(args, x, batch):
     """The CPU oracle (exact MX emulation, one slice per thread) on the first
     cpu_sample slices of the same batch and parameters, timed cpu_runs times;
     the median is reported.  Threads: the host cores this process may use,
-    at most 16 (the GPU machine's CPU share)."""
+    at most 16 (the host cores one GPU is given)."""
     import oracle
     ns = min(args.cpu_sample, batch)
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
